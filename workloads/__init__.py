@@ -1,0 +1,313 @@
+"""Seeded synthetic inputs shared by the tests, the smoke check and the benchmark.
+
+This module holds no arithmetic of the method: it only describes lattices
+(sizes, relaxation time, boundary kinds), draws particle sets by seeded random
+sequential addition (RSA, largest radius first, rejecting overlaps) and returns
+plain numpy arrays.  Both the FP64 CPU oracle and the HIP library consume these
+descriptors through their own code.
+
+The five workloads mirror the configurations used to exercise the
+partially-saturated-cell LBM of Liu & Wu (arXiv 1901.09745):
+
+* ``c1`` D2Q9 tau=0.8 200x100 channel, bounce-back walls in y, body force
+  1e-6 along x, one fixed disk r=10 at (60, 50)  (``c1b``: no disk).
+* ``c2`` D2Q9 tau=0.7 1024^2 periodic, 2000 disks r~U(6,12), gap 0.5, JKR DEM,
+  gravity 1e-6 on the particles.
+* ``c3`` D3Q19 tau=0.6 256^3 periodic, 8000 spheres r~U(4,6), prescribed
+  velocities ~N(0, 1e-3^2).
+* ``c4`` D2Q9 tau=0.8 512x256 channel, equilibrium inlet u=0.02 / outlet,
+  64 fixed disks r=8.
+* ``c5`` D3Q19 tau=0.65 384x192x192, walls on x (vertical), 20000 adhesive
+  spheres r~U(3,5) settling under gravity 1e-6.
+
+Every generator takes ``scale`` (linear factor on the box, particle count
+scaled with the area/volume so the packing fraction is kept) so the same recipe
+yields the small cases that the oracle finishes in seconds.
+"""
+from __future__ import annotations
+
+import dataclasses
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence, Tuple
+
+import numpy as np
+
+# Face boundary kinds, by name (each implementation maps them to its own enum).
+PERIODIC = "periodic"
+BOUNCE_BACK = "bounce_back"
+MOVING_WALL = "moving_wall"
+INLET_EQ = "inlet_eq"
+OUTLET_EQ = "outlet_eq"
+FACE_KINDS = (PERIODIC, BOUNCE_BACK, MOVING_WALL, INLET_EQ, OUTLET_EQ)
+
+
+@dataclass
+class LatticeSpec:
+    """Lattice, fluid and boundary description (lattice units)."""
+
+    q: int                      # 9 (D2Q9) or 19 (D3Q19)
+    nx: int
+    ny: int
+    nz: int = 1
+    tau: float = 0.8
+    force: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    faces: Tuple[str, ...] = (PERIODIC,) * 6       # x-, x+, y-, y+, z-, z+
+    face_u: Tuple[Tuple[float, float, float], ...] = ((0.0, 0.0, 0.0),) * 6
+    rho0: float = 1.0
+    h: float = 1.0              # half-width of the solid-fraction shell
+
+    @property
+    def ncells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    @property
+    def shape(self) -> Tuple[int, int, int]:
+        return (self.nz, self.ny, self.nx)
+
+    def periodic(self, axis: int) -> bool:
+        if axis == 2 and self.q == 9:
+            return True
+        return self.faces[2 * axis] == PERIODIC and self.faces[2 * axis + 1] == PERIODIC
+
+    def replace(self, **kw) -> "LatticeSpec":
+        return dataclasses.replace(self, **kw)
+
+
+@dataclass
+class Particles:
+    """Particle state as FP64 SoA arrays: x, u, omega of shape (n, 3), r (n,)."""
+
+    x: np.ndarray
+    u: np.ndarray
+    omega: np.ndarray
+    r: np.ndarray
+
+    @property
+    def n(self) -> int:
+        return int(self.r.shape[0])
+
+    def copy(self) -> "Particles":
+        return Particles(self.x.copy(), self.u.copy(), self.omega.copy(), self.r.copy())
+
+    @staticmethod
+    def empty() -> "Particles":
+        z = np.zeros((0, 3))
+        return Particles(z.copy(), z.copy(), z.copy(), np.zeros(0))
+
+
+@dataclass
+class DemSpec:
+    """DEM material and time-stepping parameters (lattice units)."""
+
+    rho_p: float = 3.0
+    rho_f: float = 1.0
+    E_p: float = 1e-3
+    poisson: float = 0.3
+    gamma: float = 1e-5
+    eta_n: float = 0.0
+    g: Tuple[float, float, float] = (0.0, 0.0, 0.0)
+    dt: float = 1.0
+    n_sub: int = 1
+    kinematic: bool = False
+    max_contacts: int = 16
+
+
+@dataclass
+class Workload:
+    name: str
+    lattice: LatticeSpec
+    particles: Particles
+    steps: int
+    dem: Optional[DemSpec] = None        # None: particles held fixed
+    description: str = ""
+
+
+# --------------------------------------------------------------------------
+# Random sequential addition
+# --------------------------------------------------------------------------
+
+def _min_image(d: np.ndarray, L: float, periodic: bool) -> np.ndarray:
+    if not periodic:
+        return d
+    return d - L * np.round(d / L)
+
+
+def rsa(rng: np.random.Generator, radii: Sequence[float], box: Tuple[float, ...],
+        periodic: Tuple[bool, ...], gap: float = 0.0, clearance: float = 0.0,
+        xrange: Optional[Tuple[float, float]] = None, max_trials: int = 50_000_000
+        ) -> np.ndarray:
+    """Place disks/spheres of the given radii (in the given order) uniformly at
+    random without overlap: a candidate is accepted when its distance to every
+    placed particle is at least r_i + r_j + gap (nearest image on periodic
+    axes).  On a walled axis the centre keeps ``clearance`` + r from the walls at
+    -1/2 and L-1/2.  ``xrange`` optionally narrows the x placement window.
+    Candidates are drawn in batches, the first acceptable one in a batch wins.
+    Returns positions of shape (n, 3) (z = 0 in 2D).
+    """
+    dim = len(box)
+    radii = np.asarray(radii, dtype=np.float64)
+    n = radii.shape[0]
+    rmax = float(radii.max()) if n else 1.0
+    cell = 2.0 * rmax + gap + 1e-9
+    nb = [max(1, int(np.floor(box[a] / cell))) for a in range(dim)]
+    bsz = [box[a] / nb[a] for a in range(dim)]
+    cap = 4
+    bins = -np.ones(tuple(nb) + (cap,), dtype=np.int64)
+    counts = np.zeros(tuple(nb), dtype=np.int64)
+    pos = np.zeros((n, 3))
+    offs = np.array(np.meshgrid(*[[-1, 0, 1]] * dim, indexing="ij")).reshape(dim, -1).T
+    batch = 4
+    trials = 0
+    for k in range(n):
+        r = radii[k]
+        lo = np.zeros(dim)
+        hi = np.zeros(dim)
+        for a in range(dim):
+            if periodic[a]:
+                lo[a], hi[a] = 0.0, box[a]
+            else:
+                lo[a], hi[a] = -0.5 + r + clearance, box[a] - 0.5 - r - clearance
+        if xrange is not None:
+            lo[0], hi[0] = max(lo[0], xrange[0]), min(hi[0], xrange[1])
+        while True:
+            if trials > max_trials:
+                raise RuntimeError(f"RSA: gave up after {trials} trials at particle {k}")
+            P = rng.uniform(lo, hi, size=(batch, dim))
+            trials += batch
+            b = np.floor(np.mod(P, np.asarray(box)) / np.asarray(bsz)).astype(np.int64)
+            b = np.minimum(b, np.asarray(nb) - 1)
+            nbr = b[:, None, :] + offs[None, :, :]            # (B, 3^dim, dim)
+            for a in range(dim):
+                if periodic[a]:
+                    nbr[..., a] %= nb[a]
+            valid = np.ones(nbr.shape[:2], dtype=bool)
+            for a in range(dim):
+                if not periodic[a]:
+                    valid &= (nbr[..., a] >= 0) & (nbr[..., a] < nb[a])
+                    nbr[..., a] = np.clip(nbr[..., a], 0, nb[a] - 1)
+            ids = bins[tuple(nbr[..., a] for a in range(dim))]  # (B, 3^dim, cap)
+            ids = np.where(valid[..., None], ids, -1).reshape(batch, -1)
+            safe = np.where(ids >= 0, ids, 0)
+            d2 = np.zeros(ids.shape)
+            for a in range(dim):
+                d = _min_image(pos[safe, a] - P[:, a:a + 1], box[a], periodic[a])
+                d2 += d * d
+            need = (radii[safe] + r + gap) ** 2
+            clash = ((d2 < need) & (ids >= 0)).any(axis=1)
+            ok = np.nonzero(~clash)[0]
+            if ok.size:
+                p = P[ok[0]]
+                pos[k, :dim] = p
+                bb = tuple(int(v) for v in np.minimum(
+                    np.floor(np.mod(p, np.asarray(box)) / np.asarray(bsz)).astype(np.int64),
+                    np.asarray(nb) - 1))
+                if counts[bb] >= cap:
+                    cap *= 2
+                    nbins = -np.ones(tuple(nb) + (cap,), dtype=np.int64)
+                    nbins[..., : cap // 2] = bins
+                    bins = nbins
+                bins[bb + (int(counts[bb]),)] = k
+                counts[bb] += 1
+                if ok[0] == 0 and batch > 4:
+                    batch //= 2
+                break
+            batch = min(batch * 4, 16384)
+    return pos
+
+
+def _particles(x: np.ndarray, u: Optional[np.ndarray] = None, r: Optional[np.ndarray] = None
+               ) -> Particles:
+    n = x.shape[0]
+    return Particles(np.ascontiguousarray(x, dtype=np.float64),
+                     np.zeros((n, 3)) if u is None else np.ascontiguousarray(u, dtype=np.float64),
+                     np.zeros((n, 3)),
+                     np.ascontiguousarray(r, dtype=np.float64))
+
+
+def _scaled_count(n: int, scale: float, dim: int) -> int:
+    return max(1, int(round(n * scale ** dim)))
+
+
+# --------------------------------------------------------------------------
+# The five workloads
+# --------------------------------------------------------------------------
+
+def c1(with_disk: bool = True) -> Workload:
+    lat = LatticeSpec(q=9, nx=200, ny=100, tau=0.8, force=(1e-6, 0.0, 0.0),
+                      faces=(PERIODIC, PERIODIC, BOUNCE_BACK, BOUNCE_BACK, PERIODIC, PERIODIC))
+    if with_disk:
+        p = _particles(np.array([[60.0, 50.0, 0.0]]), r=np.array([10.0]))
+    else:
+        p = Particles.empty()
+    return Workload("c1" if with_disk else "c1b", lat, p, steps=2000,
+                    description="D2Q9 tau=0.8 200x100 channel, body force 1e-6, "
+                    + ("one fixed disk r=10 at (60,50)" if with_disk else "no disk"))
+
+
+def c2(scale: float = 1.0, seed: int = 2) -> Workload:
+    L = int(round(1024 * scale))
+    n = _scaled_count(2000, scale, 2)
+    rng = np.random.default_rng(seed)
+    radii = np.sort(rng.uniform(6.0, 12.0, size=n))[::-1]
+    x = rsa(rng, radii, (float(L), float(L)), (True, True), gap=0.5)
+    lat = LatticeSpec(q=9, nx=L, ny=L, tau=0.7)
+    dem = DemSpec(g=(0.0, -1e-6, 0.0))
+    return Workload("c2", lat, _particles(x, r=radii), steps=10_000, dem=dem,
+                    description=f"D2Q9 tau=0.7 {L}^2 periodic, {n} disks r~U(6,12) seed {seed}, "
+                    "gap 0.5, JKR E=1e-3 nu=0.3 gamma=1e-5, gravity 1e-6 on particles")
+
+
+def c3(scale: float = 1.0, seed: int = 3) -> Workload:
+    L = int(round(256 * scale))
+    n = _scaled_count(8000, scale, 3)
+    ss = np.random.SeedSequence(seed)
+    rng_pos, rng_vel = [np.random.default_rng(s) for s in ss.spawn(2)]
+    radii = np.sort(rng_pos.uniform(4.0, 6.0, size=n))[::-1]
+    x = rsa(rng_pos, radii, (float(L),) * 3, (True, True, True))
+    u = rng_vel.normal(0.0, 1e-3, size=(n, 3))
+    lat = LatticeSpec(q=19, nx=L, ny=L, nz=L, tau=0.6)
+    dem = DemSpec(kinematic=True)
+    return Workload("c3", lat, _particles(x, u=u, r=radii), steps=1000, dem=dem,
+                    description=f"D3Q19 tau=0.6 {L}^3 periodic, {n} spheres r~U(4,6) seed {seed}, "
+                    "prescribed velocities N(0,1e-3^2), particles advected kinematically")
+
+
+def c4(scale: float = 1.0, seed: int = 4, u_in: float = 0.02) -> Workload:
+    nx, ny = int(round(512 * scale)), int(round(256 * scale))
+    n = _scaled_count(64, scale, 2)
+    rng = np.random.default_rng(seed)
+    radii = np.full(n, 8.0)
+    x = rsa(rng, radii, (float(nx), float(ny)), (False, False), gap=0.5, clearance=1.0,
+            xrange=(40.0 * scale, nx - 40.0 * scale))
+    lat = LatticeSpec(q=9, nx=nx, ny=ny, tau=0.8,
+                      faces=(INLET_EQ, OUTLET_EQ, BOUNCE_BACK, BOUNCE_BACK, PERIODIC, PERIODIC),
+                      face_u=((u_in, 0.0, 0.0),) + ((0.0, 0.0, 0.0),) * 5)
+    return Workload("c4", lat, _particles(x, r=radii), steps=4000,
+                    description=f"D2Q9 tau=0.8 {nx}x{ny} channel, equilibrium inlet u={u_in}, "
+                    f"outlet rho=1, {n} fixed disks r=8 seed {seed}")
+
+
+def c5(scale: float = 1.0, seed: int = 5) -> Workload:
+    nx, ny, nz = int(round(384 * scale)), int(round(192 * scale)), int(round(192 * scale))
+    n = _scaled_count(20000, scale, 3)
+    rng = np.random.default_rng(seed)
+    radii = np.sort(rng.uniform(3.0, 5.0, size=n))[::-1]
+    x = rsa(rng, radii, (float(nx), float(ny), float(nz)), (False, True, True))
+    lat = LatticeSpec(q=19, nx=nx, ny=ny, nz=nz, tau=0.65,
+                      faces=(BOUNCE_BACK, BOUNCE_BACK, PERIODIC, PERIODIC, PERIODIC, PERIODIC))
+    dem = DemSpec(g=(-1e-6, 0.0, 0.0))
+    return Workload("c5", lat, _particles(x, r=radii), steps=20_000, dem=dem,
+                    description=f"D3Q19 tau=0.65 {nx}x{ny}x{nz}, walls at x=-1/2 and {nx}-1/2, "
+                    f"{n} adhesive spheres r~U(3,5) seed {seed}, gravity 1e-6 along -x")
+
+
+WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
+
+
+def random_state(lat: LatticeSpec, seed: int, amp: float = 1e-2) -> np.ndarray:
+    """A seeded non-equilibrium distribution field f[Q, nz, ny, nx] around
+    w_i * rho0 built from uniform noise: f_i = rho0 / Q * (1 + amp * xi) with
+    xi ~ U(-1, 1) -- a generic positive state for one-step parity checks."""
+    rng = np.random.default_rng(seed)
+    f = lat.rho0 / lat.q * (1.0 + amp * rng.uniform(-1.0, 1.0, size=(lat.q,) + lat.shape))
+    return np.ascontiguousarray(f)
