@@ -1,0 +1,218 @@
+/*
+ * psclbm.h -- C ABI of the MI355X (gfx950) partially-saturated-cell lattice
+ * Boltzmann library.
+ *
+ * The library implements the per-time-step hot path of the hybrid IBM-LBM-DEM
+ * method of Liu & Wu, "A hybrid LBM-DEM framework with an improved immersed
+ * moving boundary method for modelling complex particle-liquid flows involving
+ * adhesive particles" (arXiv 1901.09745):
+ *   - psc_rasterize: per-particle solid fractions by the linear approximation
+ *     (Sec. 2.4, Eqs. 15-19, Table 1), binned into per-tile particle lists;
+ *   - lbm_step: the fused collide-stream of the modified PSC lattice Boltzmann
+ *     equation (Sec. 2.1-2.3, Eqs. 1-6, 10, 12-13) with the per-particle
+ *     hydrodynamic force and torque of Eq. 14 and a global FP64 mass sum;
+ *   - dem_step: the adhesive DEM step with the JKR normal force and
+ *     Newton-Euler motion (Sec. 2.5, Eqs. 21, 25-27).
+ *
+ * Conventions shared by every call:
+ *   - All array arguments named d_* are DEVICE pointers; h_* are host pointers.
+ *     The caller owns all memory; the library never allocates device memory.
+ *     Lattice state, tile lists, particle snapshots, force accumulators and DEM
+ *     contact state live in one caller-provided device workspace of
+ *     psclbm_workspace_bytes() bytes.
+ *   - All work is enqueued asynchronously on the HIP stream given to lbm_init
+ *     (or psclbm_set_stream); one context per stream; calls on one context are
+ *     not thread-safe.
+ *   - Every call returns PSCLBM_OK (0) or a negative error code.  Argument
+ *     errors are reported synchronously and leave the state untouched.
+ *     Conditions detected on the device (slot or list overflow, contact
+ *     overflow, invalid particle radius, non-finite mass) raise a sticky flag
+ *     reported by the next psclbm_sync() or lbm_mass() call.
+ *   - The canonical distribution layout is f[i][z][y][x] in FP64 (x fastest),
+ *     with the velocity order
+ *       D2Q9 : 0 (0,0) 1 (1,0) 2 (0,1) 3 (-1,0) 4 (0,-1) 5 (1,1) 6 (-1,1)
+ *              7 (-1,-1) 8 (1,-1);
+ *       D3Q19: 0 rest, 1/2 = +-x, 3/4 = +-y, 5/6 = +-z, then (1,1,0),(-1,-1,0),
+ *              (1,-1,0),(-1,1,0),(1,0,1),(-1,0,-1),(1,0,-1),(-1,0,1),
+ *              (0,1,1),(0,-1,-1),(0,1,-1),(0,-1,1).
+ *     Cell (x, y, z) has its centre at the integer point (x, y, z).
+ *   - Particle arrays are FP64 structure-of-arrays: x[3n], u[3n], omega[3n]
+ *     (z components 0 in 2D; only omega_z is used in 2D) and radius[n].
+ */
+#ifndef PSCLBM_H
+#define PSCLBM_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ------------------------------------------------------- */
+#define PSCLBM_OK 0
+#define PSCLBM_EINVAL (-1)     /* invalid argument or configuration */
+#define PSCLBM_ENOMEM (-2)     /* workspace smaller than required */
+#define PSCLBM_EHIP (-3)       /* a HIP runtime call or launch failed */
+#define PSCLBM_ESLOTS (-4)     /* a cell or tile list exceeded its capacity */
+#define PSCLBM_ECONTACTS (-5)  /* a particle exceeded max_contacts, or a DEM bin overflowed */
+#define PSCLBM_ENONFINITE (-6) /* the lattice mass is not finite */
+#define PSCLBM_ESTATE (-7)     /* call out of order (e.g. lbm_step before psc_rasterize) */
+
+/* ---- face boundary kinds (faces: 0 x-, 1 x+, 2 y-, 3 y+, 4 z-, 5 z+) ------ */
+#define PSCLBM_PERIODIC 0      /* both faces of the axis must be periodic */
+#define PSCLBM_BOUNCE_BACK 1   /* resting wall at -1/2 or L-1/2, halfway bounce-back (Eq. 6) */
+#define PSCLBM_MOVING_WALL 2   /* bounce-back with the wall-momentum term
+                                  -2 w_i rho (e_i . u_w) / c_s^2, u_w = face_velocity */
+#define PSCLBM_INLET_EQ 3      /* boundary layer reset to f^eq(rho0, face_velocity) before
+                                  every collision */
+#define PSCLBM_OUTLET_EQ 4     /* boundary layer reset to f^eq(rho0, u of the adjacent interior
+                                  cell) before every collision */
+
+/* ---- precision forms --------------------------------------------------- */
+#define PSCLBM_FP64 0          /* FP64 storage of f, FP64 arithmetic */
+#define PSCLBM_FP32 1          /* FP32 storage of g_i = f_i - w_i rho0, FP32 arithmetic */
+#define PSCLBM_FP32_FP16STORE 2 /* FP16 storage of (f_i - w_i rho0) / w_i, FP32 arithmetic */
+/* In every form the particle force/torque accumulation, the mass sum and the
+ * DEM are FP64. */
+
+typedef struct {
+  int lattice;                /* 9 (D2Q9, requires nz == 1) or 19 (D3Q19) */
+  int nx, ny, nz;             /* lattice size, >= 1 each */
+  double tau;                 /* BGK relaxation time, > 1/2 (Eq. 2) */
+  double body_force[3];       /* constant fluid body-force density F (Eqs. 4-5) */
+  int face_bc[6];             /* PSCLBM_PERIODIC ... PSCLBM_OUTLET_EQ per face */
+  double face_velocity[6][3]; /* wall / inlet velocity per face */
+  double rho0;                /* reference density: initial state, inlet and outlet density */
+  double shell_h;             /* half-width h of the solid-fraction shell (Sec. 2.4), >= 0 */
+  int precision;              /* PSCLBM_FP64, PSCLBM_FP32 or PSCLBM_FP32_FP16STORE */
+  int max_particles;          /* capacity of the particle snapshot, >= 0 */
+  double max_radius;          /* largest particle radius the DEM bins are sized for */
+  int max_tile_particles;     /* capacity of each tile's particle list (e.g. 256) */
+  int max_contacts;           /* DEM contact capacity per particle (e.g. 16) */
+} psclbm_config;
+
+typedef struct {
+  int n;                      /* number of particles, 0 <= n <= max_particles */
+  const double* x;            /* d_x[3n]: centre positions */
+  const double* u;            /* d_u[3n]: translational velocities U_s */
+  const double* omega;        /* d_omega[3n]: angular velocities Omega_s */
+  const double* radius;       /* d_radius[n]: radii, r^2 > 1/4 (2D) or > 1/2 (3D) */
+} psclbm_particles;
+
+typedef struct {
+  double rho_p, rho_f;        /* particle and fluid density */
+  double E_p, poisson;        /* Young modulus and Poisson ratio (Eq. 25) */
+  double gamma;               /* surface energy (Eq. 27); work of adhesion 2 gamma */
+  double eta_n;               /* normal damping coefficient (Eq. 26) */
+  double g[3];                /* gravity; G = (rho_p - rho_f) V g */
+  double dt;                  /* coupling step (one LBM step) */
+  int n_sub;                  /* DEM sub-cycles per coupling step (lambda), >= 1 */
+  int kinematic;              /* nonzero: prescribed motion, x += dt u only */
+} psclbm_dem_params;
+
+typedef struct psclbm_ctx psclbm_ctx;
+
+/* Bytes of device workspace that lbm_init needs for cfg (0 if cfg is invalid).
+ * Host-only. */
+size_t psclbm_workspace_bytes(const psclbm_config* cfg);
+
+/* Create a context on d_workspace (device memory of at least
+ * psclbm_workspace_bytes(cfg) bytes, 256-byte aligned, owned by the caller
+ * and kept alive until lbm_free) and initialise f = f^eq(rho0, 0) (Eq. 3).
+ * hip_stream is a hipStream_t (NULL: the null stream).  *out receives the
+ * context (a small host allocation).  Errors: EINVAL (tau <= 1/2, lattice /
+ * nz mismatch, unpaired periodic faces, open face on an axis shorter than 3
+ * cells, negative capacities), ENOMEM (workspace too small), EHIP. */
+int lbm_init(const psclbm_config* cfg, void* d_workspace, size_t bytes, void* hip_stream,
+             psclbm_ctx** out);
+
+/* Release the host-side context (the workspace stays the caller's). */
+void lbm_free(psclbm_ctx* ctx);
+
+/* Change the stream used by later calls. */
+int psclbm_set_stream(psclbm_ctx* ctx, void* hip_stream);
+
+/* Load / store the state in the canonical FP64 layout (Q*N doubles, device),
+ * whatever the storage precision and streaming parity.  lbm_set_f converts to
+ * the storage form (rounding in the FP32 / FP16 forms). */
+int lbm_set_f(psclbm_ctx* ctx, const double* d_f);
+int lbm_get_f(psclbm_ctx* ctx, double* d_f);
+
+/* f = f^eq(rho, u) per cell (Eq. 3); d_rho[N] or NULL (rho0), d_u[3N] or NULL
+ * (rest). */
+int lbm_set_equilibrium(psclbm_ctx* ctx, const double* d_rho, const double* d_u);
+
+/* Density and velocity of the current state (Eq. 5, with the half-force
+ * shift): d_rho[N], d_u[3N] (either may be NULL). */
+int lbm_get_macros(psclbm_ctx* ctx, double* d_rho, double* d_u);
+
+/* Snapshot the particle state and bin every particle into the lattice tiles
+ * its shell box X +- (r + h) touches (Table 1 Step 1).  The following
+ * lbm_step calls use this snapshot for positions, velocities and radii; the
+ * solid fractions eps_{n,s} (Eqs. 15-19, Table 1 Steps 2-6) are evaluated per
+ * cell inside lbm_step.  Errors: EINVAL (n out of range, NULL arrays), EHIP;
+ * sticky ESLOTS if a tile list overflows, sticky EINVAL for a radius outside
+ * the domain of Eqs. 17/19. */
+int psc_rasterize(psclbm_ctx* ctx, const psclbm_particles* p);
+
+/* Materialise the rasterised solid fractions for inspection: d_eps_total[N]
+ * = min(sum_s eps_{n,s}, 1) (Table 1 Step 5); optionally the first kslots
+ * recorded particles per cell in ascending id, d_slot_id[N*kslots] (-1 when
+ * empty) and d_slot_eps[N*kslots] (either may be NULL). */
+int psc_get_solid_fraction(psclbm_ctx* ctx, double* d_eps_total, int* d_slot_id,
+                           double* d_slot_eps, int kslots);
+
+/* Advance the lattice nsteps >= 1 time steps: per step, per cell, the moments
+ * (Eq. 5), the modified PSC collision (Eqs. 3-4, 10, 12-13) with the solid
+ * fractions of the rasterised particles, the hydrodynamic force and torque of
+ * Eq. 14 on every particle, and in-place streaming with periodic, bounce-back
+ * (Eq. 6), moving-wall and inlet/outlet boundaries.  Errors: ESTATE if
+ * particles were never rasterised (use psc_rasterize with n = 0 for pure
+ * fluid), EINVAL, EHIP; sticky ESLOTS if a cell is covered by more particles
+ * than the kernel's slot capacity (4). */
+int lbm_step(psclbm_ctx* ctx, int nsteps);
+
+/* Copy the FP64 hydrodynamic force and torque (Eq. 14) of the most recent
+ * lbm_step to d_force[3n] and d_torque[3n] (n of the snapshot; either pointer
+ * may be NULL).  The torque is about the particle centre; in 2D only its z
+ * component is nonzero. */
+int particle_forces(psclbm_ctx* ctx, double* d_force, double* d_torque);
+
+/* One DEM coupling step (Eq. 21) for n particles, updating d_x, d_u, d_omega
+ * in place: n_sub semi-implicit Euler sub-steps of dt/n_sub with the
+ * hydrodynamic force d_force[3n] and torque d_torque[3n] held fixed (Sec. 2.5),
+ * gravity (rho_p - rho_f) V g, and JKR normal contacts (Eqs. 25-27, with the
+ * jump-on / pull-off hysteresis) between particles and with the walls of
+ * non-periodic axes (flat walls at -1/2 and L-1/2).  Positions wrap into
+ * [0, L) on periodic axes.  2D: disks of unit depth.  Contact history lives in
+ * the workspace (dem_reset_contacts clears it).  Errors: EINVAL (bad params,
+ * n > max_particles, a contact reach beyond the bin size), EHIP; sticky
+ * ECONTACTS on contact or bin overflow, sticky EINVAL for a radius above
+ * max_radius. */
+int dem_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double* d_u,
+             double* d_omega, const double* d_radius, int n, const double* d_force,
+             const double* d_torque);
+
+/* Forget all DEM contacts (no pair is bonded). */
+int dem_reset_contacts(psclbm_ctx* ctx);
+
+/* Synchronise the stream and return the total mass sum_n sum_i f_i of the
+ * current state in FP64 (*h_mass), or the sticky error if one is set
+ * (ENONFINITE if the mass is not finite). */
+int lbm_mass(psclbm_ctx* ctx, double* h_mass);
+
+/* Synchronise the stream; return and clear the sticky device error. */
+int psclbm_sync(psclbm_ctx* ctx);
+
+/* Static description of an error code. */
+const char* psclbm_strerror(int code);
+
+/* Number of completed lbm_step time steps since lbm_init / lbm_set_f /
+ * lbm_set_equilibrium (the in-place streaming parity is its low bit). */
+long long lbm_step_count(const psclbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PSCLBM_H */

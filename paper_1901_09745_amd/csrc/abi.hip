@@ -1,0 +1,362 @@
+// extern "C" entry points of the gfx950 PSC-LBM library (see include/psclbm.h).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+
+#include "common.hpp"
+
+using namespace psclbm;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+inline int storage_bytes(int prec) {
+  return prec == PSCLBM_FP64 ? 8 : (prec == PSCLBM_FP32 ? 4 : 2);
+}
+
+bool axis_is_periodic(const psclbm_config* c, int a) {
+  if (a == 2 && c->lattice == 9) return true;
+  return c->face_bc[2 * a] == PSCLBM_PERIODIC;
+}
+
+// Validates a configuration; 0 when usable.
+int validate(const psclbm_config* c) {
+  if (!c) return PSCLBM_EINVAL;
+  if (c->lattice != 9 && c->lattice != 19) return PSCLBM_EINVAL;
+  if (c->nx < 1 || c->ny < 1 || c->nz < 1) return PSCLBM_EINVAL;
+  if (c->lattice == 9 && c->nz != 1) return PSCLBM_EINVAL;
+  if (!(c->tau > 0.5) || !std::isfinite(c->tau)) return PSCLBM_EINVAL;
+  if (!(c->rho0 > 0.0) || !std::isfinite(c->rho0)) return PSCLBM_EINVAL;
+  if (!(c->shell_h >= 0.0) || !std::isfinite(c->shell_h)) return PSCLBM_EINVAL;
+  if (c->precision < PSCLBM_FP64 || c->precision > PSCLBM_FP32_FP16STORE) return PSCLBM_EINVAL;
+  for (int k = 0; k < 3; ++k)
+    if (!std::isfinite(c->body_force[k])) return PSCLBM_EINVAL;
+  const int L[3] = {c->nx, c->ny, c->nz};
+  for (int a = 0; a < (c->lattice == 9 ? 2 : 3); ++a) {
+    const int f0 = c->face_bc[2 * a], f1 = c->face_bc[2 * a + 1];
+    for (int f : {f0, f1})
+      if (f < PSCLBM_PERIODIC || f > PSCLBM_OUTLET_EQ) return PSCLBM_EINVAL;
+    if ((f0 == PSCLBM_PERIODIC) != (f1 == PSCLBM_PERIODIC)) return PSCLBM_EINVAL;
+    for (int f : {f0, f1})
+      if ((f == PSCLBM_INLET_EQ || f == PSCLBM_OUTLET_EQ) && L[a] < 3) return PSCLBM_EINVAL;
+  }
+  for (int f = 0; f < 6; ++f)
+    for (int k = 0; k < 3; ++k)
+      if (!std::isfinite(c->face_velocity[f][k])) return PSCLBM_EINVAL;
+  if (c->max_particles < 0) return PSCLBM_EINVAL;
+  if (c->max_particles > 0) {
+    if (c->max_tile_particles < 1 || c->max_tile_particles > 512) return PSCLBM_EINVAL;
+    if (c->max_contacts < 1 || c->max_contacts > 64) return PSCLBM_EINVAL;
+    if (!(c->max_radius > 0.0) || !std::isfinite(c->max_radius)) return PSCLBM_EINVAL;
+  }
+  const double cells = (double)c->nx * c->ny * c->nz;
+  if (cells * c->lattice > 9.0e12) return PSCLBM_EINVAL;
+  return PSCLBM_OK;
+}
+
+struct Layout {
+  size_t f, err, scalar, tile_count, tile_list, snap, facc0, facc1, mass_part, outlet_u;
+  size_t bin_count, bin_list, cn0, cn1, cid0, cid1, fcontact, total;
+  int ntx, nty, ntz, ntiles;
+  long long face_stride;
+  int nbin[3];
+  double bin_size[3];
+  int bin_cap;
+};
+
+Layout plan(const psclbm_config* c) {
+  Layout l;
+  const long long N = (long long)c->nx * c->ny * c->nz;
+  l.ntx = (c->nx + TX - 1) / TX;
+  l.nty = (c->ny + TY - 1) / TY;
+  l.ntz = (c->nz + TZ - 1) / TZ;
+  l.ntiles = l.ntx * l.nty * l.ntz;
+  const int np = c->max_particles;
+  const int cap = np > 0 ? c->max_tile_particles : 1;
+  bool outlet = false;
+  for (int f = 0; f < 6; ++f) outlet |= c->face_bc[f] == PSCLBM_OUTLET_EQ;
+  long long fs = (long long)c->ny * c->nz;
+  if ((long long)c->nx * c->nz > fs) fs = (long long)c->nx * c->nz;
+  if ((long long)c->nx * c->ny > fs) fs = (long long)c->nx * c->ny;
+  l.face_stride = fs;
+  // DEM bins: at least 2 r_max + 1 wide so that every contact partner (centre
+  // distance below r_i + r_j + delta_C with delta_C <= 1) is in a neighbour bin
+  const int L[3] = {c->nx, c->ny, c->nz};
+  const double bs = np > 0 ? 2.0 * c->max_radius + 1.0 : 1.0;
+  for (int a = 0; a < 3; ++a) {
+    if (a == 2 && c->lattice == 9) {
+      l.nbin[a] = 1;
+      l.bin_size[a] = 1.0;
+      continue;
+    }
+    int nb = (int)std::floor(L[a] / bs);
+    if (nb < 1) nb = 1;
+    l.nbin[a] = nb;
+    l.bin_size[a] = (double)L[a] / nb;
+  }
+  l.bin_cap = 32;
+  const size_t nbins = (size_t)l.nbin[0] * l.nbin[1] * l.nbin[2];
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at = off;
+    off += align_up(bytes > 0 ? bytes : 1);
+    return at;
+  };
+  l.f = take((size_t)N * c->lattice * storage_bytes(c->precision));
+  l.err = take(sizeof(unsigned) * 4);
+  l.scalar = take(sizeof(double) * 4);
+  l.tile_count = take(sizeof(int) * (size_t)l.ntiles);
+  l.tile_list = take(sizeof(int) * (size_t)l.ntiles * cap);
+  l.snap = take(sizeof(PSnap) * (size_t)(np > 0 ? np : 1));
+  l.facc0 = take(sizeof(double) * 6 * (size_t)(np > 0 ? np : 1));
+  l.facc1 = take(sizeof(double) * 6 * (size_t)(np > 0 ? np : 1));
+  l.mass_part = take(sizeof(double) * (size_t)l.ntiles);
+  l.outlet_u = take(outlet ? sizeof(double) * 3 * 6 * (size_t)fs : 8);
+  const int mc = np > 0 ? c->max_contacts : 1;
+  l.bin_count = take(sizeof(int) * nbins);
+  l.bin_list = take(sizeof(int) * nbins * l.bin_cap * (np > 0 ? 1 : 0));
+  l.cn0 = take(sizeof(int) * (size_t)(np > 0 ? np : 1));
+  l.cn1 = take(sizeof(int) * (size_t)(np > 0 ? np : 1));
+  l.cid0 = take(sizeof(int) * (size_t)(np > 0 ? np : 1) * mc);
+  l.cid1 = take(sizeof(int) * (size_t)(np > 0 ? np : 1) * mc);
+  l.fcontact = take(sizeof(double) * 3 * (size_t)(np > 0 ? np : 1));
+  l.total = off;
+  return l;
+}
+
+int sticky(psclbm_ctx* c, bool clear) {
+  unsigned bits = 0;
+  int rc = hip_ok(hipMemcpyAsync(&bits, c->err, sizeof(unsigned), hipMemcpyDeviceToHost,
+                                 c->stream));
+  if (rc) return rc;
+  rc = hip_ok(hipStreamSynchronize(c->stream));
+  if (rc) return rc;
+  if (bits && clear) {
+    rc = hip_ok(hipMemsetAsync(c->err, 0, sizeof(unsigned), c->stream));
+    if (rc) return rc;
+  }
+  if (bits & ERR_SLOTS) return PSCLBM_ESLOTS;
+  if (bits & ERR_CONTACTS) return PSCLBM_ECONTACTS;
+  if (bits & ERR_RADIUS) return PSCLBM_EINVAL;
+  return PSCLBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t psclbm_workspace_bytes(const psclbm_config* cfg) {
+  if (validate(cfg) != PSCLBM_OK) return 0;
+  return plan(cfg).total;
+}
+
+int lbm_init(const psclbm_config* cfg, void* d_workspace, size_t bytes, void* hip_stream,
+             psclbm_ctx** out) {
+  if (!out) return PSCLBM_EINVAL;
+  *out = nullptr;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (!d_workspace || ((uintptr_t)d_workspace % ALIGN) != 0) return PSCLBM_EINVAL;
+  const Layout l = plan(cfg);
+  if (bytes < l.total) return PSCLBM_ENOMEM;
+  psclbm_ctx* c = new (std::nothrow) psclbm_ctx();
+  if (!c) return PSCLBM_EINVAL;
+  std::memset(c, 0, sizeof(*c));
+  c->cfg = *cfg;
+  c->stream = static_cast<hipStream_t>(hip_stream);
+  char* base = static_cast<char*>(d_workspace);
+  Geom& g = c->geom;
+  g.nx = cfg->nx;
+  g.ny = cfg->ny;
+  g.nz = cfg->nz;
+  g.N = (long long)cfg->nx * cfg->ny * cfg->nz;
+  g.q = cfg->lattice;
+  for (int f = 0; f < 6; ++f) {
+    g.face[f] = cfg->face_bc[f];
+    if (cfg->lattice == 9 && f >= 4) g.face[f] = PSCLBM_PERIODIC;
+    for (int k = 0; k < 3; ++k) g.face_u[f][k] = cfg->face_velocity[f][k];
+  }
+  for (int a = 0; a < 3; ++a) g.periodic[a] = axis_is_periodic(cfg, a) ? 1 : 0;
+  g.ntx = l.ntx;
+  g.nty = l.nty;
+  g.ntz = l.ntz;
+  g.rho0 = cfg->rho0;
+  c->prec = cfg->precision;
+  c->f = base + l.f;
+  c->err = reinterpret_cast<unsigned*>(base + l.err);
+  c->scalar = reinterpret_cast<double*>(base + l.scalar);
+  c->tile_count = reinterpret_cast<int*>(base + l.tile_count);
+  c->tile_list = reinterpret_cast<int*>(base + l.tile_list);
+  c->ntiles = l.ntiles;
+  c->snap = reinterpret_cast<PSnap*>(base + l.snap);
+  c->facc[0] = reinterpret_cast<double*>(base + l.facc0);
+  c->facc[1] = reinterpret_cast<double*>(base + l.facc1);
+  c->mass_part = reinterpret_cast<double*>(base + l.mass_part);
+  c->nblocks = l.ntiles;
+  c->outlet_u = reinterpret_cast<double*>(base + l.outlet_u);
+  c->face_stride = l.face_stride;
+  for (int a = 0; a < 3; ++a) {
+    c->nbin[a] = l.nbin[a];
+    c->bin_size[a] = l.bin_size[a];
+  }
+  c->bin_cap = l.bin_cap;
+  c->bin_count = reinterpret_cast<int*>(base + l.bin_count);
+  c->bin_list = reinterpret_cast<int*>(base + l.bin_list);
+  c->contact_n[0] = reinterpret_cast<int*>(base + l.cn0);
+  c->contact_n[1] = reinterpret_cast<int*>(base + l.cn1);
+  c->contact_id[0] = reinterpret_cast<int*>(base + l.cid0);
+  c->contact_id[1] = reinterpret_cast<int*>(base + l.cid1);
+  c->fcontact = reinterpret_cast<double*>(base + l.fcontact);
+  // clear everything but the distributions, then set f = f^eq(rho0, 0)
+  rc = launch_zero(c, base + l.err, l.total - l.err);
+  if (!rc) rc = launch_init_equilibrium(c, nullptr, nullptr);
+  if (rc) {
+    delete c;
+    return rc;
+  }
+  *out = c;
+  return PSCLBM_OK;
+}
+
+void lbm_free(psclbm_ctx* ctx) { delete ctx; }
+
+int psclbm_set_stream(psclbm_ctx* ctx, void* hip_stream) {
+  if (!ctx) return PSCLBM_EINVAL;
+  ctx->stream = static_cast<hipStream_t>(hip_stream);
+  return PSCLBM_OK;
+}
+
+int lbm_set_f(psclbm_ctx* ctx, const double* d_f) {
+  if (!ctx || !d_f) return PSCLBM_EINVAL;
+  int rc = launch_set_f(ctx, d_f);
+  if (rc) return rc;
+  ctx->steps = 0;
+  ctx->mass_valid = 0;
+  return PSCLBM_OK;
+}
+
+int lbm_get_f(psclbm_ctx* ctx, double* d_f) {
+  if (!ctx || !d_f) return PSCLBM_EINVAL;
+  return launch_get_f(ctx, d_f);
+}
+
+int lbm_set_equilibrium(psclbm_ctx* ctx, const double* d_rho, const double* d_u) {
+  if (!ctx) return PSCLBM_EINVAL;
+  int rc = launch_init_equilibrium(ctx, d_rho, d_u);
+  if (rc) return rc;
+  ctx->steps = 0;
+  ctx->mass_valid = 0;
+  return PSCLBM_OK;
+}
+
+int lbm_get_macros(psclbm_ctx* ctx, double* d_rho, double* d_u) {
+  if (!ctx) return PSCLBM_EINVAL;
+  if (!d_rho && !d_u) return PSCLBM_OK;
+  return launch_get_macros(ctx, d_rho, d_u);
+}
+
+int psc_rasterize(psclbm_ctx* ctx, const psclbm_particles* p) {
+  if (!ctx || !p) return PSCLBM_EINVAL;
+  if (p->n < 0 || p->n > ctx->cfg.max_particles) return PSCLBM_EINVAL;
+  if (p->n > 0 && (!p->x || !p->u || !p->omega || !p->radius)) return PSCLBM_EINVAL;
+  int rc = launch_rasterize(ctx, p);
+  if (rc) return rc;
+  ctx->np = p->n;
+  ctx->rasterized = 1;
+  return PSCLBM_OK;
+}
+
+int psc_get_solid_fraction(psclbm_ctx* ctx, double* d_eps_total, int* d_slot_id,
+                           double* d_slot_eps, int kslots) {
+  if (!ctx || kslots < 0) return PSCLBM_EINVAL;
+  if (!ctx->rasterized) return PSCLBM_ESTATE;
+  if (kslots == 0) d_slot_id = nullptr, d_slot_eps = nullptr;
+  return launch_solid_fraction(ctx, d_eps_total, d_slot_id, d_slot_eps, kslots);
+}
+
+int lbm_step(psclbm_ctx* ctx, int nsteps) {
+  if (!ctx || nsteps < 1) return PSCLBM_EINVAL;
+  if (!ctx->rasterized) return PSCLBM_ESTATE;
+  for (int k = 0; k < nsteps; ++k) {
+    int rc = launch_step(ctx);
+    if (rc) return rc;
+  }
+  return PSCLBM_OK;
+}
+
+int particle_forces(psclbm_ctx* ctx, double* d_force, double* d_torque) {
+  if (!ctx) return PSCLBM_EINVAL;
+  if (!ctx->rasterized) return PSCLBM_ESTATE;
+  if (ctx->np == 0 || (!d_force && !d_torque)) return PSCLBM_OK;
+  const double* src = ctx->facc[ctx->force_buf];
+  const size_t pitch = 6 * sizeof(double);
+  int rc = PSCLBM_OK;
+  if (d_force)
+    rc = hip_ok(hipMemcpy2DAsync(d_force, 3 * sizeof(double), src, pitch, 3 * sizeof(double),
+                                 ctx->np, hipMemcpyDeviceToDevice, ctx->stream));
+  if (!rc && d_torque)
+    rc = hip_ok(hipMemcpy2DAsync(d_torque, 3 * sizeof(double), src + 3, pitch,
+                                 3 * sizeof(double), ctx->np, hipMemcpyDeviceToDevice,
+                                 ctx->stream));
+  return rc;
+}
+
+int dem_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double* d_u,
+             double* d_omega, const double* d_radius, int n, const double* d_force,
+             const double* d_torque) {
+  if (!ctx || !prm) return PSCLBM_EINVAL;
+  if (n < 0 || n > ctx->cfg.max_particles) return PSCLBM_EINVAL;
+  if (n == 0) return PSCLBM_OK;
+  if (!d_x || !d_u || !d_omega || !d_radius) return PSCLBM_EINVAL;
+  if (!prm->kinematic && (!d_force || !d_torque)) return PSCLBM_EINVAL;
+  if (prm->n_sub < 1 || !(prm->dt > 0.0) || !std::isfinite(prm->dt)) return PSCLBM_EINVAL;
+  if (!prm->kinematic) {
+    if (!(prm->rho_p > 0.0) || !(prm->E_p > 0.0) || !(prm->gamma >= 0.0) ||
+        !(prm->poisson > -1.0 && prm->poisson < 0.5) || !(prm->eta_n >= 0.0))
+      return PSCLBM_EINVAL;
+  }
+  return launch_dem_step(ctx, prm, d_x, d_u, d_omega, d_radius, n, d_force, d_torque);
+}
+
+int dem_reset_contacts(psclbm_ctx* ctx) {
+  if (!ctx) return PSCLBM_EINVAL;
+  return launch_dem_reset(ctx);
+}
+
+int lbm_mass(psclbm_ctx* ctx, double* h_mass) {
+  if (!ctx || !h_mass) return PSCLBM_EINVAL;
+  int rc = launch_mass(ctx, h_mass);
+  if (rc) return rc;
+  rc = sticky(ctx, true);
+  if (rc) return rc;
+  if (!std::isfinite(*h_mass)) return PSCLBM_ENONFINITE;
+  return PSCLBM_OK;
+}
+
+int psclbm_sync(psclbm_ctx* ctx) {
+  if (!ctx) return PSCLBM_EINVAL;
+  return sticky(ctx, true);
+}
+
+long long lbm_step_count(const psclbm_ctx* ctx) { return ctx ? ctx->steps : -1; }
+
+const char* psclbm_strerror(int code) {
+  switch (code) {
+    case PSCLBM_OK: return "success";
+    case PSCLBM_EINVAL: return "invalid argument or configuration";
+    case PSCLBM_ENOMEM: return "workspace smaller than psclbm_workspace_bytes()";
+    case PSCLBM_EHIP: return "HIP runtime error";
+    case PSCLBM_ESLOTS: return "a cell or tile particle list exceeded its capacity";
+    case PSCLBM_ECONTACTS: return "DEM contact list or bin exceeded its capacity";
+    case PSCLBM_ENONFINITE: return "lattice mass is not finite";
+    case PSCLBM_ESTATE: return "call out of order";
+    default: return "unknown error";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,188 @@
+// Internal declarations of the gfx950 PSC-LBM library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "psclbm.h"
+
+namespace psclbm {
+
+// ---------------------------------------------------------------------------
+// Lattice velocity sets in the canonical order of psclbm.h.
+// ---------------------------------------------------------------------------
+template <int Q>
+struct Lattice;
+
+template <>
+struct Lattice<9> {
+  static constexpr int D = 2;
+  __host__ __device__ static constexpr int ex(int i) {
+    return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int ey(int i) {
+    return i == 2 || i == 5 || i == 6 ? 1 : (i == 4 || i == 7 || i == 8 ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int ez(int) { return 0; }
+  // 1 <-> 3, 2 <-> 4, 5 <-> 7, 6 <-> 8
+  __host__ __device__ static constexpr int opp(int i) {
+    return i == 0 ? 0 : (i <= 4 ? (i + 1) % 4 + 1 : (i - 3) % 4 + 5);
+  }
+  __host__ __device__ static constexpr double w(int i) {
+    return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+  }
+};
+
+template <>
+struct Lattice<19> {
+  static constexpr int D = 3;
+  // rest, +-x, +-y, +-z, then the 12 edge vectors in (v, -v) pairs
+  __host__ __device__ static constexpr int ex(int i) {
+    return i == 1 || i == 7 || i == 9 || i == 11 || i == 13
+               ? 1
+               : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14 ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int ey(int i) {
+    return i == 3 || i == 7 || i == 10 || i == 15 || i == 17
+               ? 1
+               : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18 ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int ez(int i) {
+    return i == 5 || i == 11 || i == 14 || i == 15 || i == 18
+               ? 1
+               : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17 ? -1 : 0);
+  }
+  __host__ __device__ static constexpr int opp(int i) { return i == 0 ? 0 : (i % 2 ? i + 1 : i - 1); }
+  __host__ __device__ static constexpr double w(int i) {
+    return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+  }
+};
+
+// Storage / compute type pairs of the three precision forms.
+template <int PREC>
+struct Form;
+template <>
+struct Form<PSCLBM_FP64> {
+  using S = double;  // stores f_i
+  using C = double;
+};
+template <>
+struct Form<PSCLBM_FP32> {
+  using S = float;  // stores f_i - w_i rho0
+  using C = float;
+};
+template <>
+struct Form<PSCLBM_FP32_FP16STORE> {
+  using S = _Float16;  // stores (f_i - w_i rho0) / w_i
+  using C = float;
+};
+
+// Workgroup tile: 64 cells along x (one wave per row) by 4 rows along y.
+constexpr int TX = 64;
+constexpr int TY = 4;
+constexpr int TZ = 1;
+constexpr int BLOCK = TX * TY * TZ;
+constexpr int KSLOTS = 4;  // particles a single cell can be covered by
+
+// Sticky device error bits.
+constexpr unsigned ERR_SLOTS = 1u;
+constexpr unsigned ERR_RADIUS = 2u;
+constexpr unsigned ERR_CONTACTS = 4u;
+
+// Snapshot of one particle used by the lattice kernels (FP64).
+struct alignas(16) PSnap {
+  double x[3];
+  double r;
+  double cs;  // V_a(r) + 1/2 (Eqs. 15, 18)
+  double u[3];
+  double w[3];
+  double pad;
+};
+
+// Geometry shared by all lattice kernels (passed by value).
+struct Geom {
+  int nx, ny, nz;
+  long long N;
+  int q;
+  int face[6];
+  int periodic[3];
+  int ntx, nty, ntz;
+  double face_u[6][3];
+  double rho0;
+};
+
+struct StepArgs {
+  Geom g;
+  void* f;
+  double tau;
+  double force[3];
+  double h;
+  int np;
+  int cap;                 // tile list capacity
+  const int* tile_count;
+  const int* tile_list;
+  const PSnap* snap;
+  double* facc;            // force / torque buffer accumulated this step: [np][6]
+  double* fzero;           // the other buffer, cleared this step
+  double* mass_part;       // per-block mass partials
+  const double* outlet_u;  // [6][max face cells][3]
+  long long face_stride;   // cells per face slot in outlet_u
+  unsigned* err;
+  int has_open;            // any inlet / outlet face
+};
+
+}  // namespace psclbm
+
+struct psclbm_ctx {
+  psclbm_config cfg;
+  hipStream_t stream;
+  psclbm::Geom geom;
+  int prec;
+  void* f;
+  unsigned* err;
+  int* tile_count;
+  int* tile_list;
+  int ntiles;
+  psclbm::PSnap* snap;
+  double* facc[2];
+  double* mass_part;
+  int nblocks;
+  double* outlet_u;
+  long long face_stride;
+  // DEM
+  int nbin[3];
+  double bin_size[3];
+  int bin_cap;
+  int* bin_count;
+  int* bin_list;
+  int* contact_n[2];
+  int* contact_id[2];
+  int contact_cur;
+  double* fcontact;
+  double* scalar;  // one FP64 device scalar for reductions
+  // host-side state
+  long long steps;
+  int np;
+  int rasterized;
+  int force_buf;   // buffer holding the last step's forces
+  int mass_valid;  // mass partials describe the current state
+};
+
+namespace psclbm {
+// Launchers (return a psclbm error code).
+int launch_init_equilibrium(psclbm_ctx* c, const double* rho, const double* u);
+int launch_set_f(psclbm_ctx* c, const double* f);
+int launch_get_f(psclbm_ctx* c, double* f);
+int launch_get_macros(psclbm_ctx* c, double* rho, double* u);
+int launch_rasterize(psclbm_ctx* c, const psclbm_particles* p);
+int launch_solid_fraction(psclbm_ctx* c, double* eps, int* ids, double* seps, int k);
+int launch_step(psclbm_ctx* c);
+int launch_mass(psclbm_ctx* c, double* h_mass);
+int launch_zero(psclbm_ctx* c, void* p, size_t bytes);
+int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, double* u,
+                    double* w, const double* r, int n, const double* F, const double* T);
+int launch_dem_reset(psclbm_ctx* c);
+inline int hip_ok(hipError_t e) { return e == hipSuccess ? PSCLBM_OK : PSCLBM_EHIP; }
+}  // namespace psclbm

@@ -1,0 +1,364 @@
+// Adhesive DEM step of the gfx950 PSC-LBM library (FP64), Sec. 2.5:
+// Newton-Euler motion (Eq. 21) with the JKR normal contact force (Eqs. 25-27)
+// including the jump-on / pull-off hysteresis, sub-cycled n_sub times per
+// coupling step with the hydrodynamic force and torque held fixed.
+//
+// Per sub-step: (1) bin the particles into a uniform grid whose bins are at
+// least 2 r_max + 1 wide, (2) one thread per particle gathers its contacts
+// from the neighbouring bins and the walls, sums their forces in ascending
+// partner order and records the new contact list, (3) one thread per particle
+// integrates with semi-implicit Euler.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "common.hpp"
+
+namespace psclbm {
+
+constexpr int MAXC = 64;  // contacts a thread can hold while sorting
+
+struct DemArgs {
+  int n;
+  int three_d;
+  int L[3];
+  int periodic[3];
+  int nbin[3];
+  double bin_size[3];
+  int bin_cap;
+  int* bin_count;
+  int* bin_list;
+  const int* prev_n;
+  const int* prev_id;
+  int* next_n;
+  int* next_id;
+  int max_contacts;
+  double* fc;
+  double E;       // effective modulus of two bodies of the material (Eq. 25)
+  double gamma;
+  double eta_n;
+  unsigned* err;
+};
+
+__device__ inline double min_img(double d, int periodic, int L) {
+  if (periodic) {
+    if (d > 0.5 * L) d -= L;
+    else if (d < -0.5 * L) d += L;
+  }
+  return d;
+}
+
+// JKR (work of adhesion 2 gamma): F/F_C = 4 (x^3 - x^{3/2}) with x = a/a0 on
+// the stable branch of delta/delta_C = 6^{1/3} (2 x^2 - (4/3) x^{1/2}),
+// F_C = 3 pi gamma R, a0^3 = 9 pi gamma R^2 / E, delta_C = a0^2/(2 6^{1/3} R).
+// Solved for s = x^{1/2} by Newton from above (g(s) = 2 s^4 - 4/3 s is convex
+// and increasing on the branch s >= 6^{-1/3}, so the iterates decrease
+// monotonically to the root).  Returns the repulsive-positive force.
+__device__ inline double jkr_force(double R, double E, double gamma, double delta, double* dC) {
+  const double c6 = 1.8171205928321397;  // 6^{1/3}
+  const double FC = 3.0 * M_PI * gamma * R;
+  const double a0 = cbrt(9.0 * M_PI * gamma * R * R / E);
+  const double dc = a0 * a0 / (2.0 * c6 * R);
+  *dC = dc;
+  const double target = (delta / dc) / c6;
+  const double sC = 1.0 / c6;
+  double s;
+  if (target <= 2.0 * sC * sC * sC * sC - (4.0 / 3.0) * sC) {
+    s = sC;
+  } else {
+    s = fmax(1.0, sqrt(sqrt(1.5 * fmax(target, 0.0))));
+    for (int it = 0; it < 200; ++it) {
+      const double s3 = s * s * s;
+      const double gs = 2.0 * s3 * s - (4.0 / 3.0) * s - target;
+      const double dg = 8.0 * s3 - 4.0 / 3.0;
+      double sn = s - gs / dg;
+      if (sn < sC) sn = sC;
+      if (!(sn < s)) break;  // monotone from above: stop when it no longer decreases
+      s = sn;
+    }
+  }
+  const double x = s * s;
+  return 4.0 * FC * (x * x * x - x * s);
+}
+
+__global__ void k_dem_clear(int* count, int nb) {
+  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nb; k += gridDim.x * blockDim.x)
+    count[k] = 0;
+}
+
+__device__ inline int bin_coord(double x, int a, const DemArgs& d) {
+  double v = x;
+  if (d.periodic[a]) {
+    v = fmod(v, (double)d.L[a]);
+    if (v < 0) v += d.L[a];
+  }
+  int b = (int)floor(v / d.bin_size[a]);
+  if (b < 0) b = 0;
+  if (b >= d.nbin[a]) b = d.nbin[a] - 1;
+  return b;
+}
+
+__global__ void k_dem_bin(DemArgs d, const double* x) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const int bx = bin_coord(x[3 * i], 0, d);
+  const int by = bin_coord(x[3 * i + 1], 1, d);
+  const int bz = d.three_d ? bin_coord(x[3 * i + 2], 2, d) : 0;
+  const int b = bx + d.nbin[0] * (by + d.nbin[1] * bz);
+  const int k = atomicAdd(&d.bin_count[b], 1);
+  if (k < d.bin_cap)
+    d.bin_list[(size_t)b * d.bin_cap + k] = i;
+  else
+    atomicOr(d.err, ERR_CONTACTS);
+}
+
+// Distinct neighbour-bin offsets along one axis.
+__device__ inline int axis_offsets(int b, int a, const DemArgs& d, int* out) {
+  const int nb = d.nbin[a];
+  int k = 0;
+  if (d.periodic[a]) {
+    if (nb == 1) {
+      out[k++] = 0;
+    } else if (nb == 2) {
+      out[k++] = b;
+      out[k++] = 1 - b;
+    } else {
+      out[k++] = (b + nb - 1) % nb;
+      out[k++] = b;
+      out[k++] = (b + 1) % nb;
+    }
+  } else {
+    for (int o = -1; o <= 1; ++o)
+      if (b + o >= 0 && b + o < nb) out[k++] = b + o;
+  }
+  return k;
+}
+
+__device__ inline bool was_in_contact(const int* ids, int n, int id) {
+  for (int k = 0; k < n; ++k)
+    if (ids[k] == id) return true;
+  return false;
+}
+
+__global__ void k_dem_contacts(DemArgs d, const double* x, const double* u, const double* r) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.n) return;
+  const double xi[3] = {x[3 * i], x[3 * i + 1], d.three_d ? x[3 * i + 2] : 0.0};
+  const double ui[3] = {u[3 * i], u[3 * i + 1], d.three_d ? u[3 * i + 2] : 0.0};
+  const double ri = r[i];
+  const int pn = d.prev_n[i];
+  const int* prev = d.prev_id + (size_t)i * d.max_contacts;
+  int cid[MAXC];
+  double cf[MAXC][3];
+  int cnt = 0;
+  bool overflow = false;
+  auto add = [&](int id, const double* f) {
+    if (cnt >= d.max_contacts || cnt >= MAXC) {
+      overflow = true;
+      return;
+    }
+    // keep ascending partner ids
+    int k = cnt;
+    while (k > 0 && cid[k - 1] > id) {
+      cid[k] = cid[k - 1];
+      cf[k][0] = cf[k - 1][0];
+      cf[k][1] = cf[k - 1][1];
+      cf[k][2] = cf[k - 1][2];
+      --k;
+    }
+    cid[k] = id;
+    cf[k][0] = f[0];
+    cf[k][1] = f[1];
+    cf[k][2] = f[2];
+    ++cnt;
+  };
+  const int D = d.three_d ? 3 : 2;
+  // walls of non-periodic axes: flat bodies at -1/2 and L-1/2 (1/R = 1/r)
+  for (int face = 0; face < 2 * D; ++face) {
+    const int a = face / 2;
+    if (d.periodic[a]) continue;
+    const double dist = (face % 2 == 0) ? xi[a] + 0.5 : (d.L[a] - 0.5) - xi[a];
+    const double delta = ri - dist;
+    const int id = -1 - face;
+    double dC;
+    const double F = jkr_force(ri, d.E, d.gamma, delta, &dC);
+    if (delta >= 0.0 || (delta > -dC && was_in_contact(prev, pn, id))) {
+      double nrm[3] = {0, 0, 0};
+      nrm[a] = (face % 2 == 0) ? -1.0 : 1.0;
+      const double vrn = -(ui[0] * nrm[0] + ui[1] * nrm[1] + ui[2] * nrm[2]);
+      const double fm = -F + d.eta_n * vrn;
+      const double f[3] = {fm * nrm[0], fm * nrm[1], fm * nrm[2]};
+      add(id, f);
+    }
+  }
+  // particle pairs from the neighbouring bins
+  int ox[3], oy[3], oz[3];
+  const int bx = bin_coord(xi[0], 0, d), by = bin_coord(xi[1], 1, d);
+  const int bz = d.three_d ? bin_coord(xi[2], 2, d) : 0;
+  const int nxo = axis_offsets(bx, 0, d, ox);
+  const int nyo = axis_offsets(by, 1, d, oy);
+  int nzo = 1;
+  oz[0] = 0;
+  if (d.three_d) nzo = axis_offsets(bz, 2, d, oz);
+  for (int kz = 0; kz < nzo; ++kz)
+    for (int ky = 0; ky < nyo; ++ky)
+      for (int kx = 0; kx < nxo; ++kx) {
+        const int b = ox[kx] + d.nbin[0] * (oy[ky] + d.nbin[1] * oz[kz]);
+        int m = d.bin_count[b];
+        if (m > d.bin_cap) m = d.bin_cap;
+        for (int t = 0; t < m; ++t) {
+          const int j = d.bin_list[(size_t)b * d.bin_cap + t];
+          if (j == i) continue;
+          double dv[3] = {0, 0, 0}, d2 = 0.0;
+          for (int a = 0; a < D; ++a) {
+            dv[a] = min_img(x[3 * j + a] - xi[a], d.periodic[a], d.L[a]);
+            d2 += dv[a] * dv[a];
+          }
+          const double dist = sqrt(d2);
+          const double rj = r[j];
+          const double delta = ri + rj - dist;
+          if (delta < 0.0 && !was_in_contact(prev, pn, j)) continue;
+          const double Reff = 1.0 / (1.0 / ri + 1.0 / rj);
+          double dC;
+          const double F = jkr_force(Reff, d.E, d.gamma, delta, &dC);
+          if (delta >= 0.0 || delta > -dC) {
+            double vrn = 0.0, nrm[3];
+            for (int a = 0; a < 3; ++a) nrm[a] = dv[a] / dist;
+            for (int a = 0; a < D; ++a) vrn += (u[3 * j + a] - ui[a]) * nrm[a];
+            const double fm = -F + d.eta_n * vrn;
+            const double f[3] = {fm * nrm[0], fm * nrm[1], fm * nrm[2]};
+            add(j, f);
+          }
+        }
+      }
+  if (overflow) atomicOr(d.err, ERR_CONTACTS);
+  double fs[3] = {0, 0, 0};
+  for (int k = 0; k < cnt; ++k)
+    for (int a = 0; a < 3; ++a) fs[a] += cf[k][a];
+  for (int a = 0; a < 3; ++a) d.fc[3 * i + a] = fs[a];
+  d.next_n[i] = cnt;
+  for (int k = 0; k < cnt; ++k) d.next_id[(size_t)i * d.max_contacts + k] = cid[k];
+}
+
+struct IntArgs {
+  int n, three_d;
+  int L[3], periodic[3];
+  double dt;
+  double rho_p, rho_f;
+  double g[3];
+  int kinematic;
+  int wrap;
+};
+
+__global__ void k_dem_integrate(IntArgs p, double* x, double* u, double* w, const double* r,
+                                const double* Ff, const double* Tf, const double* Fc) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const int D = p.three_d ? 3 : 2;
+  if (!p.kinematic) {
+    const double ri = r[i];
+    const double V = p.three_d ? (4.0 / 3.0) * M_PI * ri * ri * ri : M_PI * ri * ri;
+    const double m = p.rho_p * V;
+    const double I = p.three_d ? 0.4 * m * ri * ri : 0.5 * m * ri * ri;
+    for (int a = 0; a < D; ++a) {
+      const double G = (p.rho_p - p.rho_f) * V * p.g[a];
+      u[3 * i + a] += p.dt * (Ff[3 * i + a] + Fc[3 * i + a] + G) / m;
+      x[3 * i + a] += p.dt * u[3 * i + a];
+    }
+    if (p.three_d) {
+      for (int a = 0; a < 3; ++a) w[3 * i + a] += p.dt * Tf[3 * i + a] / I;
+    } else {
+      w[3 * i + 2] += p.dt * Tf[3 * i + 2] / I;
+    }
+  } else {
+    for (int a = 0; a < D; ++a) x[3 * i + a] += p.dt * u[3 * i + a];
+  }
+  if (p.wrap) {
+    for (int a = 0; a < D; ++a) {
+      if (!p.periodic[a]) continue;
+      const double L = (double)p.L[a];
+      if (x[3 * i + a] >= L) x[3 * i + a] -= L;
+      else if (x[3 * i + a] < 0.0) x[3 * i + a] += L;
+    }
+  }
+}
+
+int launch_dem_reset(psclbm_ctx* c) {
+  if (c->cfg.max_particles <= 0) return PSCLBM_OK;
+  return hip_ok(hipMemsetAsync(c->contact_n[c->contact_cur], 0,
+                               sizeof(int) * (size_t)c->cfg.max_particles, c->stream));
+}
+
+int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, double* u, double* w,
+                    const double* r, int n, const double* F, const double* T) {
+  const int three_d = c->geom.q == 19;
+  const int L[3] = {c->geom.nx, c->geom.ny, c->geom.nz};
+  const double dts = prm->dt / prm->n_sub;
+  IntArgs ia;
+  ia.n = n;
+  ia.three_d = three_d;
+  for (int a = 0; a < 3; ++a) {
+    ia.L[a] = L[a];
+    ia.periodic[a] = c->geom.periodic[a];
+    ia.g[a] = prm->g[a];
+  }
+  ia.dt = dts;
+  ia.rho_p = prm->rho_p;
+  ia.rho_f = prm->rho_f;
+  ia.kinematic = prm->kinematic ? 1 : 0;
+  const int blocks = (n + 127) / 128;
+  if (prm->kinematic) {
+    for (int s = 0; s < prm->n_sub; ++s) {
+      ia.wrap = s == prm->n_sub - 1;
+      k_dem_integrate<<<blocks, 128, 0, c->stream>>>(ia, x, u, w, r, F, T, c->fcontact);
+      int rc = hip_ok(hipGetLastError());
+      if (rc) return rc;
+    }
+    return PSCLBM_OK;
+  }
+  // the contact reach delta_C of the largest pair must fit in the bin margin
+  const double E = 1.0 / (2.0 * (1.0 - prm->poisson * prm->poisson) / prm->E_p);
+  {
+    const double Rm = c->cfg.max_radius;  // wall contact: R = r
+    const double a0 = std::cbrt(9.0 * M_PI * prm->gamma * Rm * Rm / E);
+    const double dC = a0 * a0 / (2.0 * std::cbrt(6.0) * Rm);
+    if (!(dC < 1.0)) return PSCLBM_EINVAL;
+  }
+  DemArgs d;
+  d.n = n;
+  d.three_d = three_d;
+  for (int a = 0; a < 3; ++a) {
+    d.L[a] = L[a];
+    d.periodic[a] = c->geom.periodic[a];
+    d.nbin[a] = c->nbin[a];
+    d.bin_size[a] = c->bin_size[a];
+  }
+  d.bin_cap = c->bin_cap;
+  d.bin_count = c->bin_count;
+  d.bin_list = c->bin_list;
+  d.max_contacts = c->cfg.max_contacts;
+  d.fc = c->fcontact;
+  d.E = E;
+  d.gamma = prm->gamma;
+  d.eta_n = prm->eta_n;
+  d.err = c->err;
+  const int nbins = c->nbin[0] * c->nbin[1] * c->nbin[2];
+  for (int s = 0; s < prm->n_sub; ++s) {
+    ia.wrap = s == prm->n_sub - 1;  // positions wrap once, after the last sub-step
+    d.prev_n = c->contact_n[c->contact_cur];
+    d.prev_id = c->contact_id[c->contact_cur];
+    d.next_n = c->contact_n[c->contact_cur ^ 1];
+    d.next_id = c->contact_id[c->contact_cur ^ 1];
+    k_dem_clear<<<(nbins + 255) / 256 < 1024 ? (nbins + 255) / 256 : 1024, 256, 0, c->stream>>>(
+        c->bin_count, nbins);
+    k_dem_bin<<<blocks, 128, 0, c->stream>>>(d, x);
+    k_dem_contacts<<<blocks, 128, 0, c->stream>>>(d, x, u, r);
+    k_dem_integrate<<<blocks, 128, 0, c->stream>>>(ia, x, u, w, r, F, T, c->fcontact);
+    int rc = hip_ok(hipGetLastError());
+    if (rc) return rc;
+    c->contact_cur ^= 1;
+  }
+  return PSCLBM_OK;
+}
+
+}  // namespace psclbm

@@ -1,0 +1,1023 @@
+// Lattice kernels of the gfx950 PSC-LBM library.
+//
+// Storage: one structure-of-arrays distribution array A[i][n] (n = x + nx*(y +
+// ny*z)) updated in place with the two-parity "AA" streaming pattern, so each
+// time step reads and writes every population exactly once:
+//   even step (parity 0): cell n reads A[i][n] and writes its post-collision
+//                          f*_i to A[opp(i)][n];
+//   odd step  (parity 1): cell n reads f_i from A[opp(i)][n - e_i] and writes
+//                          f*_i to A[i][n + e_i].
+// A link that leaves the domain through a non-periodic face is reflected into
+// the cell itself (halfway bounce-back, Eq. 6), which in both parities lands
+// on the location the same cell reads back next step; every location is read
+// and written by one thread per step, so the update needs no second copy.
+//
+// Per-cell physics (Sec. 2.1-2.3): moments with the half-force shift (Eq. 5),
+// BGK with Guo forcing (Eqs. 2-4), and in cells covered by particles the
+// modified partially-saturated-cell collision (Eqs. 10, 12, 13) with the
+// per-particle momentum exchange of Eq. 14.  The solid fractions (Eqs. 15-19,
+// Table 1) are evaluated per cell from the workgroup tile's particle list held
+// in LDS, so no per-cell solid data is stored in HBM.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "common.hpp"
+
+namespace psclbm {
+
+static_assert(Lattice<9>::opp(1) == 3 && Lattice<9>::opp(6) == 8 && Lattice<9>::opp(7) == 5,
+              "D2Q9 opposite table");
+
+template <int Q>
+__host__ __device__ constexpr bool check_lattice() {
+  for (int i = 0; i < Q; ++i) {
+    const int o = Lattice<Q>::opp(i);
+    if (Lattice<Q>::ex(o) != -Lattice<Q>::ex(i) || Lattice<Q>::ey(o) != -Lattice<Q>::ey(i) ||
+        Lattice<Q>::ez(o) != -Lattice<Q>::ez(i))
+      return false;
+  }
+  return true;
+}
+static_assert(check_lattice<9>() && check_lattice<19>(), "opposite directions");
+
+// ---------------------------------------------------------------------------
+// Storage conversion: deviation g_i = f_i - w_i rho0 in the compute type.
+// ---------------------------------------------------------------------------
+template <int PREC, int Q>
+struct Store {
+  using S = typename Form<PREC>::S;
+  using C = typename Form<PREC>::C;
+  __device__ static C load(const S* a, size_t idx, int i, double rho0) {
+    if constexpr (PREC == PSCLBM_FP64) {
+      return a[idx] - Lattice<Q>::w(i) * rho0;
+    } else if constexpr (PREC == PSCLBM_FP32) {
+      return a[idx];
+    } else {
+      return static_cast<float>(a[idx]) * static_cast<float>(Lattice<Q>::w(i));
+    }
+  }
+  // Stores g and returns the deviation actually held by memory (for the mass sum).
+  __device__ static double store(S* a, size_t idx, int i, C g, double rho0) {
+    if constexpr (PREC == PSCLBM_FP64) {
+      const double f = Lattice<Q>::w(i) * rho0 + g;
+      a[idx] = f;
+      return f - Lattice<Q>::w(i) * rho0;
+    } else if constexpr (PREC == PSCLBM_FP32) {
+      a[idx] = g;
+      return static_cast<double>(g);
+    } else {
+      const _Float16 h = static_cast<_Float16>(g * static_cast<float>(1.0 / Lattice<Q>::w(i)));
+      a[idx] = h;
+      return static_cast<double>(static_cast<float>(h)) * Lattice<Q>::w(i);
+    }
+  }
+  // Exact canonical FP64 value of stored population i.
+  __device__ static double to_f64(const S* a, size_t idx, int i, double rho0) {
+    if constexpr (PREC == PSCLBM_FP64) {
+      return a[idx];
+    } else if constexpr (PREC == PSCLBM_FP32) {
+      return Lattice<Q>::w(i) * rho0 + static_cast<double>(a[idx]);
+    } else {
+      return Lattice<Q>::w(i) * rho0 +
+             static_cast<double>(static_cast<float>(a[idx])) * Lattice<Q>::w(i);
+    }
+  }
+  __device__ static void from_f64(S* a, size_t idx, int i, double f, double rho0) {
+    const double g = f - Lattice<Q>::w(i) * rho0;
+    if constexpr (PREC == PSCLBM_FP64) {
+      a[idx] = f;
+    } else if constexpr (PREC == PSCLBM_FP32) {
+      a[idx] = static_cast<float>(g);
+    } else {
+      a[idx] = static_cast<_Float16>(static_cast<float>(g / Lattice<Q>::w(i)));
+    }
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Neighbour addressing with periodic wrap; returns false when the link leaves
+// through a non-periodic face (and accumulates that face's wall velocity).
+// ---------------------------------------------------------------------------
+struct Cell {
+  int x, y, z;
+  long long n;
+};
+
+__device__ inline bool neighbour(const Geom& g, const Cell& c, int dx, int dy, int dz,
+                                 long long& m, double* uw) {
+  int p[3] = {c.x + dx, c.y + dy, c.z + dz};
+  const int L[3] = {g.nx, g.ny, g.nz};
+  bool inside = true;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (p[a] < 0 || p[a] >= L[a]) {
+      if (g.periodic[a]) {
+        p[a] += p[a] < 0 ? L[a] : -L[a];
+      } else {
+        inside = false;
+        if (uw) {
+          const int face = 2 * a + (p[a] < 0 ? 0 : 1);
+          if (g.face[face] == PSCLBM_MOVING_WALL) {
+            uw[0] += g.face_u[face][0];
+            uw[1] += g.face_u[face][1];
+            uw[2] += g.face_u[face][2];
+          }
+        }
+      }
+    }
+  }
+  m = p[0] + (long long)g.nx * (p[1] + (long long)g.ny * p[2]);
+  return inside;
+}
+
+// Canonical population i of cell c at streaming parity par: its storage index.
+template <int Q>
+__device__ inline size_t canonical_index(const Geom& g, const Cell& c, int i, int par) {
+  if (par == 0) return (size_t)i * g.N + c.n;
+  long long m;
+  if (neighbour(g, c, -Lattice<Q>::ex(i), -Lattice<Q>::ey(i), -Lattice<Q>::ez(i), m, nullptr))
+    return (size_t)Lattice<Q>::opp(i) * g.N + m;
+  return (size_t)i * g.N + c.n;
+}
+
+__device__ inline Cell cell_of(const Geom& g, long long n) {
+  Cell c;
+  c.n = n;
+  c.x = (int)(n % g.nx);
+  long long r = n / g.nx;
+  c.y = (int)(r % g.ny);
+  c.z = (int)(r / g.ny);
+  return c;
+}
+
+// Minimum-image separation along one axis.
+__device__ inline double min_image(double d, int periodic, int L) {
+  if (periodic) {
+    if (d > 0.5 * L) d -= L;
+    else if (d < -0.5 * L) d += L;
+  }
+  return d;
+}
+
+// ---------------------------------------------------------------------------
+// Solid fraction of one (cell, particle) pair, Table 1 Steps 2-4 with
+// Eq. 15/18: eps = V_a(r) + 1/2 - d inside the shell r +- h.
+// ---------------------------------------------------------------------------
+__device__ inline double pair_eps(double d, double r, double cs, double h) {
+  double e;
+  if (d >= r + h) e = 0.0;
+  else if (d <= r - h) e = 1.0;
+  else e = cs - d;
+  if (e <= 0.0) e = 0.0;
+  if (e >= 1.0) e = 1.0;
+  return e;
+}
+
+// LDS image of a tile's particle list.
+struct LdsEntry {
+  double x, y, z;
+  double r, cs;
+  int id;
+  int pad;
+};
+
+// Slots of one cell: up to KSLOTS particles with eps > 0, ascending id.
+struct Slots {
+  int n;
+  int id[KSLOTS];
+  int e[KSLOTS];  // index in the tile list
+  double eps[KSLOTS];
+};
+
+template <int D>
+__device__ inline void collect_slots(const Geom& g, const Cell& c, const LdsEntry* lds, int cnt,
+                                     double h, Slots& s, unsigned* err) {
+  s.n = 0;
+  for (int e = 0; e < cnt; ++e) {
+    const LdsEntry& P = lds[e];
+    const double dx = min_image((double)c.x - P.x, g.periodic[0], g.nx);
+    const double dy = min_image((double)c.y - P.y, g.periodic[1], g.ny);
+    double d2 = dx * dx + dy * dy;
+    if constexpr (D == 3) {
+      const double dz = min_image((double)c.z - P.z, g.periodic[2], g.nz);
+      d2 += dz * dz;
+    }
+    const double rh = P.r + h;
+    if (!(d2 < rh * rh)) continue;
+    const double eps = pair_eps(sqrt(d2), P.r, P.cs, h);
+    if (!(eps > 0.0)) continue;
+    if (s.n >= KSLOTS) {
+      atomicOr(err, ERR_SLOTS);
+      continue;
+    }
+    // insert keeping ascending particle ids (ids in a list are distinct)
+    int pos = 0;
+#pragma unroll
+    for (int j = 0; j < KSLOTS; ++j)
+      if (j < s.n && s.id[j] < P.id) pos = j + 1;
+#pragma unroll
+    for (int j = KSLOTS - 1; j > 0; --j)
+      if (j > pos && j <= s.n) {
+        s.id[j] = s.id[j - 1];
+        s.e[j] = s.e[j - 1];
+        s.eps[j] = s.eps[j - 1];
+      }
+#pragma unroll
+    for (int j = 0; j < KSLOTS; ++j)
+      if (j == pos) {
+        s.id[j] = P.id;
+        s.e[j] = e;
+        s.eps[j] = eps;
+      }
+    s.n += 1;
+  }
+}
+
+// Loads the tile's particle list into LDS; returns the list length (uniform).
+__device__ inline int load_tile_list(const int* tile_count, const int* tile_list, int cap,
+                                     const PSnap* snap, int tile, LdsEntry* lds, double* acc,
+                                     int np) {
+  int cnt = np > 0 ? tile_count[tile] : 0;
+  if (cnt > cap) cnt = cap;
+  for (int e = threadIdx.x; e < cnt; e += BLOCK) {
+    const int id = tile_list[(size_t)tile * cap + e];
+    const PSnap& P = snap[id];
+    lds[e].x = P.x[0];
+    lds[e].y = P.x[1];
+    lds[e].z = P.x[2];
+    lds[e].r = P.r;
+    lds[e].cs = P.cs;
+    lds[e].id = id;
+    if (acc) {
+#pragma unroll
+      for (int a = 0; a < 6; ++a) acc[6 * e + a] = 0.0;
+    }
+  }
+  return cnt;
+}
+
+__device__ inline void tile_origin(const Geom& g, int tile, int& x0, int& y0, int& z0) {
+  const int tx = tile % g.ntx;
+  const int r = tile / g.ntx;
+  const int ty = r % g.nty;
+  const int tz = r / g.nty;
+  x0 = tx * TX;
+  y0 = ty * TY;
+  z0 = tz * TZ;
+}
+
+// Workgroup -> tile map.  The dispatcher deals consecutive workgroups round-
+// robin to the 8 XCDs; this bijection gives each XCD one contiguous run of
+// tiles so that the halo lines shared by neighbouring tiles stay in one L2.
+__device__ inline int xcd_tile(int b, int nb) {
+  constexpr int NX = 8;
+  const int per = nb / NX, rem = nb % NX;
+  const int xcd = b % NX, k = b / NX;
+  return xcd * per + (xcd < rem ? xcd : rem) + k;
+}
+
+// ---------------------------------------------------------------------------
+// The fused collide-stream step.
+// ---------------------------------------------------------------------------
+template <int Q, int PREC, int PAR>
+__global__ void __launch_bounds__(BLOCK) k_step(StepArgs a) {
+  using L = Lattice<Q>;
+  using C = typename Form<PREC>::C;
+  using S = typename Form<PREC>::S;
+  using ST = Store<PREC, Q>;
+  constexpr int D = L::D;
+  extern __shared__ double smem_d[];
+  const Geom& g = a.g;
+  S* A = static_cast<S*>(a.f);
+  const int nb = gridDim.x;
+  const int tile = xcd_tile(blockIdx.x, nb);
+
+  // particle list of the tile (LDS) and its force accumulators
+  LdsEntry* lds = reinterpret_cast<LdsEntry*>(smem_d);
+  double* acc = reinterpret_cast<double*>(lds + a.cap);
+  const int cnt = load_tile_list(a.tile_count, a.tile_list, a.cap, a.snap, tile, lds, acc, a.np);
+  if (cnt > 0) __syncthreads();
+
+  int x0, y0, z0;
+  tile_origin(g, tile, x0, y0, z0);
+  const int lx = threadIdx.x % TX;
+  const int ly = (threadIdx.x / TX) % TY;
+  const int lz = threadIdx.x / (TX * TY);
+  Cell c;
+  c.x = x0 + lx;
+  c.y = y0 + ly;
+  c.z = z0 + lz;
+  const bool active = c.x < g.nx && c.y < g.ny && c.z < g.nz;
+  c.n = c.x + (long long)g.nx * (c.y + (long long)g.ny * c.z);
+  double mass_dev = 0.0;
+
+  if (active) {
+    const double rho0 = g.rho0;
+    // ---- load f (as deviations g_i = f_i - w_i rho0) ----
+    C gi[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      size_t idx;
+      if constexpr (PAR == 0) {
+        idx = (size_t)i * g.N + c.n;
+      } else {
+        long long m;
+        if (neighbour(g, c, -L::ex(i), -L::ey(i), -L::ez(i), m, nullptr))
+          idx = (size_t)L::opp(i) * g.N + m;
+        else
+          idx = (size_t)i * g.N + c.n;
+      }
+      gi[i] = ST::load(A, idx, i, rho0);
+    }
+    const C F[3] = {(C)a.force[0], (C)a.force[1], (C)a.force[2]};
+
+    // ---- inlet / outlet layers: reset to an equilibrium before collision ----
+    if (a.has_open) {
+      int kind = -1;
+      const double* uo = nullptr;
+      const int pc[3] = {c.x, c.y, c.z};
+      const int Ld[3] = {g.nx, g.ny, g.nz};
+      // outlets first, then inlets (an inlet wins on a shared corner)
+      for (int face = 0; face < 6; ++face) {
+        const int ax = face / 2;
+        const bool on = (face % 2 == 0) ? pc[ax] == 0 : pc[ax] == Ld[ax] - 1;
+        if (!on || g.face[face] != PSCLBM_OUTLET_EQ) continue;
+        const int u1 = ax == 0 ? 1 : 0, u2 = ax == 2 ? 1 : 2;
+        const long long k = pc[u1] + (long long)Ld[u1] * pc[u2];
+        uo = a.outlet_u + ((size_t)face * a.face_stride + k) * 3;
+        kind = PSCLBM_OUTLET_EQ;
+      }
+      for (int face = 0; face < 6; ++face) {
+        const int ax = face / 2;
+        const bool on = (face % 2 == 0) ? pc[ax] == 0 : pc[ax] == Ld[ax] - 1;
+        if (!on || g.face[face] != PSCLBM_INLET_EQ) continue;
+        uo = g.face_u[face];
+        kind = PSCLBM_INLET_EQ;
+      }
+      if (kind >= 0) {
+        const C ub[3] = {(C)uo[0], (C)uo[1], (C)uo[2]};
+        const C uu = ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          const C eu = L::ex(i) * ub[0] + L::ey(i) * ub[1] + L::ez(i) * ub[2];
+          gi[i] = (C)L::w(i) * (C)rho0 * ((C)3 * eu + (C)4.5 * eu * eu - (C)1.5 * uu);
+        }
+      }
+    }
+
+    // ---- moments (Eq. 5) ----
+    C drho = 0, jx = 0, jy = 0, jz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      drho += gi[i];
+      if (L::ex(i)) jx += L::ex(i) * gi[i];
+      if (L::ey(i)) jy += L::ey(i) * gi[i];
+      if (L::ez(i)) jz += L::ez(i) * gi[i];
+    }
+    const C rho = (C)rho0 + drho;
+    const C inv_rho = (C)1 / rho;
+    const C ux = (jx + (C)0.5 * F[0]) * inv_rho;
+    const C uy = (jy + (C)0.5 * F[1]) * inv_rho;
+    const C uz = (jz + (C)0.5 * F[2]) * inv_rho;
+    const C uu = ux * ux + uy * uy + uz * uz;
+
+    // ---- non-equilibrium parts (Eq. 3) and Guo forcing (Eq. 4) ----
+    const C tau = (C)a.tau;
+    const C omega = (C)1 / tau;
+    const C kguo = (C)1 - (C)0.5 * omega;
+    const C uF = ux * F[0] + uy * F[1] + uz * F[2];
+    C fneq[Q], Fi[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const C eu = L::ex(i) * ux + L::ey(i) * uy + L::ez(i) * uz;
+      const C eF = L::ex(i) * F[0] + L::ey(i) * F[1] + L::ez(i) * F[2];
+      const C wi = (C)L::w(i);
+      const C geq = wi * (drho + rho * ((C)3 * eu + (C)4.5 * eu * eu - (C)1.5 * uu));
+      fneq[i] = gi[i] - geq;
+      Fi[i] = kguo * wi * ((C)3 * (eF - uF) + (C)9 * eu * eF);
+    }
+
+    // ---- solid fractions of the covering particles (Table 1) ----
+    Slots s;
+    s.n = 0;
+    if (cnt > 0) collect_slots<D>(g, c, lds, cnt, a.h, s, a.err);
+
+    C gout[Q];
+    if (s.n == 0) {
+      // pure fluid: BGK + Guo (Eq. 2)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) gout[i] = gi[i] - omega * fneq[i] + Fi[i];
+    } else {
+      // ---- weights (Eq. 13 with Table 1 Step 5) ----
+      double S_ = 0.0;
+#pragma unroll
+      for (int k = 0; k < KSLOTS; ++k)
+        if (k < s.n) S_ += s.eps[k];
+      const double tm = a.tau - 0.5;
+      const double en = S_ < 1.0 ? S_ : 1.0;
+      const double den = (1.0 - en) + tm;
+      const C Bn = (C)(en * tm / den);
+      C Bs[KSLOTS];
+      C usx[KSLOTS], usy[KSLOTS], usz[KSLOTS];
+      double rx[KSLOTS], ry[KSLOTS], rz[KSLOTS];
+#pragma unroll
+      for (int k = 0; k < KSLOTS; ++k) {
+        Bs[k] = 0;
+        usx[k] = usy[k] = usz[k] = 0;
+        rx[k] = ry[k] = rz[k] = 0.0;
+        if (k >= s.n) continue;
+        Bs[k] = (C)(S_ <= 1.0 ? s.eps[k] * tm / den : s.eps[k] / S_);
+        const PSnap& P = a.snap[s.id[k]];
+        rx[k] = min_image((double)c.x - P.x[0], g.periodic[0], g.nx);
+        ry[k] = min_image((double)c.y - P.x[1], g.periodic[1], g.ny);
+        rz[k] = D == 3 ? min_image((double)c.z - P.x[2], g.periodic[2], g.nz) : 0.0;
+        // rigid-body velocity at the cell centre
+        usx[k] = (C)(P.u[0] + P.w[1] * rz[k] - P.w[2] * ry[k]);
+        usy[k] = (C)(P.u[1] + P.w[2] * rx[k] - P.w[0] * rz[k]);
+        usz[k] = (C)(P.u[2] + P.w[0] * ry[k] - P.w[1] * rx[k]);
+      }
+      // Eq. 12 with Eq. 10: sum_s B_s Omega^s_i =
+      //   B_n (fneq_{-i} - fneq_i) + rho w_i sum_s B_s [feq_i(u_s) - feq_i(u)] / (rho w_i)
+      const C omB = (C)1 - Bn;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const C eu = L::ex(i) * ux + L::ey(i) * uy + L::ez(i) * uz;
+        C dsum = 0;
+#pragma unroll
+        for (int k = 0; k < KSLOTS; ++k) {
+          if (k >= s.n) continue;
+          const C eus = L::ex(i) * usx[k] + L::ey(i) * usy[k] + L::ez(i) * usz[k];
+          const C us2 = usx[k] * usx[k] + usy[k] * usy[k] + usz[k] * usz[k];
+          dsum += Bs[k] * ((C)3 * (eus - eu) + (C)4.5 * (eus * eus - eu * eu) -
+                           (C)1.5 * (us2 - uu));
+        }
+        gout[i] = gi[i] - omB * omega * fneq[i] + omB * Fi[i] +
+                  Bn * (fneq[L::opp(i)] - fneq[i]) + rho * (C)L::w(i) * dsum;
+      }
+      // ---- Eq. 14: m_s = B_s sum_i Omega^s_i e_i = B_s [rho (u_s - u) + F] ----
+#pragma unroll
+      for (int k = 0; k < KSLOTS; ++k) {
+        if (k >= s.n) continue;
+        const double mx = (double)(Bs[k] * (rho * (usx[k] - ux) + F[0]));
+        const double my = (double)(Bs[k] * (rho * (usy[k] - uy) + F[1]));
+        const double mz = D == 3 ? (double)(Bs[k] * (rho * (usz[k] - uz) + F[2])) : 0.0;
+        double* ac = acc + 6 * s.e[k];
+        atomicAdd(ac + 0, -mx);
+        atomicAdd(ac + 1, -my);
+        if constexpr (D == 3) {
+          atomicAdd(ac + 2, -mz);
+          atomicAdd(ac + 3, -(ry[k] * mz - rz[k] * my));
+          atomicAdd(ac + 4, -(rz[k] * mx - rx[k] * mz));
+        }
+        atomicAdd(ac + 5, -(rx[k] * my - ry[k] * mx));
+      }
+    }
+
+    // ---- stream (Eq. 1) with bounce-back (Eq. 6) ----
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      double uw[3] = {0.0, 0.0, 0.0};
+      long long m;
+      const bool in =
+          neighbour(g, c, L::ex(i), L::ey(i), L::ez(i), m, uw);
+      C v = gout[i];
+      size_t idx;
+      if (in) {
+        idx = PAR == 0 ? (size_t)L::opp(i) * g.N + c.n : (size_t)i * g.N + m;
+      } else {
+        // moving wall: -2 w_i rho (e_i . u_w) / c_s^2
+        const double eu = L::ex(i) * uw[0] + L::ey(i) * uw[1] + L::ez(i) * uw[2];
+        if (eu != 0.0) v -= (C)(6.0 * L::w(i) * eu) * rho;
+        idx = (size_t)L::opp(i) * g.N + c.n;
+      }
+      mass_dev += ST::store(A, idx, i, v, rho0);
+    }
+  }
+
+  // ---- per-workgroup FP64 mass partial (sum of the stored deviations) ----
+  for (int off = 32; off > 0; off >>= 1) mass_dev += __shfl_down(mass_dev, off, 64);
+  __shared__ double wsum[BLOCK / 64];
+  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = mass_dev;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int k = 0; k < BLOCK / 64; ++k) t += wsum[k];
+    a.mass_part[blockIdx.x] = t;
+  }
+
+  // ---- flush the tile's force / torque partials (FP64) ----
+  if (cnt > 0) {
+    for (int e = threadIdx.x; e < cnt; e += BLOCK) {
+      const double* ac = acc + 6 * e;
+      bool any = false;
+#pragma unroll
+      for (int k = 0; k < 6; ++k) any |= ac[k] != 0.0;
+      if (!any) continue;
+      double* dst = a.facc + 6 * (size_t)lds[e].id;
+#pragma unroll
+      for (int k = 0; k < 6; ++k)
+        if (ac[k] != 0.0) atomicAdd(dst + k, ac[k]);
+    }
+  }
+  // ---- clear the other force buffer for the next step ----
+  if (a.np > 0) {
+    const size_t tot = 6 * (size_t)a.np;
+    for (size_t k = (size_t)blockIdx.x * BLOCK + threadIdx.x; k < tot; k += (size_t)nb * BLOCK)
+      a.fzero[k] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Outlet layers: velocity (Eq. 5) of the interior neighbour of every outlet
+// cell at the current time level, read before the step kernel runs.
+// ---------------------------------------------------------------------------
+template <int Q, int PREC>
+__global__ void k_outlet_velocity(Geom g, const void* f, int par, double fx, double fy,
+                                  double fz, double* out, long long stride) {
+  using L = Lattice<Q>;
+  using ST = Store<PREC, Q>;
+  using S = typename Form<PREC>::S;
+  const int face = blockIdx.y;
+  if (g.face[face] != PSCLBM_OUTLET_EQ) return;
+  const int ax = face / 2;
+  const int u1 = ax == 0 ? 1 : 0, u2 = ax == 2 ? 1 : 2;
+  const int Ld[3] = {g.nx, g.ny, g.nz};
+  const long long cells = (long long)Ld[u1] * Ld[u2];
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < cells;
+       k += (long long)gridDim.x * blockDim.x) {
+    int p[3];
+    p[u1] = (int)(k % Ld[u1]);
+    p[u2] = (int)(k / Ld[u1]);
+    p[ax] = (face % 2 == 0) ? 1 : Ld[ax] - 2;
+    Cell c;
+    c.x = p[0];
+    c.y = p[1];
+    c.z = p[2];
+    c.n = c.x + (long long)g.nx * (c.y + (long long)g.ny * c.z);
+    double rho = 0, j[3] = {0, 0, 0};
+    for (int i = 0; i < Q; ++i) {
+      const double fi = ST::to_f64(static_cast<const S*>(f), canonical_index<Q>(g, c, i, par), i,
+                                   g.rho0);
+      rho += fi;
+      j[0] += L::ex(i) * fi;
+      j[1] += L::ey(i) * fi;
+      j[2] += L::ez(i) * fi;
+    }
+    double* o = out + ((size_t)face * stride + k) * 3;
+    o[0] = (j[0] + 0.5 * fx) / rho;
+    o[1] = (j[1] + 0.5 * fy) / rho;
+    o[2] = (j[2] + 0.5 * fz) / rho;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// State I/O
+// ---------------------------------------------------------------------------
+template <int Q, int PREC>
+__global__ void k_set_equilibrium(Geom g, void* f, const double* rho, const double* u) {
+  using L = Lattice<Q>;
+  using S = typename Form<PREC>::S;
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < g.N;
+       n += (long long)gridDim.x * blockDim.x) {
+    const double r = rho ? rho[n] : g.rho0;
+    double ub[3] = {0, 0, 0};
+    if (u) {
+      ub[0] = u[3 * n];
+      ub[1] = u[3 * n + 1];
+      ub[2] = u[3 * n + 2];
+    }
+    const double uu = ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2];
+    for (int i = 0; i < Q; ++i) {
+      const double eu = L::ex(i) * ub[0] + L::ey(i) * ub[1] + L::ez(i) * ub[2];
+      const double fe = r * L::w(i) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+      Store<PREC, Q>::from_f64(static_cast<S*>(f), (size_t)i * g.N + n, i, fe, g.rho0);
+    }
+  }
+}
+
+template <int Q, int PREC>
+__global__ void k_set_f(Geom g, void* f, const double* src) {
+  using S = typename Form<PREC>::S;
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < g.N;
+       n += (long long)gridDim.x * blockDim.x)
+    for (int i = 0; i < Q; ++i)
+      Store<PREC, Q>::from_f64(static_cast<S*>(f), (size_t)i * g.N + n, i,
+                               src[(size_t)i * g.N + n], g.rho0);
+}
+
+template <int Q, int PREC>
+__global__ void k_get_f(Geom g, const void* f, int par, double* dst, double* rho, double* u,
+                        double fx, double fy, double fz) {
+  using L = Lattice<Q>;
+  using S = typename Form<PREC>::S;
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < g.N;
+       n += (long long)gridDim.x * blockDim.x) {
+    const Cell c = cell_of(g, n);
+    double m = 0, j[3] = {0, 0, 0};
+    for (int i = 0; i < Q; ++i) {
+      const double fi = Store<PREC, Q>::to_f64(static_cast<const S*>(f),
+                                               canonical_index<Q>(g, c, i, par), i, g.rho0);
+      if (dst) dst[(size_t)i * g.N + n] = fi;
+      m += fi;
+      j[0] += L::ex(i) * fi;
+      j[1] += L::ey(i) * fi;
+      j[2] += L::ez(i) * fi;
+    }
+    if (rho) rho[n] = m;
+    if (u) {
+      u[3 * n] = (j[0] + 0.5 * fx) / m;
+      u[3 * n + 1] = (j[1] + 0.5 * fy) / m;
+      u[3 * n + 2] = (j[2] + 0.5 * fz) / m;
+    }
+  }
+}
+
+// Mass of the current state, per workgroup (sum of stored deviations).
+template <int Q, int PREC>
+__global__ void __launch_bounds__(256) k_mass_direct(Geom g, const void* f, double* part) {
+  using S = typename Form<PREC>::S;
+  double t = 0.0;
+  for (long long n = (long long)blockIdx.x * blockDim.x + threadIdx.x; n < g.N;
+       n += (long long)gridDim.x * blockDim.x)
+    for (int i = 0; i < Q; ++i)
+      t += Store<PREC, Q>::to_f64(static_cast<const S*>(f), (size_t)i * g.N + n, i, g.rho0) -
+           Lattice<Q>::w(i) * g.rho0;
+  for (int off = 32; off > 0; off >>= 1) t += __shfl_down(t, off, 64);
+  __shared__ double ws[4];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = t;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// Deterministic two-level reduction of the per-workgroup mass partials.
+__global__ void k_reduce(const double* part, int n, double* out) {
+  __shared__ double s[256];
+  double t = 0.0;
+  for (int k = threadIdx.x; k < n; k += 256) t += part[k];
+  s[threadIdx.x] = t;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = s[0];
+}
+
+// ---------------------------------------------------------------------------
+// Rasterisation: particle snapshot, then tile binning (Table 1 Step 1).
+// ---------------------------------------------------------------------------
+__device__ inline double va2d(double r) {  // Eq. 19
+  const double s = sqrt(r * r - 0.25);
+  return 0.5 * s + r * r * atan(0.5 / s);
+}
+__device__ inline double va3d(double r) {  // Eq. 17 (principal-value arctangents)
+  const double r2 = r * r;
+  const double s = sqrt(r2 - 0.5);
+  return (1.0 / 12.0 - r2) * atan(0.5 * s / (0.5 - r2)) + s / 3.0 +
+         (r2 - 1.0 / 12.0) * atan(0.5 / s) - (4.0 / 3.0) * r2 * r * atan(0.25 / (r * s));
+}
+
+__global__ void k_snapshot(int n, int three_d, const double* x, const double* u, const double* w,
+                           const double* r, PSnap* snap, int* tile_count, int ntiles,
+                           double* f0, double* f1, unsigned* err) {
+  const long long tot = n > ntiles ? n : ntiles;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < tot;
+       k += (long long)gridDim.x * blockDim.x) {
+    if (k < ntiles) tile_count[k] = 0;
+    if (k < n) {
+      PSnap P;
+      for (int a = 0; a < 3; ++a) {
+        P.x[a] = x[3 * k + a];
+        P.u[a] = u[3 * k + a];
+        P.w[a] = w[3 * k + a];
+      }
+      if (!three_d) {
+        P.x[2] = 0.0;
+        P.u[2] = 0.0;
+        P.w[0] = P.w[1] = 0.0;
+      }
+      P.r = r[k];
+      P.pad = 0.0;
+      const bool ok = P.r * P.r > (three_d ? 0.5 : 0.25) && P.r < 1e300;
+      if (!ok) {
+        atomicOr(err, ERR_RADIUS);
+        P.cs = -1e300;  // never covers a cell
+        P.r = 0.0;
+      } else {
+        P.cs = (three_d ? va3d(P.r) : va2d(P.r)) + 0.5;
+      }
+      snap[k] = P;
+      for (int a = 0; a < 6; ++a) {
+        f0[6 * k + a] = 0.0;
+        f1[6 * k + a] = 0.0;
+      }
+    }
+  }
+}
+
+// Tiles touched along one axis by the cell range [lo, hi]: emits at most two
+// runs of tile indices (the second after a periodic wrap).
+struct AxisRuns {
+  int a0, a1, b0, b1;  // runs [a0, a1] and [b0, b1] (b0 > b1 when absent)
+};
+
+__device__ inline AxisRuns axis_runs(int lo, int hi, int L, int T, int periodic) {
+  AxisRuns r;
+  r.b0 = 1;
+  r.b1 = 0;
+  const int nt = (L + T - 1) / T;
+  if (!periodic) {
+    if (lo < 0) lo = 0;
+    if (hi > L - 1) hi = L - 1;
+    if (lo > hi) {
+      r.a0 = 1;
+      r.a1 = 0;
+      return r;
+    }
+    r.a0 = lo / T;
+    r.a1 = hi / T;
+    return r;
+  }
+  if (hi - lo + 1 >= L) {
+    r.a0 = 0;
+    r.a1 = nt - 1;
+    return r;
+  }
+  const int wl = ((lo % L) + L) % L;
+  const int wh = ((hi % L) + L) % L;
+  if (wl <= wh) {
+    r.a0 = wl / T;
+    r.a1 = wh / T;
+  } else {
+    const int t0 = wl / T, t1 = wh / T;
+    if (t1 >= t0) {
+      r.a0 = 0;
+      r.a1 = nt - 1;
+    } else {
+      r.a0 = t0;
+      r.a1 = nt - 1;
+      r.b0 = 0;
+      r.b1 = t1;
+    }
+  }
+  return r;
+}
+
+__global__ void k_bin(Geom g, int n, double h, const PSnap* snap, int* tile_count, int* tile_list,
+                      int cap, unsigned* err) {
+  const int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= n) return;
+  const PSnap P = snap[s];
+  if (!(P.r > 0.0)) return;
+  const double R = P.r + h;
+  const int L[3] = {g.nx, g.ny, g.nz};
+  const int T[3] = {TX, TY, TZ};
+  AxisRuns runs[3];
+  for (int a = 0; a < 3; ++a) {
+    int lo, hi;
+    if (a == 2 && g.q == 9) {
+      lo = hi = 0;
+    } else {
+      lo = (int)ceil(P.x[a] - R);
+      hi = (int)floor(P.x[a] + R);
+    }
+    runs[a] = axis_runs(lo, hi, L[a], T[a], g.periodic[a]);
+  }
+  for (int rz = 0; rz < 2; ++rz) {
+    const int z0 = rz ? runs[2].b0 : runs[2].a0, z1 = rz ? runs[2].b1 : runs[2].a1;
+    for (int tz = z0; tz <= z1; ++tz)
+      for (int ry = 0; ry < 2; ++ry) {
+        const int y0 = ry ? runs[1].b0 : runs[1].a0, y1 = ry ? runs[1].b1 : runs[1].a1;
+        for (int ty = y0; ty <= y1; ++ty)
+          for (int rx = 0; rx < 2; ++rx) {
+            const int x0 = rx ? runs[0].b0 : runs[0].a0, x1 = rx ? runs[0].b1 : runs[0].a1;
+            for (int tx = x0; tx <= x1; ++tx) {
+              const int t = tx + g.ntx * (ty + g.nty * tz);
+              const int k = atomicAdd(&tile_count[t], 1);
+              if (k < cap)
+                tile_list[(size_t)t * cap + k] = s;
+              else
+                atomicOr(err, ERR_SLOTS);
+            }
+          }
+      }
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(BLOCK) k_solid_fraction(Geom g, double h, int np, int cap,
+                                                        const int* tile_count, const int* tile_list,
+                                                        const PSnap* snap, double* eps_total,
+                                                        int* ids, double* seps, int kout,
+                                                        unsigned* err) {
+  extern __shared__ double smem_d[];
+  LdsEntry* lds = reinterpret_cast<LdsEntry*>(smem_d);
+  const int tile = blockIdx.x;
+  const int cnt = load_tile_list(tile_count, tile_list, cap, snap, tile, lds, nullptr, np);
+  __syncthreads();
+  int x0, y0, z0;
+  tile_origin(g, tile, x0, y0, z0);
+  Cell c;
+  c.x = x0 + threadIdx.x % TX;
+  c.y = y0 + (threadIdx.x / TX) % TY;
+  c.z = z0 + threadIdx.x / (TX * TY);
+  if (c.x >= g.nx || c.y >= g.ny || c.z >= g.nz) return;
+  c.n = c.x + (long long)g.nx * (c.y + (long long)g.ny * c.z);
+  Slots s;
+  s.n = 0;
+  if (cnt > 0) collect_slots<D>(g, c, lds, cnt, h, s, err);
+  double S_ = 0.0;
+  for (int k = 0; k < s.n; ++k) S_ += s.eps[k];
+  if (eps_total) eps_total[c.n] = S_ < 1.0 ? S_ : 1.0;
+  for (int k = 0; k < kout; ++k) {
+    if (ids) ids[(size_t)c.n * kout + k] = k < s.n ? s.id[k] : -1;
+    if (seps) seps[(size_t)c.n * kout + k] = k < s.n ? s.eps[k] : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers
+// ---------------------------------------------------------------------------
+static int grid_for(long long n, int block = 256) {
+  long long b = (n + block - 1) / block;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+template <int Q, int PREC>
+static int dispatch_step(psclbm_ctx* c, const StepArgs& a, int par, size_t lds_bytes) {
+  const int nb = c->ntiles;
+  if (par == 0)
+    k_step<Q, PREC, 0><<<nb, BLOCK, lds_bytes, c->stream>>>(a);
+  else
+    k_step<Q, PREC, 1><<<nb, BLOCK, lds_bytes, c->stream>>>(a);
+  return hip_ok(hipGetLastError());
+}
+
+template <int PREC>
+static int dispatch_step_q(psclbm_ctx* c, const StepArgs& a, int par, size_t lds) {
+  return c->geom.q == 9 ? dispatch_step<9, PREC>(c, a, par, lds)
+                        : dispatch_step<19, PREC>(c, a, par, lds);
+}
+
+#define PSCLBM_DISPATCH(QV, PV, CALL)                                       \
+  do {                                                                      \
+    if ((QV) == 9) {                                                        \
+      if ((PV) == PSCLBM_FP64) { constexpr int Q = 9, P = PSCLBM_FP64; CALL; } \
+      else if ((PV) == PSCLBM_FP32) { constexpr int Q = 9, P = PSCLBM_FP32; CALL; } \
+      else { constexpr int Q = 9, P = PSCLBM_FP32_FP16STORE; CALL; }        \
+    } else {                                                                \
+      if ((PV) == PSCLBM_FP64) { constexpr int Q = 19, P = PSCLBM_FP64; CALL; } \
+      else if ((PV) == PSCLBM_FP32) { constexpr int Q = 19, P = PSCLBM_FP32; CALL; } \
+      else { constexpr int Q = 19, P = PSCLBM_FP32_FP16STORE; CALL; }       \
+    }                                                                       \
+  } while (0)
+
+int launch_zero(psclbm_ctx* c, void* p, size_t bytes) {
+  return hip_ok(hipMemsetAsync(p, 0, bytes, c->stream));
+}
+
+int launch_init_equilibrium(psclbm_ctx* c, const double* rho, const double* u) {
+  const int grid = grid_for(c->geom.N);
+  PSCLBM_DISPATCH(c->geom.q, c->prec,
+                  (k_set_equilibrium<Q, P><<<grid, 256, 0, c->stream>>>(c->geom, c->f, rho, u)));
+  return hip_ok(hipGetLastError());
+}
+
+int launch_set_f(psclbm_ctx* c, const double* f) {
+  const int grid = grid_for(c->geom.N);
+  PSCLBM_DISPATCH(c->geom.q, c->prec,
+                  (k_set_f<Q, P><<<grid, 256, 0, c->stream>>>(c->geom, c->f, f)));
+  return hip_ok(hipGetLastError());
+}
+
+int launch_get_f(psclbm_ctx* c, double* f) {
+  const int grid = grid_for(c->geom.N);
+  const int par = (int)(c->steps & 1);
+  PSCLBM_DISPATCH(c->geom.q, c->prec,
+                  (k_get_f<Q, P><<<grid, 256, 0, c->stream>>>(c->geom, c->f, par, f, nullptr,
+                                                              nullptr, 0.0, 0.0, 0.0)));
+  return hip_ok(hipGetLastError());
+}
+
+int launch_get_macros(psclbm_ctx* c, double* rho, double* u) {
+  const int grid = grid_for(c->geom.N);
+  const int par = (int)(c->steps & 1);
+  const double* F = c->cfg.body_force;
+  PSCLBM_DISPATCH(c->geom.q, c->prec,
+                  (k_get_f<Q, P><<<grid, 256, 0, c->stream>>>(c->geom, c->f, par, nullptr, rho, u,
+                                                              F[0], F[1], F[2])));
+  return hip_ok(hipGetLastError());
+}
+
+int launch_rasterize(psclbm_ctx* c, const psclbm_particles* p) {
+  const int three_d = c->geom.q == 19;
+  const long long tot = p->n > c->ntiles ? p->n : c->ntiles;
+  if (p->n > 0 || c->ntiles > 0) {
+    k_snapshot<<<grid_for(tot), 256, 0, c->stream>>>(p->n, three_d, p->x, p->u, p->omega,
+                                                     p->radius, c->snap, c->tile_count, c->ntiles,
+                                                     c->facc[0], c->facc[1], c->err);
+    int rc = hip_ok(hipGetLastError());
+    if (rc) return rc;
+  }
+  if (p->n > 0) {
+    k_bin<<<(p->n + 127) / 128, 128, 0, c->stream>>>(c->geom, p->n, c->cfg.shell_h, c->snap,
+                                                      c->tile_count, c->tile_list,
+                                                      c->cfg.max_tile_particles, c->err);
+    return hip_ok(hipGetLastError());
+  }
+  return PSCLBM_OK;
+}
+
+int launch_solid_fraction(psclbm_ctx* c, double* eps, int* ids, double* seps, int k) {
+  const size_t lds = sizeof(LdsEntry) * (size_t)c->cfg.max_tile_particles;
+  if (c->geom.q == 9)
+    k_solid_fraction<2><<<c->ntiles, BLOCK, lds, c->stream>>>(
+        c->geom, c->cfg.shell_h, c->np, c->cfg.max_tile_particles, c->tile_count, c->tile_list,
+        c->snap, eps, ids, seps, k, c->err);
+  else
+    k_solid_fraction<3><<<c->ntiles, BLOCK, lds, c->stream>>>(
+        c->geom, c->cfg.shell_h, c->np, c->cfg.max_tile_particles, c->tile_count, c->tile_list,
+        c->snap, eps, ids, seps, k, c->err);
+  return hip_ok(hipGetLastError());
+}
+
+int launch_step(psclbm_ctx* c) {
+  const int par = (int)(c->steps & 1);
+  StepArgs a;
+  a.g = c->geom;
+  a.f = c->f;
+  a.tau = c->cfg.tau;
+  for (int k = 0; k < 3; ++k) a.force[k] = c->cfg.body_force[k];
+  a.h = c->cfg.shell_h;
+  a.np = c->np;
+  a.cap = c->cfg.max_tile_particles;
+  a.tile_count = c->tile_count;
+  a.tile_list = c->tile_list;
+  a.snap = c->snap;
+  const int next = c->force_buf ^ 1;
+  a.facc = c->facc[next];
+  a.fzero = c->facc[next ^ 1];
+  a.mass_part = c->mass_part;
+  a.outlet_u = c->outlet_u;
+  a.face_stride = c->face_stride;
+  a.err = c->err;
+  a.has_open = 0;
+  int has_outlet = 0;
+  for (int f = 0; f < 6; ++f) {
+    if (c->geom.face[f] == PSCLBM_INLET_EQ || c->geom.face[f] == PSCLBM_OUTLET_EQ) a.has_open = 1;
+    if (c->geom.face[f] == PSCLBM_OUTLET_EQ) has_outlet = 1;
+  }
+  if (has_outlet) {
+    const double* F = c->cfg.body_force;
+    dim3 grid((unsigned)grid_for(c->face_stride), 6);
+    PSCLBM_DISPATCH(c->geom.q, c->prec,
+                    (k_outlet_velocity<Q, P><<<grid, 256, 0, c->stream>>>(
+                        c->geom, c->f, par, F[0], F[1], F[2], c->outlet_u, c->face_stride)));
+    int rc = hip_ok(hipGetLastError());
+    if (rc) return rc;
+  }
+  const size_t lds = c->np > 0 ? (sizeof(LdsEntry) + 6 * sizeof(double)) *
+                                     (size_t)c->cfg.max_tile_particles
+                               : 0;
+  int rc;
+  if (c->prec == PSCLBM_FP64)
+    rc = dispatch_step_q<PSCLBM_FP64>(c, a, par, lds);
+  else if (c->prec == PSCLBM_FP32)
+    rc = dispatch_step_q<PSCLBM_FP32>(c, a, par, lds);
+  else
+    rc = dispatch_step_q<PSCLBM_FP32_FP16STORE>(c, a, par, lds);
+  if (rc) return rc;
+  c->force_buf = next;
+  c->steps += 1;
+  c->mass_valid = 1;
+  return PSCLBM_OK;
+}
+
+int launch_mass(psclbm_ctx* c, double* h_mass) {
+  // After a step the fused per-workgroup partials already hold the sum of
+  // the stored state; otherwise reduce the state directly.
+  if (!c->mass_valid) {
+    PSCLBM_DISPATCH(c->geom.q, c->prec,
+                    (k_mass_direct<Q, P><<<c->nblocks, 256, 0, c->stream>>>(c->geom, c->f,
+                                                                            c->mass_part)));
+    int rc0 = hip_ok(hipGetLastError());
+    if (rc0) return rc0;
+    c->mass_valid = 1;
+  }
+  double* tmp = c->scalar;
+  k_reduce<<<1, 256, 0, c->stream>>>(c->mass_part, c->nblocks, tmp);
+  int rc = hip_ok(hipGetLastError());
+  if (rc) return rc;
+  double dev = 0.0;
+  rc = hip_ok(hipMemcpyAsync(&dev, tmp, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  if (rc) return rc;
+  rc = hip_ok(hipStreamSynchronize(c->stream));
+  if (rc) return rc;
+  *h_mass = (double)c->geom.N * c->geom.rho0 + dev;
+  return PSCLBM_OK;
+}
+
+}  // namespace psclbm

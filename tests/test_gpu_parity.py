@@ -1,0 +1,140 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerances (FP64 form): distributions within 1e-12 of max|f|; per-particle
+forces within 1e-12 of the L1 size of their Eq. 14 summands (the GPU sums them
+in a different order with FP64 atomics).
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import force_scale, gpu_lattice, gpu_run, oracle_run, relerr
+
+pytestmark = pytest.mark.gpu
+
+WALLS_Y = (W.PERIODIC, W.PERIODIC, W.BOUNCE_BACK, W.BOUNCE_BACK, W.PERIODIC, W.PERIODIC)
+
+
+def _print_case(**kw):
+    print("case:", ", ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def _particles(lat, n, rmin, rmax, seed, umax=0.01, wmax=0.002, overlap=False):
+    rng = np.random.default_rng(seed)
+    dim = 2 if lat.q == 9 else 3
+    box = (lat.nx, lat.ny, lat.nz)[:dim]
+    periodic = tuple(lat.periodic(a) for a in range(dim))
+    r = np.sort(rng.uniform(rmin, rmax, n))[::-1]
+    gap = -0.6 * rmin if overlap else 0.3
+    x = W.rsa(rng, r, tuple(float(b) for b in box), periodic, gap=gap, clearance=0.5)
+    u = rng.uniform(-umax, umax, (n, 3))
+    w = rng.uniform(-wmax, wmax, (n, 3))
+    if dim == 2:
+        u[:, 2] = 0
+        w[:, :2] = 0
+        x[:, 2] = 0
+    return W.Particles(x, u, w, r)
+
+
+CASES = {
+    "d2q9_periodic": W.LatticeSpec(q=9, nx=150, ny=70, tau=0.7, force=(1e-5, -3e-6, 0)),
+    "d2q9_walls": W.LatticeSpec(q=9, nx=130, ny=37, tau=0.8, force=(2e-5, 0, 0), faces=WALLS_Y),
+    "d2q9_couette": W.LatticeSpec(q=9, nx=67, ny=29, tau=0.9, faces=(
+        W.PERIODIC, W.PERIODIC, W.MOVING_WALL, W.MOVING_WALL, W.PERIODIC, W.PERIODIC),
+        face_u=((0, 0, 0), (0, 0, 0), (-0.01, 0, 0), (0.02, 0.001, 0), (0, 0, 0), (0, 0, 0))),
+    "d2q9_open": W.LatticeSpec(q=9, nx=100, ny=45, tau=0.8, faces=(
+        W.INLET_EQ, W.OUTLET_EQ, W.BOUNCE_BACK, W.BOUNCE_BACK, W.PERIODIC, W.PERIODIC),
+        face_u=((0.02, 0.0, 0),) + ((0, 0, 0),) * 5),
+    "d3q19_periodic": W.LatticeSpec(q=19, nx=70, ny=21, nz=18, tau=0.6, force=(1e-5, 0, 2e-6)),
+    "d3q19_walls": W.LatticeSpec(q=19, nx=33, ny=26, nz=22, tau=0.65, force=(-1e-5, 0, 0), faces=(
+        W.BOUNCE_BACK, W.MOVING_WALL, W.PERIODIC, W.PERIODIC, W.BOUNCE_BACK, W.BOUNCE_BACK),
+        face_u=((0, 0, 0), (0, 0.01, -0.005), (0, 0, 0), (0, 0, 0), (0, 0, 0), (0, 0, 0))),
+}
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+@pytest.mark.parametrize("steps", [1, 2, 5])
+def test_fluid_steps_parity(name, steps):
+    lat = CASES[name]
+    _print_case(test="fluid", name=name, steps=steps)
+    f0 = W.random_state(lat, 11)
+    ref, _, _ = oracle_run(lat, f0, None, steps)
+    _, f, _, _ = gpu_run(lat, f0, None, steps)
+    assert relerr(f, ref.f) < 1e-12
+
+
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_psc_steps_parity(name):
+    lat = CASES[name]
+    _print_case(test="psc", name=name)
+    if lat.q == 9:
+        p = _particles(lat, 6, 4.0, 9.0, seed=3, overlap=True)
+    else:
+        p = _particles(lat, 5, 3.0, 5.0, seed=4, overlap=True)
+    f0 = W.random_state(lat, 12)
+    for steps in (1, 3):
+        ref, F_ref, T_ref = oracle_run(lat, f0, p, steps)
+        _, f, F, T = gpu_run(lat, f0, p, steps)
+        assert relerr(f, ref.f) < 1e-12
+        # the last step's forces start from the state after steps-1 steps
+        prev, _, _ = oracle_run(lat, f0, p, steps - 1)
+        scale = force_scale(lat, prev.f, p)
+        assert np.all(np.abs(F - F_ref).max(axis=1) <= 1e-12 * scale + 1e-300)
+        assert np.all(np.abs(T - T_ref).max(axis=1) <= 1e-12 * scale * 30 + 1e-300)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_rasterize_parity(q):
+    if q == 9:
+        lat = W.LatticeSpec(q=9, nx=140, ny=90)
+        p = _particles(lat, 12, 3.0, 10.0, seed=5, overlap=True)
+    else:
+        lat = W.LatticeSpec(q=19, nx=70, ny=40, nz=36)
+        p = _particles(lat, 10, 2.5, 6.0, seed=6, overlap=True)
+    _print_case(test="rasterize", q=q)
+    nslot, ids, eps, ssum = oracle.rasterize(lat, p.x, p.r)
+    assert nslot.max() <= 4
+    G = gpu_lattice(lat, p)
+    import paper_1901_09745_amd.psclbm as P
+    G.rasterize(P.DeviceParticles.from_host(p))
+    e, gid, geps = G.solid_fraction(4)
+    G.sync()
+    e = e.cpu().numpy().reshape(-1)
+    gid = gid.cpu().numpy().reshape(-1, 4)
+    geps = geps.cpu().numpy().reshape(-1, 4)
+    assert np.allclose(e, np.minimum(ssum, 1.0), rtol=0, atol=1e-14)
+    for k in range(4):
+        ref_ids = np.where(nslot > k, ids[:, k], -1)
+        assert np.array_equal(gid[:, k], ref_ids)
+        ref_eps = np.where(nslot > k, eps[:, k], 0.0)
+        assert np.allclose(geps[:, k], ref_eps, rtol=0, atol=1e-14)
+
+
+def test_c1_full_run():
+    # D2Q9 tau=0.8 200x100 channel, body force 1e-6, fixed disk r=10 at
+    # (60,50), 2000 steps: full-run FP64 parity.
+    w = W.c1()
+    _print_case(test="c1", steps=w.steps)
+    ref, F_ref, T_ref = oracle_run(w.lattice, None, w.particles, w.steps)
+    _, f, F, T = gpu_run(w.lattice, None, w.particles, w.steps)
+    assert relerr(f, ref.f) < 1e-12
+    rho_r, u_r = ref.macros()
+    Lg = oracle.Lattice(w.lattice, f)
+    rho_g, u_g = Lg.macros()
+    assert relerr(u_g, u_r) < 1e-10
+    assert abs(F[0, 0] - F_ref[0, 0]) < 1e-11 * abs(F_ref[0, 0])
+    assert abs(F[0, 1] - F_ref[0, 1]) < 1e-11 * abs(F_ref[0, 0])
+
+
+def test_mass_and_roundtrip():
+    lat = CASES["d3q19_walls"]
+    f0 = W.random_state(lat, 13)
+    G, f, _, _ = gpu_run(lat, f0, None, 0 + 1)
+    ref, _, _ = oracle_run(lat, f0, None, 1)
+    m = G.mass()
+    assert m == pytest.approx(ref.mass(), rel=1e-14)
+    import torch
+    G.set_f(torch.from_numpy(f0).cuda())
+    assert np.array_equal(G.get_f().cpu().numpy(), f0)
+    assert G.mass() == pytest.approx(oracle.Lattice(lat, f0).mass(), rel=1e-14)
