@@ -130,7 +130,11 @@ struct StepArgs {
   const double* outlet_u;  // [6][max face cells][3]
   long long face_stride;   // cells per face slot in outlet_u
   unsigned* err;
-  int has_open;            // any inlet / outlet face
+  double omega;            // 1 / tau
+  unsigned inlet_mask;     // faces of kind INLET_EQ (bit f)
+  unsigned outlet_mask;    // faces of kind OUTLET_EQ
+  unsigned open_mask;      // inlet | outlet
+  unsigned moving_mask;    // faces of kind MOVING_WALL
 };
 
 }  // namespace psclbm

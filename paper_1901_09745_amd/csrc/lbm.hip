@@ -191,16 +191,18 @@ struct Slots {
 };
 
 template <int D>
-__device__ inline void collect_slots(const Geom& g, const Cell& c, const LdsEntry* lds, int cnt,
-                                     double h, Slots& s, unsigned* err) {
+__device__ inline void collect_slots(const Geom& g, int x, int y, int z, const LdsEntry* lds,
+                                     int cnt, double h, Slots& s, unsigned* err) {
   s.n = 0;
+  const int px = g.periodic[0], py = g.periodic[1], pz = g.periodic[2];
+  const int nx = g.nx, ny = g.ny, nz = g.nz;
   for (int e = 0; e < cnt; ++e) {
     const LdsEntry& P = lds[e];
-    const double dx = min_image((double)c.x - P.x, g.periodic[0], g.nx);
-    const double dy = min_image((double)c.y - P.y, g.periodic[1], g.ny);
+    const double dx = min_image((double)x - P.x, px, nx);
+    const double dy = min_image((double)y - P.y, py, ny);
     double d2 = dx * dx + dy * dy;
     if constexpr (D == 3) {
-      const double dz = min_image((double)c.z - P.z, g.periodic[2], g.nz);
+      const double dz = min_image((double)z - P.z, pz, nz);
       d2 += dz * dz;
     }
     const double rh = P.r + h;
@@ -280,16 +282,77 @@ __device__ inline int xcd_tile(int b, int nb) {
 // ---------------------------------------------------------------------------
 // The fused collide-stream step.
 // ---------------------------------------------------------------------------
+// Lattice extents and periodicity as plain scalars (no arrays: every access
+// stays a register or a kernel-argument load).
+struct Dims {
+  int nx, ny, nz;
+  int px, py, pz;
+  unsigned sy, sz;  // strides of y and z
+};
+
+__device__ __forceinline__ Dims dims_of(const Geom& g) {
+  Dims d;
+  d.nx = g.nx;
+  d.ny = g.ny;
+  d.nz = g.nz;
+  d.px = g.periodic[0];
+  d.py = g.periodic[1];
+  d.pz = g.periodic[2];
+  d.sy = (unsigned)g.nx;
+  d.sz = (unsigned)g.nx * (unsigned)g.ny;
+  return d;
+}
+
+// The link from cell (x, y, z) along (dx, dy, dz): sets the neighbour's cell
+// offset m (periodic wrap applied) and returns the mask of non-periodic faces
+// the link leaves through (bit f for face f; 0 when the neighbour exists).
+__device__ __forceinline__ unsigned link(const Dims& d, int x, int y, int z, int dx, int dy,
+                                         int dz, unsigned n, unsigned& m) {
+  unsigned out = 0;
+  int off = 0;
+  if (dx) {
+    const int v = x + dx;
+    int o = dx;
+    if (v < 0) {
+      if (d.px) o += d.nx; else out |= 1u;
+    } else if (v >= d.nx) {
+      if (d.px) o -= d.nx; else out |= 2u;
+    }
+    off += o;
+  }
+  if (dy) {
+    const int v = y + dy;
+    int o = dy;
+    if (v < 0) {
+      if (d.py) o += d.ny; else out |= 4u;
+    } else if (v >= d.ny) {
+      if (d.py) o -= d.ny; else out |= 8u;
+    }
+    off += o * (int)d.sy;
+  }
+  if (dz) {
+    const int v = z + dz;
+    int o = dz;
+    if (v < 0) {
+      if (d.pz) o += d.nz; else out |= 16u;
+    } else if (v >= d.nz) {
+      if (d.pz) o -= d.nz; else out |= 32u;
+    }
+    off += o * (int)d.sz;
+  }
+  m = (unsigned)((int)n + off);
+  return out;
+}
+
 template <int Q, int PREC, int PAR>
-__global__ void __launch_bounds__(BLOCK) k_step(StepArgs a) {
+__global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
   using L = Lattice<Q>;
   using C = typename Form<PREC>::C;
   using S = typename Form<PREC>::S;
   using ST = Store<PREC, Q>;
   constexpr int D = L::D;
   extern __shared__ double smem_d[];
-  const Geom& g = a.g;
-  S* A = static_cast<S*>(a.f);
+  S* __restrict__ A = static_cast<S*>(a.f);
   const int nb = gridDim.x;
   const int tile = xcd_tile(blockIdx.x, nb);
 
@@ -299,197 +362,209 @@ __global__ void __launch_bounds__(BLOCK) k_step(StepArgs a) {
   const int cnt = load_tile_list(a.tile_count, a.tile_list, a.cap, a.snap, tile, lds, acc, a.np);
   if (cnt > 0) __syncthreads();
 
+  const Dims d = dims_of(a.g);
   int x0, y0, z0;
-  tile_origin(g, tile, x0, y0, z0);
-  const int lx = threadIdx.x % TX;
-  const int ly = (threadIdx.x / TX) % TY;
-  const int lz = threadIdx.x / (TX * TY);
-  Cell c;
-  c.x = x0 + lx;
-  c.y = y0 + ly;
-  c.z = z0 + lz;
-  const bool active = c.x < g.nx && c.y < g.ny && c.z < g.nz;
-  c.n = c.x + (long long)g.nx * (c.y + (long long)g.ny * c.z);
+  tile_origin(a.g, tile, x0, y0, z0);
+  const int x = x0 + (int)(threadIdx.x % TX);
+  const int y = y0 + (int)((threadIdx.x / TX) % TY);
+  const int z = z0 + (int)(threadIdx.x / (TX * TY));
+  const bool active = x < d.nx && y < d.ny && z < d.nz;
+  const unsigned n = (unsigned)x + d.sy * (unsigned)y + d.sz * (unsigned)z;
+  const unsigned N = (unsigned)a.g.N;
+  const double rho0 = a.g.rho0;
   double mass_dev = 0.0;
 
   if (active) {
-    const double rho0 = g.rho0;
-    // ---- load f (as deviations g_i = f_i - w_i rho0) ----
-    C gi[Q];
+    // ---- load f as deviations g_i = f_i - w_i rho0 ----
+    C g[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      size_t idx;
-      if constexpr (PAR == 0) {
-        idx = (size_t)i * g.N + c.n;
-      } else {
-        long long m;
-        if (neighbour(g, c, -L::ex(i), -L::ey(i), -L::ez(i), m, nullptr))
-          idx = (size_t)L::opp(i) * g.N + m;
-        else
-          idx = (size_t)i * g.N + c.n;
+      unsigned idx = (unsigned)i * N + n;
+      if constexpr (PAR == 1) {
+        unsigned m;
+        if (!link(d, x, y, z, -L::ex(i), -L::ey(i), -L::ez(i), n, m))
+          idx = (unsigned)L::opp(i) * N + m;
       }
-      gi[i] = ST::load(A, idx, i, rho0);
+      g[i] = ST::load(A, idx, i, rho0);
     }
-    const C F[3] = {(C)a.force[0], (C)a.force[1], (C)a.force[2]};
 
     // ---- inlet / outlet layers: reset to an equilibrium before collision ----
-    if (a.has_open) {
-      int kind = -1;
-      const double* uo = nullptr;
-      const int pc[3] = {c.x, c.y, c.z};
-      const int Ld[3] = {g.nx, g.ny, g.nz};
-      // outlets first, then inlets (an inlet wins on a shared corner)
-      for (int face = 0; face < 6; ++face) {
-        const int ax = face / 2;
-        const bool on = (face % 2 == 0) ? pc[ax] == 0 : pc[ax] == Ld[ax] - 1;
-        if (!on || g.face[face] != PSCLBM_OUTLET_EQ) continue;
-        const int u1 = ax == 0 ? 1 : 0, u2 = ax == 2 ? 1 : 2;
-        const long long k = pc[u1] + (long long)Ld[u1] * pc[u2];
-        uo = a.outlet_u + ((size_t)face * a.face_stride + k) * 3;
-        kind = PSCLBM_OUTLET_EQ;
+    if (a.open_mask) {
+      bool reset = false;
+      double ub0 = 0.0, ub1 = 0.0, ub2 = 0.0;
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {  // outlets first, an inlet wins on a corner
+        const bool on = f == 0 ? x == 0 : f == 1 ? x == d.nx - 1 : f == 2 ? y == 0
+                      : f == 3 ? y == d.ny - 1 : f == 4 ? z == 0 : z == d.nz - 1;
+        if (((a.outlet_mask >> f) & 1u) && on) {
+          const unsigned k = f < 2 ? (unsigned)y + (unsigned)d.ny * z
+                                   : (f < 4 ? (unsigned)x + (unsigned)d.nx * z
+                                            : (unsigned)x + (unsigned)d.nx * y);
+          const double* o = a.outlet_u + ((size_t)f * a.face_stride + k) * 3;
+          ub0 = o[0];
+          ub1 = o[1];
+          ub2 = o[2];
+          reset = true;
+        }
       }
-      for (int face = 0; face < 6; ++face) {
-        const int ax = face / 2;
-        const bool on = (face % 2 == 0) ? pc[ax] == 0 : pc[ax] == Ld[ax] - 1;
-        if (!on || g.face[face] != PSCLBM_INLET_EQ) continue;
-        uo = g.face_u[face];
-        kind = PSCLBM_INLET_EQ;
+#pragma unroll
+      for (int f = 0; f < 6; ++f) {
+        const bool on = f == 0 ? x == 0 : f == 1 ? x == d.nx - 1 : f == 2 ? y == 0
+                      : f == 3 ? y == d.ny - 1 : f == 4 ? z == 0 : z == d.nz - 1;
+        if (((a.inlet_mask >> f) & 1u) && on) {
+          ub0 = a.g.face_u[f][0];
+          ub1 = a.g.face_u[f][1];
+          ub2 = a.g.face_u[f][2];
+          reset = true;
+        }
       }
-      if (kind >= 0) {
-        const C ub[3] = {(C)uo[0], (C)uo[1], (C)uo[2]};
-        const C uu = ub[0] * ub[0] + ub[1] * ub[1] + ub[2] * ub[2];
+      if (reset) {
+        const C u0 = (C)ub0, u1 = (C)ub1, u2 = (C)ub2;
+        const C uu = u0 * u0 + u1 * u1 + u2 * u2;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          const C eu = L::ex(i) * ub[0] + L::ey(i) * ub[1] + L::ez(i) * ub[2];
-          gi[i] = (C)L::w(i) * (C)rho0 * ((C)3 * eu + (C)4.5 * eu * eu - (C)1.5 * uu);
+          const C eu = (C)L::ex(i) * u0 + (C)L::ey(i) * u1 + (C)L::ez(i) * u2;
+          g[i] = (C)L::w(i) * (C)rho0 * ((C)3 * eu + (C)4.5 * eu * eu - (C)1.5 * uu);
         }
       }
     }
 
-    // ---- moments (Eq. 5) ----
+    // ---- moments with the half-force shift (Eq. 5) ----
+    const C F0 = (C)a.force[0], F1 = (C)a.force[1], F2 = (C)a.force[2];
     C drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      drho += gi[i];
-      if (L::ex(i)) jx += L::ex(i) * gi[i];
-      if (L::ey(i)) jy += L::ey(i) * gi[i];
-      if (L::ez(i)) jz += L::ez(i) * gi[i];
+      drho += g[i];
+      if (L::ex(i) > 0) jx += g[i];
+      if (L::ex(i) < 0) jx -= g[i];
+      if (L::ey(i) > 0) jy += g[i];
+      if (L::ey(i) < 0) jy -= g[i];
+      if (L::ez(i) > 0) jz += g[i];
+      if (L::ez(i) < 0) jz -= g[i];
     }
     const C rho = (C)rho0 + drho;
     const C inv_rho = (C)1 / rho;
-    const C ux = (jx + (C)0.5 * F[0]) * inv_rho;
-    const C uy = (jy + (C)0.5 * F[1]) * inv_rho;
-    const C uz = (jz + (C)0.5 * F[2]) * inv_rho;
+    const C ux = (jx + (C)0.5 * F0) * inv_rho;
+    const C uy = (jy + (C)0.5 * F1) * inv_rho;
+    const C uz = (jz + (C)0.5 * F2) * inv_rho;
     const C uu = ux * ux + uy * uy + uz * uz;
-
-    // ---- non-equilibrium parts (Eq. 3) and Guo forcing (Eq. 4) ----
-    const C tau = (C)a.tau;
-    const C omega = (C)1 / tau;
+    const C omega = (C)a.omega;
     const C kguo = (C)1 - (C)0.5 * omega;
-    const C uF = ux * F[0] + uy * F[1] + uz * F[2];
-    C fneq[Q], Fi[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const C eu = L::ex(i) * ux + L::ey(i) * uy + L::ez(i) * uz;
-      const C eF = L::ex(i) * F[0] + L::ey(i) * F[1] + L::ez(i) * F[2];
-      const C wi = (C)L::w(i);
-      const C geq = wi * (drho + rho * ((C)3 * eu + (C)4.5 * eu * eu - (C)1.5 * uu));
-      fneq[i] = gi[i] - geq;
-      Fi[i] = kguo * wi * ((C)3 * (eF - uF) + (C)9 * eu * eF);
-    }
+    const C uF = ux * F0 + uy * F1 + uz * F2;
 
     // ---- solid fractions of the covering particles (Table 1) ----
     Slots s;
     s.n = 0;
-    if (cnt > 0) collect_slots<D>(g, c, lds, cnt, a.h, s, a.err);
+    if (cnt > 0) collect_slots<D>(a.g, x, y, z, lds, cnt, a.h, s, a.err);
 
-    C gout[Q];
-    if (s.n == 0) {
-      // pure fluid: BGK + Guo (Eq. 2)
+    // Weights (Eq. 13 with Table 1 Step 5): B_n from the clamped cell total;
+    // each particle's share B_s is formed in the second pass below.
+    double S_ = 0.0;
 #pragma unroll
-      for (int i = 0; i < Q; ++i) gout[i] = gi[i] - omega * fneq[i] + Fi[i];
-    } else {
-      // ---- weights (Eq. 13 with Table 1 Step 5) ----
-      double S_ = 0.0;
+    for (int k = 0; k < KSLOTS; ++k)
+      if (k < s.n) S_ += s.eps[k];
+    const double tm = a.tau - 0.5;
+    const double en = S_ < 1.0 ? S_ : 1.0;
+    const double den = (1.0 - en) + tm;
+    const C Bn = s.n > 0 ? (C)(en * tm / den) : (C)0;
+    const C omB = (C)1 - Bn;
+    const C relax = omB * omega;
+
+    // ---- pass 1: BGK + Guo weighted by (1 - B_n), plus the bounce-back of the
+    // non-equilibrium part, B_n (fneq_{-i} - fneq_i); one opposite pair at a
+    // time (Eqs. 2-4, 10, 12) ----
+    {
+      const C wi = (C)L::w(0);
+      const C fneq = g[0] - wi * (drho - rho * (C)1.5 * uu);
+      g[0] = g[0] - relax * fneq - omB * kguo * wi * (C)3 * uF;
+    }
 #pragma unroll
-      for (int k = 0; k < KSLOTS; ++k)
-        if (k < s.n) S_ += s.eps[k];
-      const double tm = a.tau - 0.5;
-      const double en = S_ < 1.0 ? S_ : 1.0;
-      const double den = (1.0 - en) + tm;
-      const C Bn = (C)(en * tm / den);
-      C Bs[KSLOTS];
-      C usx[KSLOTS], usy[KSLOTS], usz[KSLOTS];
-      double rx[KSLOTS], ry[KSLOTS], rz[KSLOTS];
+    for (int i = 1; i < Q; ++i) {
+      const int o = L::opp(i);
+      if (o < i) continue;
+      const C wi = (C)L::w(i);
+      const C eu = (C)L::ex(i) * ux + (C)L::ey(i) * uy + (C)L::ez(i) * uz;
+      const C eF = (C)L::ex(i) * F0 + (C)L::ey(i) * F1 + (C)L::ez(i) * F2;
+      const C sym = drho + rho * ((C)4.5 * eu * eu - (C)1.5 * uu);
+      const C fn_i = g[i] - wi * (sym + rho * (C)3 * eu);
+      const C fn_o = g[o] - wi * (sym - rho * (C)3 * eu);
+      // Guo term (Eq. 4): even and odd parts under e -> -e
+      const C Fsym = kguo * wi * ((C)9 * eu * eF - (C)3 * uF);
+      const C Fant = kguo * wi * ((C)3 * eF);
+      const C bb = Bn * (fn_o - fn_i);
+      g[i] = g[i] - relax * fn_i + omB * (Fsym + Fant) + bb;
+      g[o] = g[o] - relax * fn_o + omB * (Fsym - Fant) - bb;
+    }
+
+    // ---- pass 2 (covered cells): sum_s B_s [f^eq_i(rho, u_s) - f^eq_i(rho, u)]
+    // and the momentum exchange of Eq. 14, m_s = B_s [rho (u_s - u) + F] ----
+    if (s.n > 0) {
 #pragma unroll
       for (int k = 0; k < KSLOTS; ++k) {
-        Bs[k] = 0;
-        usx[k] = usy[k] = usz[k] = 0;
-        rx[k] = ry[k] = rz[k] = 0.0;
         if (k >= s.n) continue;
-        Bs[k] = (C)(S_ <= 1.0 ? s.eps[k] * tm / den : s.eps[k] / S_);
+        const C Bs = (C)(S_ <= 1.0 ? s.eps[k] * tm / den : s.eps[k] / S_);
         const PSnap& P = a.snap[s.id[k]];
-        rx[k] = min_image((double)c.x - P.x[0], g.periodic[0], g.nx);
-        ry[k] = min_image((double)c.y - P.x[1], g.periodic[1], g.ny);
-        rz[k] = D == 3 ? min_image((double)c.z - P.x[2], g.periodic[2], g.nz) : 0.0;
-        // rigid-body velocity at the cell centre
-        usx[k] = (C)(P.u[0] + P.w[1] * rz[k] - P.w[2] * ry[k]);
-        usy[k] = (C)(P.u[1] + P.w[2] * rx[k] - P.w[0] * rz[k]);
-        usz[k] = (C)(P.u[2] + P.w[0] * ry[k] - P.w[1] * rx[k]);
-      }
-      // Eq. 12 with Eq. 10: sum_s B_s Omega^s_i =
-      //   B_n (fneq_{-i} - fneq_i) + rho w_i sum_s B_s [feq_i(u_s) - feq_i(u)] / (rho w_i)
-      const C omB = (C)1 - Bn;
+        const double rx = min_image((double)x - P.x[0], d.px, d.nx);
+        const double ry = min_image((double)y - P.x[1], d.py, d.ny);
+        const double rz = D == 3 ? min_image((double)z - P.x[2], d.pz, d.nz) : 0.0;
+        // rigid-body velocity of particle s at the cell centre
+        const C usx = (C)(P.u[0] + P.w[1] * rz - P.w[2] * ry);
+        const C usy = (C)(P.u[1] + P.w[2] * rx - P.w[0] * rz);
+        const C usz = (C)(P.u[2] + P.w[0] * ry - P.w[1] * rx);
+        const C du2 = usx * usx + usy * usy + usz * usz - uu;
+        const C rB = rho * Bs;
+        g[0] += rB * (C)L::w(0) * (-(C)1.5 * du2);
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const C eu = L::ex(i) * ux + L::ey(i) * uy + L::ez(i) * uz;
-        C dsum = 0;
-#pragma unroll
-        for (int k = 0; k < KSLOTS; ++k) {
-          if (k >= s.n) continue;
-          const C eus = L::ex(i) * usx[k] + L::ey(i) * usy[k] + L::ez(i) * usz[k];
-          const C us2 = usx[k] * usx[k] + usy[k] * usy[k] + usz[k] * usz[k];
-          dsum += Bs[k] * ((C)3 * (eus - eu) + (C)4.5 * (eus * eus - eu * eu) -
-                           (C)1.5 * (us2 - uu));
+        for (int i = 1; i < Q; ++i) {
+          const int o = L::opp(i);
+          if (o < i) continue;
+          const C wi = (C)L::w(i);
+          const C eu = (C)L::ex(i) * ux + (C)L::ey(i) * uy + (C)L::ez(i) * uz;
+          const C eus = (C)L::ex(i) * usx + (C)L::ey(i) * usy + (C)L::ez(i) * usz;
+          const C ds_s = (C)4.5 * (eus * eus - eu * eu) - (C)1.5 * du2;
+          const C ds_a = (C)3 * (eus - eu);
+          g[i] += rB * wi * (ds_s + ds_a);
+          g[o] += rB * wi * (ds_s - ds_a);
         }
-        gout[i] = gi[i] - omB * omega * fneq[i] + omB * Fi[i] +
-                  Bn * (fneq[L::opp(i)] - fneq[i]) + rho * (C)L::w(i) * dsum;
-      }
-      // ---- Eq. 14: m_s = B_s sum_i Omega^s_i e_i = B_s [rho (u_s - u) + F] ----
-#pragma unroll
-      for (int k = 0; k < KSLOTS; ++k) {
-        if (k >= s.n) continue;
-        const double mx = (double)(Bs[k] * (rho * (usx[k] - ux) + F[0]));
-        const double my = (double)(Bs[k] * (rho * (usy[k] - uy) + F[1]));
-        const double mz = D == 3 ? (double)(Bs[k] * (rho * (usz[k] - uz) + F[2])) : 0.0;
+        const double mx = (double)(Bs * (rho * (usx - ux) + F0));
+        const double my = (double)(Bs * (rho * (usy - uy) + F1));
+        const double mz = D == 3 ? (double)(Bs * (rho * (usz - uz) + F2)) : 0.0;
         double* ac = acc + 6 * s.e[k];
         atomicAdd(ac + 0, -mx);
         atomicAdd(ac + 1, -my);
         if constexpr (D == 3) {
           atomicAdd(ac + 2, -mz);
-          atomicAdd(ac + 3, -(ry[k] * mz - rz[k] * my));
-          atomicAdd(ac + 4, -(rz[k] * mx - rx[k] * mz));
+          atomicAdd(ac + 3, -(ry * mz - rz * my));
+          atomicAdd(ac + 4, -(rz * mx - rx * mz));
         }
-        atomicAdd(ac + 5, -(rx[k] * my - ry[k] * mx));
+        atomicAdd(ac + 5, -(rx * my - ry * mx));
       }
     }
 
-    // ---- stream (Eq. 1) with bounce-back (Eq. 6) ----
+    // ---- stream (Eq. 1) with halfway bounce-back (Eq. 6) ----
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      double uw[3] = {0.0, 0.0, 0.0};
-      long long m;
-      const bool in =
-          neighbour(g, c, L::ex(i), L::ey(i), L::ez(i), m, uw);
-      C v = gout[i];
-      size_t idx;
-      if (in) {
-        idx = PAR == 0 ? (size_t)L::opp(i) * g.N + c.n : (size_t)i * g.N + m;
+      unsigned m = n;
+      const unsigned out = i == 0 ? 0u : link(d, x, y, z, L::ex(i), L::ey(i), L::ez(i), n, m);
+      C v = g[i];
+      unsigned idx;
+      if (!out) {
+        idx = PAR == 0 ? (unsigned)L::opp(i) * N + n : (unsigned)i * N + m;
       } else {
-        // moving wall: -2 w_i rho (e_i . u_w) / c_s^2
-        const double eu = L::ex(i) * uw[0] + L::ey(i) * uw[1] + L::ez(i) * uw[2];
-        if (eu != 0.0) v -= (C)(6.0 * L::w(i) * eu) * rho;
-        idx = (size_t)L::opp(i) * g.N + c.n;
+        const unsigned mw = out & a.moving_mask;
+        if (mw) {  // moving wall: -2 w_i rho (e_i . u_w) / c_s^2
+          double uw0 = 0.0, uw1 = 0.0, uw2 = 0.0;
+#pragma unroll
+          for (int f = 0; f < 6; ++f)
+            if ((mw >> f) & 1u) {
+              uw0 += a.g.face_u[f][0];
+              uw1 += a.g.face_u[f][1];
+              uw2 += a.g.face_u[f][2];
+            }
+          const double eu = L::ex(i) * uw0 + L::ey(i) * uw1 + L::ez(i) * uw2;
+          v -= (C)(6.0 * L::w(i) * eu) * rho;
+        }
+        idx = (unsigned)L::opp(i) * N + n;
       }
       mass_dev += ST::store(A, idx, i, v, rho0);
     }
@@ -510,10 +585,6 @@ __global__ void __launch_bounds__(BLOCK) k_step(StepArgs a) {
   if (cnt > 0) {
     for (int e = threadIdx.x; e < cnt; e += BLOCK) {
       const double* ac = acc + 6 * e;
-      bool any = false;
-#pragma unroll
-      for (int k = 0; k < 6; ++k) any |= ac[k] != 0.0;
-      if (!any) continue;
       double* dst = a.facc + 6 * (size_t)lds[e].id;
 #pragma unroll
       for (int k = 0; k < 6; ++k)
@@ -522,8 +593,8 @@ __global__ void __launch_bounds__(BLOCK) k_step(StepArgs a) {
   }
   // ---- clear the other force buffer for the next step ----
   if (a.np > 0) {
-    const size_t tot = 6 * (size_t)a.np;
-    for (size_t k = (size_t)blockIdx.x * BLOCK + threadIdx.x; k < tot; k += (size_t)nb * BLOCK)
+    const unsigned tot = 6u * (unsigned)a.np;
+    for (unsigned k = blockIdx.x * BLOCK + threadIdx.x; k < tot; k += (unsigned)nb * BLOCK)
       a.fzero[k] = 0.0;
   }
 }
@@ -826,7 +897,7 @@ __global__ void __launch_bounds__(BLOCK) k_solid_fraction(Geom g, double h, int 
   c.n = c.x + (long long)g.nx * (c.y + (long long)g.ny * c.z);
   Slots s;
   s.n = 0;
-  if (cnt > 0) collect_slots<D>(g, c, lds, cnt, h, s, err);
+  if (cnt > 0) collect_slots<D>(g, c.x, c.y, c.z, lds, cnt, h, s, err);
   double S_ = 0.0;
   for (int k = 0; k < s.n; ++k) S_ += s.eps[k];
   if (eps_total) eps_total[c.n] = S_ < 1.0 ? S_ : 1.0;
@@ -964,12 +1035,15 @@ int launch_step(psclbm_ctx* c) {
   a.outlet_u = c->outlet_u;
   a.face_stride = c->face_stride;
   a.err = c->err;
-  a.has_open = 0;
-  int has_outlet = 0;
+  a.omega = 1.0 / c->cfg.tau;
+  a.inlet_mask = a.outlet_mask = a.moving_mask = 0;
   for (int f = 0; f < 6; ++f) {
-    if (c->geom.face[f] == PSCLBM_INLET_EQ || c->geom.face[f] == PSCLBM_OUTLET_EQ) a.has_open = 1;
-    if (c->geom.face[f] == PSCLBM_OUTLET_EQ) has_outlet = 1;
+    if (c->geom.face[f] == PSCLBM_INLET_EQ) a.inlet_mask |= 1u << f;
+    if (c->geom.face[f] == PSCLBM_OUTLET_EQ) a.outlet_mask |= 1u << f;
+    if (c->geom.face[f] == PSCLBM_MOVING_WALL) a.moving_mask |= 1u << f;
   }
+  a.open_mask = a.inlet_mask | a.outlet_mask;
+  const int has_outlet = a.outlet_mask != 0;
   if (has_outlet) {
     const double* F = c->cfg.body_force;
     dim3 grid((unsigned)grid_for(c->face_stride), 6);
