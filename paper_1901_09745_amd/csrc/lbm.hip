@@ -44,10 +44,44 @@ static_assert(check_lattice<9>() && check_lattice<19>(), "opposite directions");
 // ---------------------------------------------------------------------------
 // Storage conversion: deviation g_i = f_i - w_i rho0 in the compute type.
 // ---------------------------------------------------------------------------
+// Element `e` of a per-direction array through a 32-bit byte offset, so the
+// address is a uniform 64-bit base (SGPRs) plus one 32-bit VGPR offset.
+template <typename S>
+__device__ __forceinline__ S& elem(S* base, unsigned e) {
+  return *reinterpret_cast<S*>(reinterpret_cast<char*>(base) + (e * (unsigned)sizeof(S)));
+}
+
 template <int PREC, int Q>
 struct Store {
   using S = typename Form<PREC>::S;
   using C = typename Form<PREC>::C;
+  // direction-i array `b` (= A + i N), element e
+  __device__ static C ld(S* b, unsigned e, int i, double rho0) {
+    const S v = elem(b, e);
+    if constexpr (PREC == PSCLBM_FP64) {
+      return v - Lattice<Q>::w(i) * rho0;
+    } else if constexpr (PREC == PSCLBM_FP32) {
+      return v;
+    } else {
+      return static_cast<float>(v) * static_cast<float>(Lattice<Q>::w(i));
+    }
+  }
+  // stores deviation g of direction i; returns the deviation memory now holds
+  // (in the compute precision: the per-cell part of the mass sum)
+  __device__ static C st(S* b, unsigned e, int i, C g, double rho0) {
+    if constexpr (PREC == PSCLBM_FP64) {
+      const double f = Lattice<Q>::w(i) * rho0 + g;
+      elem(b, e) = f;
+      return f - Lattice<Q>::w(i) * rho0;
+    } else if constexpr (PREC == PSCLBM_FP32) {
+      elem(b, e) = g;
+      return g;
+    } else {
+      const _Float16 h = static_cast<_Float16>(g * static_cast<float>(1.0 / Lattice<Q>::w(i)));
+      elem(b, e) = h;
+      return static_cast<float>(h) * static_cast<float>(Lattice<Q>::w(i));
+    }
+  }
   __device__ static C load(const S* a, size_t idx, int i, double rho0) {
     if constexpr (PREC == PSCLBM_FP64) {
       return a[idx] - Lattice<Q>::w(i) * rho0;
@@ -178,6 +212,7 @@ __device__ inline double pair_eps(double d, double r, double cs, double h) {
 struct LdsEntry {
   double x, y, z;
   double r, cs;
+  double u[3], w[3];
   int id;
   int pad;
 };
@@ -190,72 +225,143 @@ struct Slots {
   double eps[KSLOTS];
 };
 
+// The cells of one wave form one x-row of the tile (TX == 64): the wave
+// first keeps the list entries whose shell r + h reaches the row (a ballot
+// over the list, conservative), then each cell tests only those.  All 64
+// lanes must call this (active == false for cells outside the lattice).
+static_assert(TX == 64, "one wave per tile row");
+
 template <int D>
-__device__ inline void collect_slots(const Geom& g, int x, int y, int z, const LdsEntry* lds,
-                                     int cnt, double h, Slots& s, unsigned* err) {
+__device__ inline void collect_slots(const Geom& g, int x0, int x, int y, int z, bool active,
+                                     const LdsEntry* lds, int cnt, double h, Slots& s,
+                                     unsigned* err) {
   s.n = 0;
   const int px = g.periodic[0], py = g.periodic[1], pz = g.periodic[2];
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  for (int e = 0; e < cnt; ++e) {
-    const LdsEntry& P = lds[e];
-    const double dx = min_image((double)x - P.x, px, nx);
-    const double dy = min_image((double)y - P.y, py, ny);
-    double d2 = dx * dx + dy * dy;
-    if constexpr (D == 3) {
-      const double dz = min_image((double)z - P.z, pz, nz);
-      d2 += dz * dz;
-    }
-    const double rh = P.r + h;
-    if (!(d2 < rh * rh)) continue;
-    const double eps = pair_eps(sqrt(d2), P.r, P.cs, h);
-    if (!(eps > 0.0)) continue;
-    if (s.n >= KSLOTS) {
-      atomicOr(err, ERR_SLOTS);
-      continue;
-    }
-    // insert keeping ascending particle ids (ids in a list are distinct)
-    int pos = 0;
-#pragma unroll
-    for (int j = 0; j < KSLOTS; ++j)
-      if (j < s.n && s.id[j] < P.id) pos = j + 1;
-#pragma unroll
-    for (int j = KSLOTS - 1; j > 0; --j)
-      if (j > pos && j <= s.n) {
-        s.id[j] = s.id[j - 1];
-        s.e[j] = s.e[j - 1];
-        s.eps[j] = s.eps[j - 1];
+  const int lane = (int)(threadIdx.x & 63);
+  const double xc = (double)x0 + 31.5;
+  for (int base = 0; base < cnt; base += 64) {
+    const int ec = base + lane;
+    bool cand = false;
+    if (ec < cnt) {
+      const LdsEntry& P = lds[ec];
+      const double rh = P.r + h;
+      const double dy = min_image((double)y - P.y, py, ny);
+      double r2 = dy * dy;
+      if constexpr (D == 3) {
+        const double dz = min_image((double)z - P.z, pz, nz);
+        r2 += dz * dz;
       }
-#pragma unroll
-    for (int j = 0; j < KSLOTS; ++j)
-      if (j == pos) {
-        s.id[j] = P.id;
-        s.e[j] = e;
-        s.eps[j] = eps;
+      if (r2 < rh * rh) {
+        const double half = sqrt(rh * rh - r2);
+        cand = fabs(min_image(xc - P.x, px, nx)) < 31.5 + half + 1e-6;
       }
-    s.n += 1;
+    }
+    unsigned long long mask = __ballot(cand);
+    while (mask) {
+      const int b = __ffsll(mask) - 1;
+      mask &= mask - 1;
+      if (!active) continue;
+      const int e = base + b;
+      const LdsEntry& P = lds[e];
+      const double dx = min_image((double)x - P.x, px, nx);
+      const double dy = min_image((double)y - P.y, py, ny);
+      double d2 = dx * dx + dy * dy;
+      if constexpr (D == 3) {
+        const double dz = min_image((double)z - P.z, pz, nz);
+        d2 += dz * dz;
+      }
+      const double rh = P.r + h;
+      if (!(d2 < rh * rh)) continue;
+      // Table 1 Steps 3-4 on d = sqrt(d2); the root is taken only when the
+      // fraction is not already fixed at 0 or 1 by the shell or the clamp
+      double eps;
+      const double rl = P.r - h;
+      const double c1 = P.cs - 1.0;
+      if (rl >= 0.0 && d2 <= rl * rl) {
+        eps = 1.0;
+      } else if (c1 >= 0.0 && d2 <= c1 * c1) {
+        eps = 1.0;
+      } else if (P.cs <= 0.0 || d2 >= P.cs * P.cs) {
+        eps = 0.0;
+      } else {
+        eps = pair_eps(sqrt(d2), P.r, P.cs, h);
+      }
+      if (!(eps > 0.0)) continue;
+      if (s.n >= KSLOTS) {
+        atomicOr(err, ERR_SLOTS);
+        continue;
+      }
+      // the list is in ascending id, so slots are appended in id order
+#pragma unroll
+      for (int j = 0; j < KSLOTS; ++j)
+        if (j == s.n) {
+          s.id[j] = P.id;
+          s.e[j] = e;
+          s.eps[j] = eps;
+        }
+      s.n += 1;
+    }
   }
 }
 
-// Loads the tile's particle list into LDS; returns the list length (uniform).
+// Sum of a double over the 64 lanes of a wave with DPP lane moves (no LDS
+// traffic): pairs and quads by quad permutes, rows of 16 by row shifts, then
+// row broadcasts 15 and 31 carry the row totals up to lane 63, whose value is
+// read back as a wave-uniform scalar.  Every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x114>(v);  // row_shr:4
+  v += dpp_move<0x118>(v);  // row_shr:8
+  v += dpp_move<0x142>(v);  // row_bcast:15
+  v += dpp_move<0x143>(v);  // row_bcast:31
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+// Loads the tile's particle list into LDS in ascending particle id (a rank
+// sort; ids in a list are distinct) and clears its force accumulators.
+// Returns the list length (uniform over the block).  Must be called by the
+// whole block.
 __device__ inline int load_tile_list(const int* tile_count, const int* tile_list, int cap,
                                      const PSnap* snap, int tile, LdsEntry* lds, double* acc,
                                      int np) {
   int cnt = np > 0 ? tile_count[tile] : 0;
   if (cnt > cap) cnt = cap;
+  if (cnt == 0) return 0;
+  int* ids = reinterpret_cast<int*>(acc ? acc : reinterpret_cast<double*>(lds + cap));
+  for (int e = threadIdx.x; e < cnt; e += BLOCK) ids[e] = tile_list[(size_t)tile * cap + e];
+  __syncthreads();
   for (int e = threadIdx.x; e < cnt; e += BLOCK) {
-    const int id = tile_list[(size_t)tile * cap + e];
+    const int id = ids[e];
+    int rank = 0;
+    for (int j = 0; j < cnt; ++j) rank += ids[j] < id;
     const PSnap& P = snap[id];
-    lds[e].x = P.x[0];
-    lds[e].y = P.x[1];
-    lds[e].z = P.x[2];
-    lds[e].r = P.r;
-    lds[e].cs = P.cs;
-    lds[e].id = id;
-    if (acc) {
+    LdsEntry& L = lds[rank];
+    L.x = P.x[0];
+    L.y = P.x[1];
+    L.z = P.x[2];
+    L.r = P.r;
+    L.cs = P.cs;
 #pragma unroll
-      for (int a = 0; a < 6; ++a) acc[6 * e + a] = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      L.u[a] = P.u[a];
+      L.w[a] = P.w[a];
     }
+    L.id = id;
   }
+  __syncthreads();
+  if (acc)
+    for (int k = threadIdx.x; k < 6 * cnt; k += BLOCK) acc[k] = 0.0;
   return cnt;
 }
 
@@ -306,6 +412,8 @@ __device__ __forceinline__ Dims dims_of(const Geom& g) {
 // The link from cell (x, y, z) along (dx, dy, dz): sets the neighbour's cell
 // offset m (periodic wrap applied) and returns the mask of non-periodic faces
 // the link leaves through (bit f for face f; 0 when the neighbour exists).
+// WALLS == false: every axis is periodic and no link ever leaves.
+template <bool WALLS>
 __device__ __forceinline__ unsigned link(const Dims& d, int x, int y, int z, int dx, int dy,
                                          int dz, unsigned n, unsigned& m) {
   unsigned out = 0;
@@ -314,9 +422,9 @@ __device__ __forceinline__ unsigned link(const Dims& d, int x, int y, int z, int
     const int v = x + dx;
     int o = dx;
     if (v < 0) {
-      if (d.px) o += d.nx; else out |= 1u;
+      if (!WALLS || d.px) o += d.nx; else out |= 1u;
     } else if (v >= d.nx) {
-      if (d.px) o -= d.nx; else out |= 2u;
+      if (!WALLS || d.px) o -= d.nx; else out |= 2u;
     }
     off += o;
   }
@@ -324,9 +432,9 @@ __device__ __forceinline__ unsigned link(const Dims& d, int x, int y, int z, int
     const int v = y + dy;
     int o = dy;
     if (v < 0) {
-      if (d.py) o += d.ny; else out |= 4u;
+      if (!WALLS || d.py) o += d.ny; else out |= 4u;
     } else if (v >= d.ny) {
-      if (d.py) o -= d.ny; else out |= 8u;
+      if (!WALLS || d.py) o -= d.ny; else out |= 8u;
     }
     off += o * (int)d.sy;
   }
@@ -334,17 +442,17 @@ __device__ __forceinline__ unsigned link(const Dims& d, int x, int y, int z, int
     const int v = z + dz;
     int o = dz;
     if (v < 0) {
-      if (d.pz) o += d.nz; else out |= 16u;
+      if (!WALLS || d.pz) o += d.nz; else out |= 16u;
     } else if (v >= d.nz) {
-      if (d.pz) o -= d.nz; else out |= 32u;
+      if (!WALLS || d.pz) o -= d.nz; else out |= 32u;
     }
     off += o * (int)d.sz;
   }
   m = (unsigned)((int)n + off);
-  return out;
+  return WALLS ? out : 0u;
 }
 
-template <int Q, int PREC, int PAR>
+template <int Q, int PREC, int PAR, bool WALLS>
 __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
   using L = Lattice<Q>;
   using C = typename Form<PREC>::C;
@@ -374,18 +482,29 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
   const double rho0 = a.g.rho0;
   double mass_dev = 0.0;
 
+  // ---- solid fractions of the covering particles (Table 1), whole wave ----
+  Slots s;
+  s.n = 0;
+  if (cnt > 0) collect_slots<D>(a.g, x0, x, y, z, active, lds, cnt, a.h, s, a.err);
+
+  C g[Q];
+  C rho = (C)1, ux = 0, uy = 0, uz = 0, uu = 0;
+  const C F0 = (C)a.force[0], F1 = (C)a.force[1], F2 = (C)a.force[2];
+  const double tm = a.tau - 0.5;
+  double S_ = 0.0, den = 1.0, inv_den = 1.0;
   if (active) {
     // ---- load f as deviations g_i = f_i - w_i rho0 ----
-    C g[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      unsigned idx = (unsigned)i * N + n;
-      if constexpr (PAR == 1) {
-        unsigned m;
-        if (!link(d, x, y, z, -L::ex(i), -L::ey(i), -L::ez(i), n, m))
-          idx = (unsigned)L::opp(i) * N + m;
+      if constexpr (PAR == 0) {
+        g[i] = ST::ld(A + (size_t)i * N, n, i, rho0);
+      } else {
+        unsigned m = n;
+        if (!link<WALLS>(d, x, y, z, -L::ex(i), -L::ey(i), -L::ez(i), n, m))
+          g[i] = ST::ld(A + (size_t)L::opp(i) * N, m, i, rho0);
+        else  // reflected at a wall during the previous (even) step
+          g[i] = ST::ld(A + (size_t)i * N, n, i, rho0);
       }
-      g[i] = ST::load(A, idx, i, rho0);
     }
 
     // ---- inlet / outlet layers: reset to an equilibrium before collision ----
@@ -420,17 +539,16 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
       }
       if (reset) {
         const C u0 = (C)ub0, u1 = (C)ub1, u2 = (C)ub2;
-        const C uu = u0 * u0 + u1 * u1 + u2 * u2;
+        const C uq = u0 * u0 + u1 * u1 + u2 * u2;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           const C eu = (C)L::ex(i) * u0 + (C)L::ey(i) * u1 + (C)L::ez(i) * u2;
-          g[i] = (C)L::w(i) * (C)rho0 * ((C)3 * eu + (C)4.5 * eu * eu - (C)1.5 * uu);
+          g[i] = (C)L::w(i) * (C)rho0 * ((C)3 * eu + (C)4.5 * eu * eu - (C)1.5 * uq);
         }
       }
     }
 
     // ---- moments with the half-force shift (Eq. 5) ----
-    const C F0 = (C)a.force[0], F1 = (C)a.force[1], F2 = (C)a.force[2];
     C drho = 0, jx = 0, jy = 0, jz = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -442,31 +560,25 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
       if (L::ez(i) > 0) jz += g[i];
       if (L::ez(i) < 0) jz -= g[i];
     }
-    const C rho = (C)rho0 + drho;
+    rho = (C)rho0 + drho;
     const C inv_rho = (C)1 / rho;
-    const C ux = (jx + (C)0.5 * F0) * inv_rho;
-    const C uy = (jy + (C)0.5 * F1) * inv_rho;
-    const C uz = (jz + (C)0.5 * F2) * inv_rho;
-    const C uu = ux * ux + uy * uy + uz * uz;
+    ux = (jx + (C)0.5 * F0) * inv_rho;
+    uy = (jy + (C)0.5 * F1) * inv_rho;
+    uz = (jz + (C)0.5 * F2) * inv_rho;
+    uu = ux * ux + uy * uy + uz * uz;
     const C omega = (C)a.omega;
     const C kguo = (C)1 - (C)0.5 * omega;
     const C uF = ux * F0 + uy * F1 + uz * F2;
 
-    // ---- solid fractions of the covering particles (Table 1) ----
-    Slots s;
-    s.n = 0;
-    if (cnt > 0) collect_slots<D>(a.g, x, y, z, lds, cnt, a.h, s, a.err);
-
     // Weights (Eq. 13 with Table 1 Step 5): B_n from the clamped cell total;
     // each particle's share B_s is formed in the second pass below.
-    double S_ = 0.0;
 #pragma unroll
     for (int k = 0; k < KSLOTS; ++k)
       if (k < s.n) S_ += s.eps[k];
-    const double tm = a.tau - 0.5;
     const double en = S_ < 1.0 ? S_ : 1.0;
-    const double den = (1.0 - en) + tm;
-    const C Bn = s.n > 0 ? (C)(en * tm / den) : (C)0;
+    den = (1.0 - en) + tm;
+    if (s.n > 0) inv_den = 1.0 / den;
+    const C Bn = s.n > 0 ? (C)(en * tm * inv_den) : (C)0;
     const C omB = (C)1 - Bn;
     const C relax = omB * omega;
 
@@ -495,62 +607,72 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
       g[i] = g[i] - relax * fn_i + omB * (Fsym + Fant) + bb;
       g[o] = g[o] - relax * fn_o + omB * (Fsym - Fant) - bb;
     }
+  }
 
-    // ---- pass 2 (covered cells): sum_s B_s [f^eq_i(rho, u_s) - f^eq_i(rho, u)]
-    // and the momentum exchange of Eq. 14, m_s = B_s [rho (u_s - u) + F] ----
-    if (s.n > 0) {
+  // ---- pass 2 (covered cells): sum_s B_s [f^eq_i(rho, u_s) - f^eq_i(rho, u)]
+  // and the momentum exchange of Eq. 14, m_s = B_s [rho (u_s - u) + F],
+  // accumulated per list entry with LDS atomics (the LDS unit serialises
+  // same-entry lanes without costing vector instructions) ----
+  if (s.n > 0) {
+    // share of each particle: Eq. 13 when the fractions sum to at most one,
+    // else eps_{n,s} / sum (the clamped total has B_n = 1)
+    double bscale = tm * inv_den;
+    if (S_ > 1.0) bscale = 1.0 / S_;
 #pragma unroll
-      for (int k = 0; k < KSLOTS; ++k) {
-        if (k >= s.n) continue;
-        const C Bs = (C)(S_ <= 1.0 ? s.eps[k] * tm / den : s.eps[k] / S_);
-        const PSnap& P = a.snap[s.id[k]];
-        const double rx = min_image((double)x - P.x[0], d.px, d.nx);
-        const double ry = min_image((double)y - P.x[1], d.py, d.ny);
-        const double rz = D == 3 ? min_image((double)z - P.x[2], d.pz, d.nz) : 0.0;
-        // rigid-body velocity of particle s at the cell centre
-        const C usx = (C)(P.u[0] + P.w[1] * rz - P.w[2] * ry);
-        const C usy = (C)(P.u[1] + P.w[2] * rx - P.w[0] * rz);
-        const C usz = (C)(P.u[2] + P.w[0] * ry - P.w[1] * rx);
-        const C du2 = usx * usx + usy * usy + usz * usz - uu;
-        const C rB = rho * Bs;
-        g[0] += rB * (C)L::w(0) * (-(C)1.5 * du2);
+    for (int k = 0; k < KSLOTS; ++k) {
+      if (k >= s.n) continue;
+      const C Bs = (C)(s.eps[k] * bscale);
+      const LdsEntry& P = lds[s.e[k]];
+      const double rx = min_image((double)x - P.x, d.px, d.nx);
+      const double ry = min_image((double)y - P.y, d.py, d.ny);
+      const double rz = D == 3 ? min_image((double)z - P.z, d.pz, d.nz) : 0.0;
+      // rigid-body velocity of particle s at the cell centre
+      const C usx = (C)(P.u[0] + P.w[1] * rz - P.w[2] * ry);
+      const C usy = (C)(P.u[1] + P.w[2] * rx - P.w[0] * rz);
+      const C usz = (C)(P.u[2] + P.w[0] * ry - P.w[1] * rx);
+      const C dvx = usx - ux, dvy = usy - uy, dvz = usz - uz;
+      const C svx = usx + ux, svy = usy + uy, svz = usz + uz;
+      const C du2 = dvx * svx + dvy * svy + dvz * svz;  // |u_s|^2 - |u|^2
+      const C rB = rho * Bs;
+      g[0] -= rB * (C)L::w(0) * (C)1.5 * du2;
 #pragma unroll
-        for (int i = 1; i < Q; ++i) {
-          const int o = L::opp(i);
-          if (o < i) continue;
-          const C wi = (C)L::w(i);
-          const C eu = (C)L::ex(i) * ux + (C)L::ey(i) * uy + (C)L::ez(i) * uz;
-          const C eus = (C)L::ex(i) * usx + (C)L::ey(i) * usy + (C)L::ez(i) * usz;
-          const C ds_s = (C)4.5 * (eus * eus - eu * eu) - (C)1.5 * du2;
-          const C ds_a = (C)3 * (eus - eu);
-          g[i] += rB * wi * (ds_s + ds_a);
-          g[o] += rB * wi * (ds_s - ds_a);
-        }
-        const double mx = (double)(Bs * (rho * (usx - ux) + F0));
-        const double my = (double)(Bs * (rho * (usy - uy) + F1));
-        const double mz = D == 3 ? (double)(Bs * (rho * (usz - uz) + F2)) : 0.0;
-        double* ac = acc + 6 * s.e[k];
-        atomicAdd(ac + 0, -mx);
-        atomicAdd(ac + 1, -my);
-        if constexpr (D == 3) {
-          atomicAdd(ac + 2, -mz);
-          atomicAdd(ac + 3, -(ry * mz - rz * my));
-          atomicAdd(ac + 4, -(rz * mx - rx * mz));
-        }
-        atomicAdd(ac + 5, -(rx * my - ry * mx));
+      for (int i = 1; i < Q; ++i) {
+        const int o = L::opp(i);
+        if (o < i) continue;
+        const C rBw = rB * (C)L::w(i);
+        const C de = (C)L::ex(i) * dvx + (C)L::ey(i) * dvy + (C)L::ez(i) * dvz;
+        const C se = (C)L::ex(i) * svx + (C)L::ey(i) * svy + (C)L::ez(i) * svz;
+        // 4.5 [(e.u_s)^2 - (e.u)^2] - 1.5 (|u_s|^2 - |u|^2), and 3 e.(u_s - u)
+        const C ds_s = (C)4.5 * de * se - (C)1.5 * du2;
+        const C ds_a = (C)3 * de;
+        g[i] += rBw * (ds_s + ds_a);
+        g[o] += rBw * (ds_s - ds_a);
       }
+      const double mx = (double)(Bs * (rho * dvx + F0));
+      const double my = (double)(Bs * (rho * dvy + F1));
+      double* ac = acc + 6 * s.e[k];
+      atomicAdd(ac + 0, -mx);
+      atomicAdd(ac + 1, -my);
+      if constexpr (D == 3) {
+        const double mz = (double)(Bs * (rho * dvz + F2));
+        atomicAdd(ac + 2, -mz);
+        atomicAdd(ac + 3, -(ry * mz - rz * my));
+        atomicAdd(ac + 4, -(rz * mx - rx * mz));
+      }
+      atomicAdd(ac + 5, -(rx * my - ry * mx));
     }
+  }
 
+  if (active) {
     // ---- stream (Eq. 1) with halfway bounce-back (Eq. 6) ----
+    C cell_dev = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       unsigned m = n;
-      const unsigned out = i == 0 ? 0u : link(d, x, y, z, L::ex(i), L::ey(i), L::ez(i), n, m);
+      const unsigned out =
+          i == 0 ? 0u : link<WALLS>(d, x, y, z, L::ex(i), L::ey(i), L::ez(i), n, m);
       C v = g[i];
-      unsigned idx;
-      if (!out) {
-        idx = PAR == 0 ? (unsigned)L::opp(i) * N + n : (unsigned)i * N + m;
-      } else {
+      if (out) {
         const unsigned mw = out & a.moving_mask;
         if (mw) {  // moving wall: -2 w_i rho (e_i . u_w) / c_s^2
           double uw0 = 0.0, uw1 = 0.0, uw2 = 0.0;
@@ -564,14 +686,17 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
           const double eu = L::ex(i) * uw0 + L::ey(i) * uw1 + L::ez(i) * uw2;
           v -= (C)(6.0 * L::w(i) * eu) * rho;
         }
-        idx = (unsigned)L::opp(i) * N + n;
       }
-      mass_dev += ST::store(A, idx, i, v, rho0);
+      if (PAR == 0 || out)  // own cell, opposite slot
+        cell_dev += ST::st(A + (size_t)L::opp(i) * N, n, i, v, rho0);
+      else                  // neighbour cell, same slot
+        cell_dev += ST::st(A + (size_t)i * N, m, i, v, rho0);
     }
+    mass_dev = (double)cell_dev;
   }
 
   // ---- per-workgroup FP64 mass partial (sum of the stored deviations) ----
-  for (int off = 32; off > 0; off >>= 1) mass_dev += __shfl_down(mass_dev, off, 64);
+  mass_dev = wave_sum(mass_dev);
   __shared__ double wsum[BLOCK / 64];
   if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = mass_dev;
   __syncthreads();
@@ -581,7 +706,8 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
     a.mass_part[blockIdx.x] = t;
   }
 
-  // ---- flush the tile's force / torque partials (FP64) ----
+  // ---- flush the tile's force / torque partials (FP64); the barrier of the
+  // mass reduction above orders the LDS accumulation before this read ----
   if (cnt > 0) {
     for (int e = threadIdx.x; e < cnt; e += BLOCK) {
       const double* ac = acc + 6 * e;
@@ -893,11 +1019,12 @@ __global__ void __launch_bounds__(BLOCK) k_solid_fraction(Geom g, double h, int 
   c.x = x0 + threadIdx.x % TX;
   c.y = y0 + (threadIdx.x / TX) % TY;
   c.z = z0 + threadIdx.x / (TX * TY);
-  if (c.x >= g.nx || c.y >= g.ny || c.z >= g.nz) return;
+  const bool active = c.x < g.nx && c.y < g.ny && c.z < g.nz;
   c.n = c.x + (long long)g.nx * (c.y + (long long)g.ny * c.z);
   Slots s;
   s.n = 0;
-  if (cnt > 0) collect_slots<D>(g, c.x, c.y, c.z, lds, cnt, h, s, err);
+  if (cnt > 0) collect_slots<D>(g, x0, c.x, c.y, c.z, active, lds, cnt, h, s, err);
+  if (!active) return;
   double S_ = 0.0;
   for (int k = 0; k < s.n; ++k) S_ += s.eps[k];
   if (eps_total) eps_total[c.n] = S_ < 1.0 ? S_ : 1.0;
@@ -920,10 +1047,18 @@ static int grid_for(long long n, int block = 256) {
 template <int Q, int PREC>
 static int dispatch_step(psclbm_ctx* c, const StepArgs& a, int par, size_t lds_bytes) {
   const int nb = c->ntiles;
-  if (par == 0)
-    k_step<Q, PREC, 0><<<nb, BLOCK, lds_bytes, c->stream>>>(a);
-  else
-    k_step<Q, PREC, 1><<<nb, BLOCK, lds_bytes, c->stream>>>(a);
+  const bool walls = !(c->geom.periodic[0] && c->geom.periodic[1] && c->geom.periodic[2]);
+  if (walls) {
+    if (par == 0)
+      k_step<Q, PREC, 0, true><<<nb, BLOCK, lds_bytes, c->stream>>>(a);
+    else
+      k_step<Q, PREC, 1, true><<<nb, BLOCK, lds_bytes, c->stream>>>(a);
+  } else {
+    if (par == 0)
+      k_step<Q, PREC, 0, false><<<nb, BLOCK, lds_bytes, c->stream>>>(a);
+    else
+      k_step<Q, PREC, 1, false><<<nb, BLOCK, lds_bytes, c->stream>>>(a);
+  }
   return hip_ok(hipGetLastError());
 }
 
@@ -1003,7 +1138,7 @@ int launch_rasterize(psclbm_ctx* c, const psclbm_particles* p) {
 }
 
 int launch_solid_fraction(psclbm_ctx* c, double* eps, int* ids, double* seps, int k) {
-  const size_t lds = sizeof(LdsEntry) * (size_t)c->cfg.max_tile_particles;
+  const size_t lds = (sizeof(LdsEntry) + sizeof(double)) * (size_t)c->cfg.max_tile_particles;
   if (c->geom.q == 9)
     k_solid_fraction<2><<<c->ntiles, BLOCK, lds, c->stream>>>(
         c->geom, c->cfg.shell_h, c->np, c->cfg.max_tile_particles, c->tile_count, c->tile_list,
