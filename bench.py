@@ -3,8 +3,9 @@
 One "step" is one coupled time step of the whole hot path on the 2D workload
 (D2Q9 tau=0.7, 1024^2 periodic, 2000 disks r~U(6,12), JKR DEM, gravity on the
 particles): psc_rasterize -> lbm_step (fused PSC collide-stream with the
-Eq. 14 force/torque reduction and the mass partials) -> particle_forces ->
-dem_step.  Inputs are resident in HBM before the timed region.
+Eq. 14 force/torque reduction and the mass partials) -> dem_step (reading the
+step's FP64 force/torque accumulators in place).  Inputs are resident in HBM
+before the timed region.
 
 The JSON line reports:
   value          MLUPS (lattice cell updates per second / 1e6) of the coupled
@@ -69,8 +70,8 @@ def run_form(w, form, steps, warmup, coupled=True):
         if k_ev is not None:
             k_ev[1].record()
         if coupled:
-            P.particle_forces(ctx, F, T)
-            P.dem_step(ctx, prm, p.x, p.u, p.omega, p.r, F, T)
+            # the DEM reads the step's FP64 force/torque accumulators in place
+            P.dem_step(ctx, prm, p.x, p.u, p.omega, p.r, None, None)
 
     for _ in range(warmup):
         one()

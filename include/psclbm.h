@@ -122,7 +122,8 @@ size_t psclbm_workspace_bytes(const psclbm_config* cfg);
  * hip_stream is a hipStream_t (NULL: the null stream).  *out receives the
  * context (a small host allocation).  Errors: EINVAL (tau <= 1/2, lattice /
  * nz mismatch, unpaired periodic faces, open face on an axis shorter than 3
- * cells, negative capacities), ENOMEM (workspace too small), EHIP. */
+ * cells, negative capacities, one direction's array of 4 GiB or more),
+ * ENOMEM (workspace too small), EHIP. */
 int lbm_init(const psclbm_config* cfg, void* d_workspace, size_t bytes, void* hip_stream,
              psclbm_ctx** out);
 
@@ -185,10 +186,13 @@ int particle_forces(psclbm_ctx* ctx, double* d_force, double* d_torque);
  * jump-on / pull-off hysteresis) between particles and with the walls of
  * non-periodic axes (flat walls at -1/2 and L-1/2).  Positions wrap into
  * [0, L) on periodic axes.  2D: disks of unit depth.  Contact history lives in
- * the workspace (dem_reset_contacts clears it).  Errors: EINVAL (bad params,
- * n > max_particles, a contact reach beyond the bin size), EHIP; sticky
- * ECONTACTS on contact or bin overflow, sticky EINVAL for a radius above
- * max_radius. */
+ * the workspace (dem_reset_contacts clears it).  d_force and d_torque may
+ * both be NULL: the force and torque of the most recent lbm_step are then
+ * read from the workspace (n must equal the rasterised count; ESTATE
+ * otherwise).  The contact forces of a particle are summed in neighbour-bin
+ * order.  Errors: EINVAL (bad params, n > max_particles, only one of the two
+ * force pointers NULL, a contact reach delta_C of 1 or more), EHIP; sticky
+ * ECONTACTS on contact or bin overflow. */
 int dem_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double* d_u,
              double* d_omega, const double* d_radius, int n, const double* d_force,
              const double* d_torque);

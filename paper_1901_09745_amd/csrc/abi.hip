@@ -54,8 +54,9 @@ int validate(const psclbm_config* c) {
     if (c->max_contacts < 1 || c->max_contacts > 64) return PSCLBM_EINVAL;
     if (!(c->max_radius > 0.0) || !std::isfinite(c->max_radius)) return PSCLBM_EINVAL;
   }
+  // the kernels address one direction's array with 32-bit byte offsets
   const double cells = (double)c->nx * c->ny * c->nz;
-  if (cells * c->lattice > 9.0e12) return PSCLBM_EINVAL;
+  if (cells * storage_bytes(c->precision) >= 4294967296.0) return PSCLBM_EINVAL;
   return PSCLBM_OK;
 }
 
@@ -313,7 +314,11 @@ int dem_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double*
   if (n < 0 || n > ctx->cfg.max_particles) return PSCLBM_EINVAL;
   if (n == 0) return PSCLBM_OK;
   if (!d_x || !d_u || !d_omega || !d_radius) return PSCLBM_EINVAL;
-  if (!prm->kinematic && (!d_force || !d_torque)) return PSCLBM_EINVAL;
+  if ((d_force == nullptr) != (d_torque == nullptr)) return PSCLBM_EINVAL;
+  if (!prm->kinematic && !d_force) {
+    // use the accumulators of the most recent lbm_step (same particle count)
+    if (!ctx->rasterized || n != ctx->np) return PSCLBM_ESTATE;
+  }
   if (prm->n_sub < 1 || !(prm->dt > 0.0) || !std::isfinite(prm->dt)) return PSCLBM_EINVAL;
   if (!prm->kinematic) {
     if (!(prm->rho_p > 0.0) || !(prm->E_p > 0.0) || !(prm->gamma >= 0.0) ||

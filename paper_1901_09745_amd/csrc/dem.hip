@@ -16,8 +16,6 @@
 
 namespace psclbm {
 
-constexpr int MAXC = 64;  // contacts a thread can hold while sorting
-
 struct DemArgs {
   int n;
   int three_d;
@@ -81,11 +79,6 @@ __device__ inline double jkr_force(double R, double E, double gamma, double delt
   return 4.0 * FC * (x * x * x - x * s);
 }
 
-__global__ void k_dem_clear(int* count, int nb) {
-  for (int k = blockIdx.x * blockDim.x + threadIdx.x; k < nb; k += gridDim.x * blockDim.x)
-    count[k] = 0;
-}
-
 __device__ inline int bin_coord(double x, int a, const DemArgs& d) {
   double v = x;
   if (d.periodic[a]) {
@@ -140,7 +133,8 @@ __device__ inline bool was_in_contact(const int* ids, int n, int id) {
   return false;
 }
 
-__global__ void k_dem_contacts(DemArgs d, const double* x, const double* u, const double* r) {
+__global__ void __launch_bounds__(128) k_dem_contacts(DemArgs d, const double* x, const double* u,
+                                                      const double* r) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= d.n) return;
   const double xi[3] = {x[3 * i], x[3 * i + 1], d.three_d ? x[3 * i + 2] : 0.0};
@@ -148,30 +142,9 @@ __global__ void k_dem_contacts(DemArgs d, const double* x, const double* u, cons
   const double ri = r[i];
   const int pn = d.prev_n[i];
   const int* prev = d.prev_id + (size_t)i * d.max_contacts;
-  int cid[MAXC];
-  double cf[MAXC][3];
+  int* next = d.next_id + (size_t)i * d.max_contacts;
   int cnt = 0;
-  bool overflow = false;
-  auto add = [&](int id, const double* f) {
-    if (cnt >= d.max_contacts || cnt >= MAXC) {
-      overflow = true;
-      return;
-    }
-    // keep ascending partner ids
-    int k = cnt;
-    while (k > 0 && cid[k - 1] > id) {
-      cid[k] = cid[k - 1];
-      cf[k][0] = cf[k - 1][0];
-      cf[k][1] = cf[k - 1][1];
-      cf[k][2] = cf[k - 1][2];
-      --k;
-    }
-    cid[k] = id;
-    cf[k][0] = f[0];
-    cf[k][1] = f[1];
-    cf[k][2] = f[2];
-    ++cnt;
-  };
+  double fs0 = 0.0, fs1 = 0.0, fs2 = 0.0;
   const int D = d.three_d ? 3 : 2;
   // walls of non-periodic axes: flat bodies at -1/2 and L-1/2 (1/R = 1/r)
   for (int face = 0; face < 2 * D; ++face) {
@@ -180,15 +153,18 @@ __global__ void k_dem_contacts(DemArgs d, const double* x, const double* u, cons
     const double dist = (face % 2 == 0) ? xi[a] + 0.5 : (d.L[a] - 0.5) - xi[a];
     const double delta = ri - dist;
     const int id = -1 - face;
+    if (delta < 0.0 && !was_in_contact(prev, pn, id)) continue;
     double dC;
     const double F = jkr_force(ri, d.E, d.gamma, delta, &dC);
-    if (delta >= 0.0 || (delta > -dC && was_in_contact(prev, pn, id))) {
-      double nrm[3] = {0, 0, 0};
-      nrm[a] = (face % 2 == 0) ? -1.0 : 1.0;
-      const double vrn = -(ui[0] * nrm[0] + ui[1] * nrm[1] + ui[2] * nrm[2]);
-      const double fm = -F + d.eta_n * vrn;
-      const double f[3] = {fm * nrm[0], fm * nrm[1], fm * nrm[2]};
-      add(id, f);
+    if (delta >= 0.0 || delta > -dC) {
+      const double sgn = (face % 2 == 0) ? -1.0 : 1.0;  // normal towards the wall
+      const double vrn = -ui[a] * sgn;
+      const double fm = (-F + d.eta_n * vrn) * sgn;
+      if (a == 0) fs0 += fm;
+      else if (a == 1) fs1 += fm;
+      else fs2 += fm;
+      if (cnt < d.max_contacts) next[cnt] = id;
+      ++cnt;
     }
   }
   // particle pairs from the neighbouring bins
@@ -209,12 +185,10 @@ __global__ void k_dem_contacts(DemArgs d, const double* x, const double* u, cons
         for (int t = 0; t < m; ++t) {
           const int j = d.bin_list[(size_t)b * d.bin_cap + t];
           if (j == i) continue;
-          double dv[3] = {0, 0, 0}, d2 = 0.0;
-          for (int a = 0; a < D; ++a) {
-            dv[a] = min_img(x[3 * j + a] - xi[a], d.periodic[a], d.L[a]);
-            d2 += dv[a] * dv[a];
-          }
-          const double dist = sqrt(d2);
+          const double dv0 = min_img(x[3 * j] - xi[0], d.periodic[0], d.L[0]);
+          const double dv1 = min_img(x[3 * j + 1] - xi[1], d.periodic[1], d.L[1]);
+          const double dv2 = d.three_d ? min_img(x[3 * j + 2] - xi[2], d.periodic[2], d.L[2]) : 0.0;
+          const double dist = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
           const double rj = r[j];
           const double delta = ri + rj - dist;
           if (delta < 0.0 && !was_in_contact(prev, pn, j)) continue;
@@ -222,22 +196,26 @@ __global__ void k_dem_contacts(DemArgs d, const double* x, const double* u, cons
           double dC;
           const double F = jkr_force(Reff, d.E, d.gamma, delta, &dC);
           if (delta >= 0.0 || delta > -dC) {
-            double vrn = 0.0, nrm[3];
-            for (int a = 0; a < 3; ++a) nrm[a] = dv[a] / dist;
-            for (int a = 0; a < D; ++a) vrn += (u[3 * j + a] - ui[a]) * nrm[a];
+            const double n0 = dv0 / dist, n1 = dv1 / dist, n2 = dv2 / dist;
+            double vrn = (u[3 * j] - ui[0]) * n0 + (u[3 * j + 1] - ui[1]) * n1;
+            if (d.three_d) vrn += (u[3 * j + 2] - ui[2]) * n2;
             const double fm = -F + d.eta_n * vrn;
-            const double f[3] = {fm * nrm[0], fm * nrm[1], fm * nrm[2]};
-            add(j, f);
+            fs0 += fm * n0;
+            fs1 += fm * n1;
+            fs2 += fm * n2;
+            if (cnt < d.max_contacts) next[cnt] = j;
+            ++cnt;
           }
         }
       }
-  if (overflow) atomicOr(d.err, ERR_CONTACTS);
-  double fs[3] = {0, 0, 0};
-  for (int k = 0; k < cnt; ++k)
-    for (int a = 0; a < 3; ++a) fs[a] += cf[k][a];
-  for (int a = 0; a < 3; ++a) d.fc[3 * i + a] = fs[a];
+  if (cnt > d.max_contacts) {
+    atomicOr(d.err, ERR_CONTACTS);
+    cnt = d.max_contacts;
+  }
+  d.fc[3 * i] = fs0;
+  d.fc[3 * i + 1] = fs1;
+  d.fc[3 * i + 2] = fs2;
   d.next_n[i] = cnt;
-  for (int k = 0; k < cnt; ++k) d.next_id[(size_t)i * d.max_contacts + k] = cid[k];
 }
 
 struct IntArgs {
@@ -248,11 +226,16 @@ struct IntArgs {
   double g[3];
   int kinematic;
   int wrap;
+  int fstride, tstride;  // element strides of the force / torque rows
+  int* bin_count;        // cleared here for the next binning (may be null)
+  int nbins;
 };
 
 __global__ void k_dem_integrate(IntArgs p, double* x, double* u, double* w, const double* r,
                                 const double* Ff, const double* Tf, const double* Fc) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p.bin_count)
+    for (int b = i; b < p.nbins; b += gridDim.x * blockDim.x) p.bin_count[b] = 0;
   if (i >= p.n) return;
   const int D = p.three_d ? 3 : 2;
   if (!p.kinematic) {
@@ -260,15 +243,17 @@ __global__ void k_dem_integrate(IntArgs p, double* x, double* u, double* w, cons
     const double V = p.three_d ? (4.0 / 3.0) * M_PI * ri * ri * ri : M_PI * ri * ri;
     const double m = p.rho_p * V;
     const double I = p.three_d ? 0.4 * m * ri * ri : 0.5 * m * ri * ri;
+    const double* F = Ff + (size_t)p.fstride * i;
+    const double* T = Tf + (size_t)p.tstride * i;
     for (int a = 0; a < D; ++a) {
       const double G = (p.rho_p - p.rho_f) * V * p.g[a];
-      u[3 * i + a] += p.dt * (Ff[3 * i + a] + Fc[3 * i + a] + G) / m;
+      u[3 * i + a] += p.dt * (F[a] + Fc[3 * i + a] + G) / m;
       x[3 * i + a] += p.dt * u[3 * i + a];
     }
     if (p.three_d) {
-      for (int a = 0; a < 3; ++a) w[3 * i + a] += p.dt * Tf[3 * i + a] / I;
+      for (int a = 0; a < 3; ++a) w[3 * i + a] += p.dt * T[a] / I;
     } else {
-      w[3 * i + 2] += p.dt * Tf[3 * i + 2] / I;
+      w[3 * i + 2] += p.dt * T[2] / I;
     }
   } else {
     for (int a = 0; a < D; ++a) x[3 * i + a] += p.dt * u[3 * i + a];
@@ -306,6 +291,16 @@ int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doub
   ia.rho_p = prm->rho_p;
   ia.rho_f = prm->rho_f;
   ia.kinematic = prm->kinematic ? 1 : 0;
+  // NULL force and torque: the FP64 accumulators of the most recent lbm_step
+  ia.fstride = 3;
+  ia.tstride = 3;
+  if (!F && !T) {
+    F = c->facc[c->force_buf];
+    T = F + 3;
+    ia.fstride = ia.tstride = 6;
+  }
+  ia.bin_count = nullptr;
+  ia.nbins = 0;
   const int blocks = (n + 127) / 128;
   if (prm->kinematic) {
     for (int s = 0; s < prm->n_sub; ++s) {
@@ -342,18 +337,19 @@ int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doub
   d.gamma = prm->gamma;
   d.eta_n = prm->eta_n;
   d.err = c->err;
-  const int nbins = c->nbin[0] * c->nbin[1] * c->nbin[2];
+  // bins are all-zero on entry (workspace init, then cleared after each use)
+  ia.bin_count = c->bin_count;
+  ia.nbins = c->nbin[0] * c->nbin[1] * c->nbin[2];
+  const int iblocks = (ia.nbins > n ? ia.nbins + 127 : n + 127) / 128;
   for (int s = 0; s < prm->n_sub; ++s) {
     ia.wrap = s == prm->n_sub - 1;  // positions wrap once, after the last sub-step
     d.prev_n = c->contact_n[c->contact_cur];
     d.prev_id = c->contact_id[c->contact_cur];
     d.next_n = c->contact_n[c->contact_cur ^ 1];
     d.next_id = c->contact_id[c->contact_cur ^ 1];
-    k_dem_clear<<<(nbins + 255) / 256 < 1024 ? (nbins + 255) / 256 : 1024, 256, 0, c->stream>>>(
-        c->bin_count, nbins);
     k_dem_bin<<<blocks, 128, 0, c->stream>>>(d, x);
     k_dem_contacts<<<blocks, 128, 0, c->stream>>>(d, x, u, r);
-    k_dem_integrate<<<blocks, 128, 0, c->stream>>>(ia, x, u, w, r, F, T, c->fcontact);
+    k_dem_integrate<<<iblocks, 128, 0, c->stream>>>(ia, x, u, w, r, F, T, c->fcontact);
     int rc = hip_ok(hipGetLastError());
     if (rc) return rc;
     c->contact_cur ^= 1;

@@ -1,0 +1,99 @@
+"""GPU parity at the full sizes of the workloads, in the launch configuration
+the benchmark times (tile lists of 64, FP64 form).
+
+Where a whole run is too long for the oracle, the GPU advances the state
+first and the oracle then recomputes one step from the GPU's own state: the
+step is local, so this checks every output of that step at full size."""
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+from helpers import force_scale, relerr
+
+pytestmark = pytest.mark.gpu
+
+
+def _gpu(w, form="fp64"):
+    import paper_1901_09745_amd.psclbm as P
+    G = P.Lattice(w.lattice, form, max_particles=max(w.particles.n, 1),
+                  max_radius=float(w.particles.r.max()) if w.particles.n else 1.0,
+                  max_tile_particles=64, max_contacts=16)
+    return G, P.DeviceParticles.from_host(w.particles) if w.particles.n else None
+
+
+def _one_step_check(w, G, dp):
+    """Compare one more GPU step with one oracle step from the GPU state."""
+    import paper_1901_09745_amd.psclbm as P
+    f0 = G.get_f().cpu().numpy()
+    pc = W.Particles(dp.x.cpu().numpy(), dp.u.cpu().numpy(), dp.omega.cpu().numpy(),
+                     dp.r.cpu().numpy())
+    ref = oracle.Lattice(w.lattice, f0)
+    F_ref, T_ref = ref.step(pc)
+    G.rasterize(dp)
+    G.step(1)
+    F, T = G.forces()
+    G.sync()
+    f1 = G.get_f().cpu().numpy()
+    assert relerr(f1, ref.f) < 1e-12
+    scale = force_scale(w.lattice, f0, pc)
+    dF = np.abs(F.cpu().numpy() - F_ref).max(axis=1)
+    assert np.all(dF <= 1e-12 * scale + 1e-300)
+    return F_ref
+
+
+def test_2d_workload_full_size():
+    # D2Q9 tau=0.7 1024^2 periodic, 2000 disks, JKR DEM (the benchmarked case)
+    import paper_1901_09745_amd.psclbm as P
+    w = W.c2()
+    print(f"case: {w.description}", flush=True)
+    G, dp = _gpu(w)
+    prm = P.make_dem_params(w.dem)
+    for _ in range(20):
+        G.rasterize(dp)
+        G.step(1)
+        G.dem_step(prm, dp)
+    _one_step_check(w, G, dp)
+
+
+def test_3d_workload_full_size():
+    # D3Q19 tau=0.6 256^3 periodic, 8000 spheres with prescribed velocities
+    import paper_1901_09745_amd.psclbm as P
+    w = W.c3()
+    print(f"case: {w.description}", flush=True)
+    G, dp = _gpu(w)
+    kin = P.make_dem_params(w.dem)
+    for _ in range(3):
+        G.rasterize(dp)
+        G.step(1)
+        G.dem_step(kin, dp)
+    F = _one_step_check(w, G, dp)
+    assert np.abs(F).max() > 0
+
+
+def test_channel_with_disks_full_run():
+    # D2Q9 tau=0.8 512x256, equilibrium inlet u=0.02 / outlet, 64 fixed disks
+    # r=8, 4000 steps: full-run FP64 parity
+    w = W.c4()
+    print(f"case: {w.description}", flush=True)
+    G, dp = _gpu(w)
+    G.rasterize(dp)
+    G.step(w.steps)
+    F, _ = G.forces()
+    G.sync()
+    ref = oracle.Lattice(w.lattice)
+    for _ in range(w.steps):
+        F_ref, _ = ref.step(w.particles)
+    f = G.get_f().cpu().numpy()
+    assert relerr(f, ref.f) < 1e-12
+    assert np.abs(F.cpu().numpy() - F_ref).max() < 1e-10 * np.abs(F_ref).max()
+
+
+def test_2d_workload_fp32_storage_limit_is_not_hit():
+    # the largest configured lattice of each form fits the 32-bit per-direction
+    # addressing and the workspace accounting
+    import paper_1901_09745_amd.psclbm as P
+    for w, q in ((W.c2(scale=0.25), 9), (W.c3(scale=0.25), 19)):
+        for form in ("fp64", "fp32", "fp16"):
+            cfg = P.make_config(w.lattice, form, w.particles.n, 12.0, 64)
+            assert P.psclbm_workspace_bytes(cfg) > 0
