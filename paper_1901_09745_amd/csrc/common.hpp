@@ -175,6 +175,35 @@ struct psclbm_ctx {
 };
 
 namespace psclbm {
+// Sum of a double over the 64 lanes of a wave with DPP lane moves (no LDS
+// traffic): pairs and quads by quad permutes, rows of 16 by row shifts, then
+// row broadcasts 15 and 31 carry the row totals up to lane 63, whose value is
+// read back as a wave-uniform scalar.  Every lane of the wave must be active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
+  return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x114>(v);  // row_shr:4
+  v += dpp_move<0x118>(v);  // row_shr:8
+  v += dpp_move<0x142>(v);  // row_bcast:15
+  v += dpp_move<0x143>(v);  // row_bcast:31
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+  return __hiloint2double(hi, lo);
+}
+
+// Lanes of the wave below this one whose bit is set in mask.
+__device__ __forceinline__ int lanes_below(unsigned long long mask) {
+  return (int)__builtin_amdgcn_mbcnt_hi((unsigned)(mask >> 32),
+                                        __builtin_amdgcn_mbcnt_lo((unsigned)mask, 0u));
+}
+
 // Launchers (return a psclbm error code).
 int launch_init_equilibrium(psclbm_ctx* c, const double* rho, const double* u);
 int launch_set_f(psclbm_ctx* c, const double* f);

@@ -133,89 +133,126 @@ __device__ inline bool was_in_contact(const int* ids, int n, int id) {
   return false;
 }
 
-__global__ void __launch_bounds__(128) k_dem_contacts(DemArgs d, const double* x, const double* u,
+// One wave per particle.  The lanes stride over the (neighbour bin, slot)
+// candidates and the walls; contacts are compacted into the new contact list
+// with a ballot, and the contact force is summed over the wave.
+__global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, const double* x, const double* u,
                                                       const double* r) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= d.n) return;
-  const double xi[3] = {x[3 * i], x[3 * i + 1], d.three_d ? x[3 * i + 2] : 0.0};
-  const double ui[3] = {u[3 * i], u[3 * i + 1], d.three_d ? u[3 * i + 2] : 0.0};
+  const int i = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = (int)(threadIdx.x & 63);
+  if (i >= d.n) return;  // uniform over the wave
+  const int D = d.three_d ? 3 : 2;
+  const double xi0 = x[3 * i], xi1 = x[3 * i + 1], xi2 = d.three_d ? x[3 * i + 2] : 0.0;
+  const double ui0 = u[3 * i], ui1 = u[3 * i + 1], ui2 = d.three_d ? u[3 * i + 2] : 0.0;
   const double ri = r[i];
   const int pn = d.prev_n[i];
   const int* prev = d.prev_id + (size_t)i * d.max_contacts;
   int* next = d.next_id + (size_t)i * d.max_contacts;
-  int cnt = 0;
   double fs0 = 0.0, fs1 = 0.0, fs2 = 0.0;
-  const int D = d.three_d ? 3 : 2;
+  int cnt = 0;  // uniform over the wave
+
   // walls of non-periodic axes: flat bodies at -1/2 and L-1/2 (1/R = 1/r)
-  for (int face = 0; face < 2 * D; ++face) {
-    const int a = face / 2;
-    if (d.periodic[a]) continue;
-    const double dist = (face % 2 == 0) ? xi[a] + 0.5 : (d.L[a] - 0.5) - xi[a];
-    const double delta = ri - dist;
-    const int id = -1 - face;
-    if (delta < 0.0 && !was_in_contact(prev, pn, id)) continue;
-    double dC;
-    const double F = jkr_force(ri, d.E, d.gamma, delta, &dC);
-    if (delta >= 0.0 || delta > -dC) {
-      const double sgn = (face % 2 == 0) ? -1.0 : 1.0;  // normal towards the wall
-      const double vrn = -ui[a] * sgn;
-      const double fm = (-F + d.eta_n * vrn) * sgn;
-      if (a == 0) fs0 += fm;
-      else if (a == 1) fs1 += fm;
-      else fs2 += fm;
-      if (cnt < d.max_contacts) next[cnt] = id;
-      ++cnt;
+  {
+    bool have = false;
+    int id = 0;
+    if (lane < 2 * D) {
+      const int face = lane, a = face / 2;
+      if (!d.periodic[a]) {
+        const double xa = a == 0 ? xi0 : (a == 1 ? xi1 : xi2);
+        const double ua = a == 0 ? ui0 : (a == 1 ? ui1 : ui2);
+        const double dist = (face % 2 == 0) ? xa + 0.5 : (d.L[a] - 0.5) - xa;
+        const double delta = ri - dist;
+        id = -1 - face;
+        if (delta >= 0.0 || was_in_contact(prev, pn, id)) {
+          double dC;
+          const double F = jkr_force(ri, d.E, d.gamma, delta, &dC);
+          if (delta >= 0.0 || delta > -dC) {
+            const double sgn = (face % 2 == 0) ? -1.0 : 1.0;  // normal towards the wall
+            const double fm = (-F + d.eta_n * (-ua * sgn)) * sgn;
+            if (a == 0) fs0 += fm;
+            else if (a == 1) fs1 += fm;
+            else fs2 += fm;
+            have = true;
+          }
+        }
+      }
     }
+    const unsigned long long m = __ballot(have);
+    if (have) {
+      const int pos = cnt + lanes_below(m);
+      if (pos < d.max_contacts) next[pos] = id;
+    }
+    cnt += __popcll(m);
   }
+
   // particle pairs from the neighbouring bins
   int ox[3], oy[3], oz[3];
-  const int bx = bin_coord(xi[0], 0, d), by = bin_coord(xi[1], 1, d);
-  const int bz = d.three_d ? bin_coord(xi[2], 2, d) : 0;
+  const int bx = bin_coord(xi0, 0, d), by = bin_coord(xi1, 1, d);
+  const int bz = d.three_d ? bin_coord(xi2, 2, d) : 0;
   const int nxo = axis_offsets(bx, 0, d, ox);
   const int nyo = axis_offsets(by, 1, d, oy);
   int nzo = 1;
   oz[0] = 0;
   if (d.three_d) nzo = axis_offsets(bz, 2, d, oz);
-  for (int kz = 0; kz < nzo; ++kz)
-    for (int ky = 0; ky < nyo; ++ky)
-      for (int kx = 0; kx < nxo; ++kx) {
-        const int b = ox[kx] + d.nbin[0] * (oy[ky] + d.nbin[1] * oz[kz]);
-        int m = d.bin_count[b];
-        if (m > d.bin_cap) m = d.bin_cap;
-        for (int t = 0; t < m; ++t) {
-          const int j = d.bin_list[(size_t)b * d.bin_cap + t];
-          if (j == i) continue;
-          const double dv0 = min_img(x[3 * j] - xi[0], d.periodic[0], d.L[0]);
-          const double dv1 = min_img(x[3 * j + 1] - xi[1], d.periodic[1], d.L[1]);
-          const double dv2 = d.three_d ? min_img(x[3 * j + 2] - xi[2], d.periodic[2], d.L[2]) : 0.0;
-          const double dist = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
-          const double rj = r[j];
-          const double delta = ri + rj - dist;
-          if (delta < 0.0 && !was_in_contact(prev, pn, j)) continue;
+  const int nb = nxo * nyo * nzo;
+  for (int base = 0;; base += 64) {
+    const int c = base + lane;
+    const int k = c % nb, slot = c / nb;
+    const int kx = k % nxo, ky = (k / nxo) % nyo, kz = k / (nxo * nyo);
+    const int b = ox[kx] + d.nbin[0] * (oy[ky] + d.nbin[1] * oz[kz]);
+    int mcount = d.bin_count[b];
+    if (mcount > d.bin_cap) mcount = d.bin_cap;
+    const bool valid = slot < mcount;
+    if (!__any(valid)) break;
+    bool have = false;
+    int id = 0;
+    if (valid) {
+      const int j = d.bin_list[(size_t)b * d.bin_cap + slot];
+      if (j != i) {
+        const double dv0 = min_img(x[3 * j] - xi0, d.periodic[0], d.L[0]);
+        const double dv1 = min_img(x[3 * j + 1] - xi1, d.periodic[1], d.L[1]);
+        const double dv2 = d.three_d ? min_img(x[3 * j + 2] - xi2, d.periodic[2], d.L[2]) : 0.0;
+        const double dist = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
+        const double rj = r[j];
+        const double delta = ri + rj - dist;
+        if (delta >= 0.0 || was_in_contact(prev, pn, j)) {
           const double Reff = 1.0 / (1.0 / ri + 1.0 / rj);
           double dC;
           const double F = jkr_force(Reff, d.E, d.gamma, delta, &dC);
           if (delta >= 0.0 || delta > -dC) {
             const double n0 = dv0 / dist, n1 = dv1 / dist, n2 = dv2 / dist;
-            double vrn = (u[3 * j] - ui[0]) * n0 + (u[3 * j + 1] - ui[1]) * n1;
-            if (d.three_d) vrn += (u[3 * j + 2] - ui[2]) * n2;
+            double vrn = (u[3 * j] - ui0) * n0 + (u[3 * j + 1] - ui1) * n1;
+            if (d.three_d) vrn += (u[3 * j + 2] - ui2) * n2;
             const double fm = -F + d.eta_n * vrn;
             fs0 += fm * n0;
             fs1 += fm * n1;
             fs2 += fm * n2;
-            if (cnt < d.max_contacts) next[cnt] = j;
-            ++cnt;
+            have = true;
+            id = j;
           }
         }
       }
-  if (cnt > d.max_contacts) {
-    atomicOr(d.err, ERR_CONTACTS);
-    cnt = d.max_contacts;
+    }
+    const unsigned long long m = __ballot(have);
+    if (have) {
+      const int pos = cnt + lanes_below(m);
+      if (pos < d.max_contacts) next[pos] = id;
+    }
+    cnt += __popcll(m);
   }
-  d.fc[3 * i] = fs0;
-  d.fc[3 * i + 1] = fs1;
-  d.fc[3 * i + 2] = fs2;
-  d.next_n[i] = cnt;
+  fs0 = wave_sum(fs0);
+  fs1 = wave_sum(fs1);
+  fs2 = wave_sum(fs2);
+  if (lane == 0) {
+    if (cnt > d.max_contacts) {
+      atomicOr(d.err, ERR_CONTACTS);
+      cnt = d.max_contacts;
+    }
+    d.fc[3 * i] = fs0;
+    d.fc[3 * i + 1] = fs1;
+    d.fc[3 * i + 2] = fs2;
+    d.next_n[i] = cnt;
+  }
 }
 
 struct IntArgs {
@@ -348,7 +385,7 @@ int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doub
     d.next_n = c->contact_n[c->contact_cur ^ 1];
     d.next_id = c->contact_id[c->contact_cur ^ 1];
     k_dem_bin<<<blocks, 128, 0, c->stream>>>(d, x);
-    k_dem_contacts<<<blocks, 128, 0, c->stream>>>(d, x, u, r);
+    k_dem_contacts<<<(n + 3) / 4, 256, 0, c->stream>>>(d, x, u, r);
     k_dem_integrate<<<iblocks, 128, 0, c->stream>>>(ia, x, u, w, r, F, T, c->fcontact);
     int rc = hip_ok(hipGetLastError());
     if (rc) return rc;

@@ -305,28 +305,6 @@ __device__ inline void collect_slots(const Geom& g, int x0, int x, int y, int z,
   }
 }
 
-// Sum of a double over the 64 lanes of a wave with DPP lane moves (no LDS
-// traffic): pairs and quads by quad permutes, rows of 16 by row shifts, then
-// row broadcasts 15 and 31 carry the row totals up to lane 63, whose value is
-// read back as a wave-uniform scalar.  Every lane of the wave must be active.
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double v) {
-  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, true);
-  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, true);
-  return __hiloint2double(hi, lo);
-}
-
-__device__ __forceinline__ double wave_sum(double v) {
-  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
-  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
-  v += dpp_move<0x114>(v);  // row_shr:4
-  v += dpp_move<0x118>(v);  // row_shr:8
-  v += dpp_move<0x142>(v);  // row_bcast:15
-  v += dpp_move<0x143>(v);  // row_bcast:31
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
-  return __hiloint2double(hi, lo);
-}
 
 // Loads the tile's particle list into LDS in ascending particle id (a rank
 // sort; ids in a list are distinct) and clears its force accumulators.
@@ -961,16 +939,22 @@ __device__ inline AxisRuns axis_runs(int lo, int hi, int L, int T, int periodic)
   return r;
 }
 
-__global__ void k_bin(Geom g, int n, double h, const PSnap* snap, int* tile_count, int* tile_list,
-                      int cap, unsigned* err) {
-  const int s = blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= n) return;
+// One wave per particle: the lanes stride over the tiles of the particle's
+// shell box (at most two runs per axis after a periodic wrap).
+__global__ void __launch_bounds__(256) k_bin(Geom g, int n, double h, const PSnap* snap,
+                                             int* tile_count, int* tile_list, int cap,
+                                             unsigned* err) {
+  const int s = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+  const int lane = (int)(threadIdx.x & 63);
+  if (s >= n) return;  // uniform over the wave
   const PSnap P = snap[s];
   if (!(P.r > 0.0)) return;
   const double R = P.r + h;
   const int L[3] = {g.nx, g.ny, g.nz};
   const int T[3] = {TX, TY, TZ};
   AxisRuns runs[3];
+  int la[3], lt[3];
+#pragma unroll
   for (int a = 0; a < 3; ++a) {
     int lo, hi;
     if (a == 2 && g.q == 9) {
@@ -980,25 +964,23 @@ __global__ void k_bin(Geom g, int n, double h, const PSnap* snap, int* tile_coun
       hi = (int)floor(P.x[a] + R);
     }
     runs[a] = axis_runs(lo, hi, L[a], T[a], g.periodic[a]);
+    la[a] = runs[a].a1 >= runs[a].a0 ? runs[a].a1 - runs[a].a0 + 1 : 0;
+    lt[a] = la[a] + (runs[a].b1 >= runs[a].b0 ? runs[a].b1 - runs[a].b0 + 1 : 0);
   }
-  for (int rz = 0; rz < 2; ++rz) {
-    const int z0 = rz ? runs[2].b0 : runs[2].a0, z1 = rz ? runs[2].b1 : runs[2].a1;
-    for (int tz = z0; tz <= z1; ++tz)
-      for (int ry = 0; ry < 2; ++ry) {
-        const int y0 = ry ? runs[1].b0 : runs[1].a0, y1 = ry ? runs[1].b1 : runs[1].a1;
-        for (int ty = y0; ty <= y1; ++ty)
-          for (int rx = 0; rx < 2; ++rx) {
-            const int x0 = rx ? runs[0].b0 : runs[0].a0, x1 = rx ? runs[0].b1 : runs[0].a1;
-            for (int tx = x0; tx <= x1; ++tx) {
-              const int t = tx + g.ntx * (ty + g.nty * tz);
-              const int k = atomicAdd(&tile_count[t], 1);
-              if (k < cap)
-                tile_list[(size_t)t * cap + k] = s;
-              else
-                atomicOr(err, ERR_SLOTS);
-            }
-          }
-      }
+  const int total = lt[0] * lt[1] * lt[2];
+  for (int k = lane; k < total; k += 64) {
+    const int ix = k % lt[0];
+    const int iy = (k / lt[0]) % lt[1];
+    const int iz = k / (lt[0] * lt[1]);
+    const int tx = ix < la[0] ? runs[0].a0 + ix : runs[0].b0 + (ix - la[0]);
+    const int ty = iy < la[1] ? runs[1].a0 + iy : runs[1].b0 + (iy - la[1]);
+    const int tz = iz < la[2] ? runs[2].a0 + iz : runs[2].b0 + (iz - la[2]);
+    const int t = tx + g.ntx * (ty + g.nty * tz);
+    const int slot = atomicAdd(&tile_count[t], 1);
+    if (slot < cap)
+      tile_list[(size_t)t * cap + slot] = s;
+    else
+      atomicOr(err, ERR_SLOTS);
   }
 }
 
@@ -1129,7 +1111,7 @@ int launch_rasterize(psclbm_ctx* c, const psclbm_particles* p) {
     if (rc) return rc;
   }
   if (p->n > 0) {
-    k_bin<<<(p->n + 127) / 128, 128, 0, c->stream>>>(c->geom, p->n, c->cfg.shell_h, c->snap,
+    k_bin<<<(p->n + 3) / 4, 256, 0, c->stream>>>(c->geom, p->n, c->cfg.shell_h, c->snap,
                                                       c->tile_count, c->tile_list,
                                                       c->cfg.max_tile_particles, c->err);
     return hip_ok(hipGetLastError());
