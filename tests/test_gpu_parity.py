@@ -9,49 +9,9 @@ import pytest
 
 import oracle
 import workloads as W
-from helpers import force_scale, gpu_lattice, gpu_run, oracle_run, relerr
+from helpers import CASES, _particles, _print_case, force_scale, gpu_lattice, gpu_run, oracle_run, relerr
 
 pytestmark = pytest.mark.gpu
-
-WALLS_Y = (W.PERIODIC, W.PERIODIC, W.BOUNCE_BACK, W.BOUNCE_BACK, W.PERIODIC, W.PERIODIC)
-
-
-def _print_case(**kw):
-    print("case:", ", ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
-
-
-def _particles(lat, n, rmin, rmax, seed, umax=0.01, wmax=0.002, overlap=False):
-    rng = np.random.default_rng(seed)
-    dim = 2 if lat.q == 9 else 3
-    box = (lat.nx, lat.ny, lat.nz)[:dim]
-    periodic = tuple(lat.periodic(a) for a in range(dim))
-    r = np.sort(rng.uniform(rmin, rmax, n))[::-1]
-    gap = -0.6 * rmin if overlap else 0.3
-    x = W.rsa(rng, r, tuple(float(b) for b in box), periodic, gap=gap, clearance=0.5)
-    u = rng.uniform(-umax, umax, (n, 3))
-    w = rng.uniform(-wmax, wmax, (n, 3))
-    if dim == 2:
-        u[:, 2] = 0
-        w[:, :2] = 0
-        x[:, 2] = 0
-    return W.Particles(x, u, w, r)
-
-
-CASES = {
-    "d2q9_periodic": W.LatticeSpec(q=9, nx=150, ny=70, tau=0.7, force=(1e-5, -3e-6, 0)),
-    "d2q9_walls": W.LatticeSpec(q=9, nx=130, ny=37, tau=0.8, force=(2e-5, 0, 0), faces=WALLS_Y),
-    "d2q9_couette": W.LatticeSpec(q=9, nx=67, ny=29, tau=0.9, faces=(
-        W.PERIODIC, W.PERIODIC, W.MOVING_WALL, W.MOVING_WALL, W.PERIODIC, W.PERIODIC),
-        face_u=((0, 0, 0), (0, 0, 0), (-0.01, 0, 0), (0.02, 0.001, 0), (0, 0, 0), (0, 0, 0))),
-    "d2q9_open": W.LatticeSpec(q=9, nx=100, ny=45, tau=0.8, faces=(
-        W.INLET_EQ, W.OUTLET_EQ, W.BOUNCE_BACK, W.BOUNCE_BACK, W.PERIODIC, W.PERIODIC),
-        face_u=((0.02, 0.0, 0),) + ((0, 0, 0),) * 5),
-    "d3q19_periodic": W.LatticeSpec(q=19, nx=70, ny=21, nz=18, tau=0.6, force=(1e-5, 0, 2e-6)),
-    "d3q19_walls": W.LatticeSpec(q=19, nx=33, ny=26, nz=22, tau=0.65, force=(-1e-5, 0, 0), faces=(
-        W.BOUNCE_BACK, W.MOVING_WALL, W.PERIODIC, W.PERIODIC, W.BOUNCE_BACK, W.BOUNCE_BACK),
-        face_u=((0, 0, 0), (0, 0.01, -0.005), (0, 0, 0), (0, 0, 0), (0, 0, 0), (0, 0, 0))),
-}
-
 
 @pytest.mark.parametrize("name", sorted(CASES))
 @pytest.mark.parametrize("steps", [1, 2, 5])
