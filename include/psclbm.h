@@ -215,6 +215,42 @@ const char* psclbm_strerror(int code);
  * lbm_set_equilibrium (the in-place streaming parity is its low bit). */
 long long lbm_step_count(const psclbm_ctx* ctx);
 
+/* ---- adjoint ------------------------------------------------------------ */
+
+/* Adjoint of one lbm_step (FP64), for gradients of any function J of the
+ * state and of the per-particle forces and torques: the transpose of the
+ * step's Jacobian (Eqs. 1, 3-6, 10, 12-14, Table 1) applied to the given
+ * sensitivities.
+ *   d_f          canonical FP64 state f(t) entering the step (as lbm_get_f
+ *                returned it before the step), Q*N doubles;
+ *   d_lambda_in  dJ/df(t+1), canonical, Q*N doubles;
+ *   d_lambda_out receives dJ/df(t) (through this step), canonical, Q*N
+ *                doubles, must not alias d_lambda_in;
+ *   d_dJ_dF, d_dJ_dT  dJ/dF_s and dJ/dT_s of the forces and torques this step
+ *                produced (3n each, or NULL for zero);
+ *   d_g_x, d_g_u, d_g_omega  += dJ/dX_s, dJ/dU_s, dJ/dOmega_s through this
+ *                step (3n each, or NULL), X entering through the solid
+ *                fractions (Table 1) and the rigid-body velocity and torque
+ *                arms;
+ *   d_g_face_velocity  += dJ/d(face velocity) [6][3] (inlet and moving-wall
+ *                faces), or NULL.
+ * The particles are those of the last psc_rasterize (their state at step t).
+ * The derivative of the Table 1 clamps is taken as zero at their kinks.
+ * Errors: EINVAL, ESTATE (no rasterisation), EHIP. */
+int lbm_step_adjoint(psclbm_ctx* ctx, const double* d_f, const double* d_lambda_in,
+                     double* d_lambda_out, const double* d_dJ_dF, const double* d_dJ_dT,
+                     double* d_g_x, double* d_g_u, double* d_g_omega,
+                     double* d_g_face_velocity);
+
+/* Adjoint of the solid fractions alone (Eqs. 15-18, Table 1): for
+ * sensitivities dJ/deps_{n,s} given per recorded slot in the layout of
+ * psc_get_solid_fraction (d_g_slot_eps[N*kslots], slots in ascending particle
+ * id), adds dJ/dX_s = sum_n dJ/deps_{n,s} (x_n - X_s)/|x_n - X_s| over the
+ * cells on the linear band of Table 1 to d_g_x[3n].  Errors: EINVAL, ESTATE,
+ * EHIP. */
+int psc_rasterize_adjoint(psclbm_ctx* ctx, const double* d_g_slot_eps, int kslots,
+                          double* d_g_x);
+
 #ifdef __cplusplus
 }
 #endif

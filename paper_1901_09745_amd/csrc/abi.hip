@@ -61,7 +61,7 @@ int validate(const psclbm_config* c) {
 }
 
 struct Layout {
-  size_t f, err, scalar, tile_count, tile_list, snap, facc0, facc1, mass_part, outlet_u;
+  size_t f, err, scalar, tile_count, tile_list, snap, facc0, facc1, mass_part, outlet_u, outlet_g;
   size_t bin_count, bin_list, cn0, cn1, cid0, cid1, fcontact, total;
   int ntx, nty, ntz, ntiles;
   long long face_stride;
@@ -118,6 +118,7 @@ Layout plan(const psclbm_config* c) {
   l.facc1 = take(sizeof(double) * 6 * (size_t)(np > 0 ? np : 1));
   l.mass_part = take(sizeof(double) * (size_t)l.ntiles);
   l.outlet_u = take(outlet ? sizeof(double) * 3 * 6 * (size_t)fs : 8);
+  l.outlet_g = take(outlet ? sizeof(double) * 3 * 6 * (size_t)fs : 8);
   const int mc = np > 0 ? c->max_contacts : 1;
   l.bin_count = take(sizeof(int) * nbins);
   l.bin_list = take(sizeof(int) * nbins * l.bin_cap * (np > 0 ? 1 : 0));
@@ -200,6 +201,7 @@ int lbm_init(const psclbm_config* cfg, void* d_workspace, size_t bytes, void* hi
   c->mass_part = reinterpret_cast<double*>(base + l.mass_part);
   c->nblocks = l.ntiles;
   c->outlet_u = reinterpret_cast<double*>(base + l.outlet_u);
+  c->outlet_g = reinterpret_cast<double*>(base + l.outlet_g);
   c->face_stride = l.face_stride;
   for (int a = 0; a < 3; ++a) {
     c->nbin[a] = l.nbin[a];
@@ -349,6 +351,25 @@ int psclbm_sync(psclbm_ctx* ctx) {
 }
 
 long long lbm_step_count(const psclbm_ctx* ctx) { return ctx ? ctx->steps : -1; }
+
+int lbm_step_adjoint(psclbm_ctx* ctx, const double* d_f, const double* d_lambda_in,
+                     double* d_lambda_out, const double* d_dJ_dF, const double* d_dJ_dT,
+                     double* d_g_x, double* d_g_u, double* d_g_omega,
+                     double* d_g_face_velocity) {
+  if (!ctx || !d_f || !d_lambda_in || !d_lambda_out) return PSCLBM_EINVAL;
+  if (d_lambda_in == d_lambda_out) return PSCLBM_EINVAL;
+  if (!ctx->rasterized) return PSCLBM_ESTATE;
+  return launch_adjoint(ctx, d_f, d_lambda_in, d_lambda_out, d_dJ_dF, d_dJ_dT, d_g_x, d_g_u,
+                        d_g_omega, d_g_face_velocity);
+}
+
+int psc_rasterize_adjoint(psclbm_ctx* ctx, const double* d_g_slot_eps, int kslots,
+                          double* d_g_x) {
+  if (!ctx || !d_g_slot_eps || !d_g_x || kslots < 1) return PSCLBM_EINVAL;
+  if (!ctx->rasterized) return PSCLBM_ESTATE;
+  if (ctx->np == 0) return PSCLBM_OK;
+  return launch_rasterize_adjoint(ctx, d_g_slot_eps, kslots, d_g_x);
+}
 
 const char* psclbm_strerror(int code) {
   switch (code) {

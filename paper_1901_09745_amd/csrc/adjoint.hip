@@ -1,0 +1,579 @@
+// Hand-written adjoint of one PSC-LBM step (FP64), the transpose of the
+// per-cell Jacobian of the step of lbm.hip applied to a given sensitivity.
+//
+// Notation per cell n (all FP64): f the state entering the step (after the
+// inlet / outlet reset), lam*_i = dJ/df*_i the sensitivity of the post-
+// collision population (read where that population streams to), B_n and the
+// per-particle shares B_s (Eq. 13 / Table 1 Step 5), and
+//   f*_i = f_i - (1 - B_n) [w (f_i - f^eq_i) - F_i]
+//          + sum_s B_s [f_{-i} - f^eq_{-i}(rho,u) + f^eq_i(rho,u_s) - f_i]   (Eqs. 10, 12)
+//   m_s  = B_s [rho (u_s - u) + F],  F_s -= m_s,  T_s -= r_s x m_s       (Eq. 14)
+// with w = 1/tau, rho = sum f, u = (sum f e + F/2)/rho (Eq. 5),
+// u_s = U_s + Omega_s x r_s, r_s = x_n - X_s (nearest image), and the Table 1
+// fraction eps_s = V_a(r) + 1/2 - |r_s| inside its linear band.
+// Given dJ/dF_s and dJ/dT_s (the seeds of this step), q_s = dJ/dm_s =
+// -dJ/dF_s - dJ/dT_s x r_s.  Then
+//   lam_j = alpha lam*_j + B_n lam*_{-j} + kappa + a_rho + a_u . (e_j - u)/rho
+// with alpha = 1 - (1 - B_n) w - B_n, kappa the moving-wall term and
+//   a_rho = sum_i lam*_i [(1-B_n) w f^eq_i - B_n f^eq_{-i} + sum_s B_s f^eq_i(u_s)] / rho
+//           + sum_s B_s q_s . (u_s - u)
+//   a_u   = sum_i lam*_i [(1-B_n) w df^eq_i/du - B_n df^eq_{-i}/du + (1-B_n) dF_i/du]
+//           - sum_s B_s rho q_s
+// and for each covering particle
+//   dJ/du_s = B_s [sum_i lam*_i rho w_i (3 e_i + 9 (e_i.u_s) e_i - 3 u_s) + rho q_s]
+//   dJ/deps_t = B_n'(S) (lam* . P) + c(S) G_t + c'(S) sum_s eps_s G_s,
+//     P_i = w (f_i - f^eq_i) - F_i,  G_s = lam* . Omega^s + q_s . [rho (u_s - u) + F],
+//     c = tm/den, c' = tm/den^2 (sum eps <= 1) or c = 1/S, c' = -1/S^2,
+//     B_n' = tm (1 + tm)/den^2 (sum eps < 1) else 0, tm = tau - 1/2, den = 1 - S + tm,
+//   dJ/dX_s += dJ/deps_s r_s/|r_s| (linear band only) - (dJ/du_s x Omega_s + dJ/dT_s x m_s)
+//   dJ/dU_s += dJ/du_s,  dJ/dOmega_s += r_s x dJ/du_s.
+// Inlet cells (reset to f^eq(rho0, u_in)) pass lam through df^eq/du_in to the
+// face velocity and have zero sensitivity of their own state; outlet cells
+// pass it through u of their interior neighbour (a second kernel).  Moving
+// walls pass lam of the reflected population to the wall velocity.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "common.hpp"
+#include "tiles.hpp"
+
+namespace psclbm {
+
+struct AdjArgs {
+  Geom g;
+  double tau, omega;
+  double force[3];
+  double h;
+  int np, cap;
+  const int* tile_count;
+  const int* tile_list;
+  const PSnap* snap;
+  const double* f;        // canonical FP64 state entering the step
+  const double* lam_in;   // dJ/df(t+1), canonical
+  double* lam_out;        // dJ/df(t), canonical
+  const double* gF;       // dJ/dF_s of this step [3n] or null
+  const double* gT;       // dJ/dT_s of this step [3n] or null
+  double* gX;             // += [3n]
+  double* gU;             // += [3n]
+  double* gW;             // += [3n]
+  double* gface;          // += [6][3]
+  const double* outlet_u; // [6][face cells][3], velocity of each outlet's neighbour
+  double* outlet_g;       // [6][face cells][3], dJ/du of that velocity
+  long long face_stride;
+  unsigned inlet_mask, outlet_mask, moving_mask;
+};
+
+template <int Q>
+__device__ __forceinline__ double feq_i(int i, double rho, double ux, double uy, double uz,
+                                        double uu) {
+  using L = Lattice<Q>;
+  const double eu = L::ex(i) * ux + L::ey(i) * uy + L::ez(i) * uz;
+  return rho * L::w(i) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+}
+
+template <int Q, bool WALLS>
+__global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
+  using L = Lattice<Q>;
+  constexpr int D = L::D;
+  extern __shared__ double smem_d[];
+  const Geom& G = a.g;
+  const int tile = blockIdx.x;
+  LdsEntry* lds = reinterpret_cast<LdsEntry*>(smem_d);
+  double* acc = reinterpret_cast<double*>(lds + a.cap);  // [cap][9]
+  const int cnt = load_tile_list(a.tile_count, a.tile_list, a.cap, a.snap, tile, lds, nullptr,
+                                 a.np);
+  if (cnt > 0) {
+    for (int k = threadIdx.x; k < 9 * cnt; k += BLOCK) acc[k] = 0.0;
+    __syncthreads();
+  }
+  int x0, y0, z0;
+  tile_origin(G, tile, x0, y0, z0);
+  const int x = x0 + (int)(threadIdx.x % TX);
+  const int y = y0 + (int)((threadIdx.x / TX) % TY);
+  const int z = z0 + (int)(threadIdx.x / (TX * TY));
+  const bool active = x < G.nx && y < G.ny && z < G.nz;
+  const unsigned N = (unsigned)G.N;
+  const unsigned n = (unsigned)x + (unsigned)G.nx * ((unsigned)y + (unsigned)G.ny * (unsigned)z);
+  Slots s;
+  s.n = 0;
+  if (cnt > 0) collect_slots<D>(G, x0, x, y, z, active, lds, cnt, a.h, s, nullptr);
+
+  if (active) {
+    Dims d;
+    d.nx = G.nx; d.ny = G.ny; d.nz = G.nz;
+    d.px = G.periodic[0]; d.py = G.periodic[1]; d.pz = G.periodic[2];
+    d.sy = (unsigned)G.nx;
+    d.sz = (unsigned)G.nx * (unsigned)G.ny;
+    const double rho0 = G.rho0;
+    const double F0 = a.force[0], F1 = a.force[1], F2 = a.force[2];
+    double f[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) f[i] = a.f[(size_t)i * N + n];
+
+    // inlet / outlet reset (as in the forward: outlets first, an inlet wins)
+    int reset = 0, rface = 0;
+    double ub0 = 0.0, ub1 = 0.0, ub2 = 0.0;
+    if (a.inlet_mask | a.outlet_mask) {
+#pragma unroll
+      for (int fc = 0; fc < 6; ++fc) {
+        const bool on = fc == 0 ? x == 0 : fc == 1 ? x == d.nx - 1 : fc == 2 ? y == 0
+                      : fc == 3 ? y == d.ny - 1 : fc == 4 ? z == 0 : z == d.nz - 1;
+        if (((a.outlet_mask >> fc) & 1u) && on) {
+          const unsigned k = fc < 2 ? (unsigned)y + (unsigned)d.ny * z
+                                    : (fc < 4 ? (unsigned)x + (unsigned)d.nx * z
+                                              : (unsigned)x + (unsigned)d.nx * y);
+          const double* o = a.outlet_u + ((size_t)fc * a.face_stride + k) * 3;
+          ub0 = o[0]; ub1 = o[1]; ub2 = o[2];
+          reset = 2;
+          rface = fc;
+        }
+      }
+#pragma unroll
+      for (int fc = 0; fc < 6; ++fc) {
+        const bool on = fc == 0 ? x == 0 : fc == 1 ? x == d.nx - 1 : fc == 2 ? y == 0
+                      : fc == 3 ? y == d.ny - 1 : fc == 4 ? z == 0 : z == d.nz - 1;
+        if (((a.inlet_mask >> fc) & 1u) && on) {
+          ub0 = G.face_u[fc][0]; ub1 = G.face_u[fc][1]; ub2 = G.face_u[fc][2];
+          reset = 1;
+          rface = fc;
+        }
+      }
+      if (reset) {
+        const double uq = ub0 * ub0 + ub1 * ub1 + ub2 * ub2;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) f[i] = feq_i<Q>(i, rho0, ub0, ub1, ub2, uq);
+      }
+    }
+
+    // sensitivity of each post-collision population: where it streams to
+    double ls[Q];
+    double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      rho += f[i];
+      jx += L::ex(i) * f[i];
+      jy += L::ey(i) * f[i];
+      jz += L::ez(i) * f[i];
+    }
+    double kappa = 0.0;  // moving-wall term -6 w_i rho (e_i . u_w): d/df_j = -6 w_i (e_i . u_w)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      unsigned m = n;
+      const unsigned out = i == 0 ? 0u : link<WALLS>(d, x, y, z, L::ex(i), L::ey(i), L::ez(i), n, m);
+      if (!out) {
+        ls[i] = a.lam_in[(size_t)i * N + m];
+      } else {
+        ls[i] = a.lam_in[(size_t)L::opp(i) * N + n];
+        const unsigned mw = out & a.moving_mask;
+        if (mw) {
+          double uw0 = 0.0, uw1 = 0.0, uw2 = 0.0;
+#pragma unroll
+          for (int fc = 0; fc < 6; ++fc)
+            if ((mw >> fc) & 1u) {
+              uw0 += G.face_u[fc][0];
+              uw1 += G.face_u[fc][1];
+              uw2 += G.face_u[fc][2];
+            }
+          kappa -= 6.0 * L::w(i) * (L::ex(i) * uw0 + L::ey(i) * uw1 + L::ez(i) * uw2) * ls[i];
+          // wall velocity: d/du_w of -6 w_i rho (e_i . u_w)
+          if (a.gface) {
+            const double cw = -6.0 * L::w(i) * rho * ls[i];
+#pragma unroll
+            for (int fc = 0; fc < 6; ++fc)
+              if ((mw >> fc) & 1u) {
+                if (L::ex(i)) atomicAdd(a.gface + 3 * fc, cw * L::ex(i));
+                if (L::ey(i)) atomicAdd(a.gface + 3 * fc + 1, cw * L::ey(i));
+                if (L::ez(i)) atomicAdd(a.gface + 3 * fc + 2, cw * L::ez(i));
+              }
+          }
+        }
+      }
+    }
+
+    const double ux = (jx + 0.5 * F0) / rho, uy = (jy + 0.5 * F1) / rho, uz = (jz + 0.5 * F2) / rho;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    const double w = a.omega;
+    const double kg = 1.0 - 0.5 * w;
+
+    // weights
+    double S = 0.0;
+#pragma unroll
+    for (int k = 0; k < KSLOTS; ++k)
+      if (k < s.n) S += s.eps[k];
+    const double tm = a.tau - 0.5;
+    const double en = S < 1.0 ? S : 1.0;
+    const double den = (1.0 - en) + tm;
+    const double Bn = s.n > 0 ? en * tm / den : 0.0;
+    const double c = S <= 1.0 ? tm / den : 1.0 / S;
+    const double cp = S <= 1.0 ? tm / (den * den) : -1.0 / (S * S);
+    const double Bnp = S < 1.0 ? tm * (1.0 + tm) / (den * den) : 0.0;
+
+    // base adjoint terms
+    double ar = 0.0, aux = 0.0, auy = 0.0, auz = 0.0, LP = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int o = L::opp(i);
+      const double ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
+      const double eu = ex * ux + ey * uy + ez * uz;
+      const double fe = rho * L::w(i) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+      const double eF = ex * F0 + ey * F1 + ez * F2;
+      const double Fi = kg * L::w(i) * (3.0 * (eF - (ux * F0 + uy * F1 + uz * F2)) + 9.0 * eu * eF);
+      LP += ls[i] * (w * (f[i] - fe) - Fi);
+      // coefficient of f^eq_i: (1-B_n) w lam*_i - B_n lam*_{-i}
+      const double cf = (1.0 - Bn) * w * ls[i] - Bn * ls[o];
+      ar += cf * fe / rho;
+      // df^eq_i/du = rho w_i (3 e + 9 (e.u) e - 3 u)
+      const double rw = rho * L::w(i);
+      aux += cf * rw * (3.0 * ex + 9.0 * eu * ex - 3.0 * ux);
+      auy += cf * rw * (3.0 * ey + 9.0 * eu * ey - 3.0 * uy);
+      auz += cf * rw * (3.0 * ez + 9.0 * eu * ez - 3.0 * uz);
+      // dF_i/du = k w_i (-3 F + 9 (e.F) e)
+      const double cF = (1.0 - Bn) * ls[i] * kg * L::w(i);
+      aux += cF * (-3.0 * F0 + 9.0 * eF * ex);
+      auy += cF * (-3.0 * F1 + 9.0 * eF * ey);
+      auz += cF * (-3.0 * F2 + 9.0 * eF * ez);
+    }
+
+    // covering particles
+    double Gk[KSLOTS], Ak[KSLOTS][3], Rk[KSLOTS][3], Mk[KSLOTS][3], SG = 0.0;
+#pragma unroll
+    for (int k = 0; k < KSLOTS; ++k) {
+      Gk[k] = 0.0;
+      for (int t = 0; t < 3; ++t) Ak[k][t] = Rk[k][t] = Mk[k][t] = 0.0;
+      if (k >= s.n) continue;
+      const LdsEntry& P = lds[s.e[k]];
+      const double rx = min_image((double)x - P.x, d.px, d.nx);
+      const double ry = min_image((double)y - P.y, d.py, d.ny);
+      const double rz = D == 3 ? min_image((double)z - P.z, d.pz, d.nz) : 0.0;
+      const double usx = P.u[0] + P.w[1] * rz - P.w[2] * ry;
+      const double usy = P.u[1] + P.w[2] * rx - P.w[0] * rz;
+      const double usz = P.u[2] + P.w[0] * ry - P.w[1] * rx;
+      const double us2 = usx * usx + usy * usy + usz * usz;
+      const double Bs = s.eps[k] * c;
+      // q = dJ/dm = -dJ/dF - dJ/dT x r
+      double qx = 0.0, qy = 0.0, qz = 0.0;
+      const int id = s.id[k];
+      if (a.gF) {
+        qx -= a.gF[3 * id];
+        qy -= a.gF[3 * id + 1];
+        qz -= a.gF[3 * id + 2];
+      }
+      double tx = 0.0, ty = 0.0, tz = 0.0;
+      if (a.gT) {
+        tx = a.gT[3 * id];
+        ty = a.gT[3 * id + 1];
+        tz = a.gT[3 * id + 2];
+        qx -= ty * rz - tz * ry;
+        qy -= tz * rx - tx * rz;
+        qz -= tx * ry - ty * rx;
+      }
+      const double Mx = rho * (usx - ux) + F0, My = rho * (usy - uy) + F1, Mz = rho * (usz - uz) + F2;
+      double LO = 0.0, Lfs = 0.0, dsx = 0.0, dsy = 0.0, dsz = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const int o = L::opp(i);
+        const double ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
+        const double eu_o = -(ex * ux + ey * uy + ez * uz);
+        const double fe_o = rho * L::w(o) * (1.0 + 3.0 * eu_o + 4.5 * eu_o * eu_o - 1.5 * uu);
+        const double eus = ex * usx + ey * usy + ez * usz;
+        const double fs = rho * L::w(i) * (1.0 + 3.0 * eus + 4.5 * eus * eus - 1.5 * us2);
+        LO += ls[i] * (f[o] - fe_o + fs - f[i]);
+        Lfs += ls[i] * fs;
+        const double rw = ls[i] * rho * L::w(i);
+        dsx += rw * (3.0 * ex + 9.0 * eus * ex - 3.0 * usx);
+        dsy += rw * (3.0 * ey + 9.0 * eus * ey - 3.0 * usy);
+        dsz += rw * (3.0 * ez + 9.0 * eus * ez - 3.0 * usz);
+      }
+      Gk[k] = LO + qx * Mx + qy * My + qz * Mz;
+      SG += s.eps[k] * Gk[k];
+      ar += Bs * Lfs / rho + Bs * (qx * (usx - ux) + qy * (usy - uy) + qz * (usz - uz));
+      aux -= Bs * rho * qx;
+      auy -= Bs * rho * qy;
+      auz -= Bs * rho * qz;
+      Ak[k][0] = Bs * (dsx + rho * qx);
+      Ak[k][1] = Bs * (dsy + rho * qy);
+      Ak[k][2] = Bs * (dsz + rho * qz);
+      Rk[k][0] = rx;
+      Rk[k][1] = ry;
+      Rk[k][2] = rz;
+      // m x dJ/dT term of dJ/dr: dJ/dT x m
+      const double mx = Bs * Mx, my = Bs * My, mz = Bs * Mz;
+      Mk[k][0] = ty * mz - tz * my;
+      Mk[k][1] = tz * mx - tx * mz;
+      Mk[k][2] = tx * my - ty * mx;
+    }
+
+    // particle gradients
+#pragma unroll
+    for (int k = 0; k < KSLOTS; ++k) {
+      if (k >= s.n) continue;
+      const LdsEntry& P = lds[s.e[k]];
+      const double dJde = Bnp * LP + c * Gk[k] + cp * SG;
+      const double rx = Rk[k][0], ry = Rk[k][1], rz = Rk[k][2];
+      const double dist = sqrt(rx * rx + ry * ry + rz * rz);
+      // d eps / d X = r / |r| on the linear band of Table 1 (zero when clamped)
+      const double lin = P.cs - dist;
+      const bool band = dist < P.r + a.h && dist > P.r - a.h && lin > 0.0 && lin < 1.0;
+      const double gd = band ? dJde / dist : 0.0;
+      const double ax = Ak[k][0], ay = Ak[k][1], az = Ak[k][2];
+      // dJ/dr from u_s = U + Omega x r: dJ/du_s x Omega
+      const double cx = ay * P.w[2] - az * P.w[1];
+      const double cy = az * P.w[0] - ax * P.w[2];
+      const double cz = ax * P.w[1] - ay * P.w[0];
+      double* ac = acc + 9 * s.e[k];
+      atomicAdd(ac + 0, gd * rx - (cx + Mk[k][0]));
+      atomicAdd(ac + 1, gd * ry - (cy + Mk[k][1]));
+      atomicAdd(ac + 3, ax);
+      atomicAdd(ac + 4, ay);
+      if constexpr (D == 3) {
+        atomicAdd(ac + 2, gd * rz - (cz + Mk[k][2]));
+        atomicAdd(ac + 5, az);
+        atomicAdd(ac + 6, ry * az - rz * ay);
+        atomicAdd(ac + 7, rz * ax - rx * az);
+      }
+      atomicAdd(ac + 8, rx * ay - ry * ax);
+    }
+
+    // sensitivity of the state entering the step
+    const double alpha = 1.0 - (1.0 - Bn) * w - Bn;
+    double lam[Q];
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const double ex = L::ex(j), ey = L::ey(j), ez = L::ez(j);
+      lam[j] = alpha * ls[j] + Bn * ls[L::opp(j)] + kappa + ar +
+               (aux * (ex - ux) + auy * (ey - uy) + auz * (ez - uz)) / rho;
+    }
+    if (reset) {
+      // f = f^eq(rho0, u_b): dJ/du_b = sum_j lam_j rho0 w_j (3 e_j + 9 (e_j.u_b) e_j - 3 u_b)
+      double g0 = 0.0, g1 = 0.0, g2 = 0.0;
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const double ex = L::ex(j), ey = L::ey(j), ez = L::ez(j);
+        const double eu = ex * ub0 + ey * ub1 + ez * ub2;
+        const double rw = lam[j] * rho0 * L::w(j);
+        g0 += rw * (3.0 * ex + 9.0 * eu * ex - 3.0 * ub0);
+        g1 += rw * (3.0 * ey + 9.0 * eu * ey - 3.0 * ub1);
+        g2 += rw * (3.0 * ez + 9.0 * eu * ez - 3.0 * ub2);
+        lam[j] = 0.0;
+      }
+      if (reset == 1) {
+        if (a.gface) {
+          atomicAdd(a.gface + 3 * rface, g0);
+          atomicAdd(a.gface + 3 * rface + 1, g1);
+          atomicAdd(a.gface + 3 * rface + 2, g2);
+        }
+      } else {
+        const unsigned k = rface < 2 ? (unsigned)y + (unsigned)d.ny * z
+                                     : (rface < 4 ? (unsigned)x + (unsigned)d.nx * z
+                                                  : (unsigned)x + (unsigned)d.nx * y);
+        double* o = a.outlet_g + ((size_t)rface * a.face_stride + k) * 3;
+        o[0] = g0;
+        o[1] = g1;
+        o[2] = g2;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < Q; ++j) a.lam_out[(size_t)j * N + n] = lam[j];
+  }
+
+  // flush the tile's particle gradients
+  __syncthreads();
+  for (int e = threadIdx.x; e < cnt; e += BLOCK) {
+    const double* ac = acc + 9 * e;
+    const int id = lds[e].id;
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      if (a.gX && ac[t] != 0.0) atomicAdd(a.gX + 3 * id + t, ac[t]);
+      if (a.gU && ac[3 + t] != 0.0) atomicAdd(a.gU + 3 * id + t, ac[3 + t]);
+      if (a.gW && ac[6 + t] != 0.0) atomicAdd(a.gW + 3 * id + t, ac[6 + t]);
+    }
+  }
+}
+
+// Velocity (Eq. 5) of each outlet cell's interior neighbour, from a canonical
+// FP64 state.
+__global__ void k_outlet_velocity_canon(Geom g, int face, const double* f, double fx, double fy,
+                                        double fz, double* out, long long stride) {
+  const int ax = face / 2;
+  const int u1 = ax == 0 ? 1 : 0, u2 = ax == 2 ? 1 : 2;
+  const int Ld[3] = {g.nx, g.ny, g.nz};
+  const long long cells = (long long)Ld[u1] * Ld[u2];
+  const int q = g.q;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < cells;
+       k += (long long)gridDim.x * blockDim.x) {
+    int p[3];
+    p[u1] = (int)(k % Ld[u1]);
+    p[u2] = (int)(k / Ld[u1]);
+    p[ax] = (face % 2 == 0) ? 1 : Ld[ax] - 2;
+    const long long m = p[0] + (long long)g.nx * (p[1] + (long long)g.ny * p[2]);
+    double rho = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
+    for (int i = 0; i < q; ++i) {
+      const double fi = f[(size_t)i * g.N + m];
+      const int ex = q == 9 ? Lattice<9>::ex(i) : Lattice<19>::ex(i);
+      const int ey = q == 9 ? Lattice<9>::ey(i) : Lattice<19>::ey(i);
+      const int ez = q == 9 ? Lattice<9>::ez(i) : Lattice<19>::ez(i);
+      rho += fi;
+      j0 += ex * fi;
+      j1 += ey * fi;
+      j2 += ez * fi;
+    }
+    double* o = out + ((size_t)face * stride + k) * 3;
+    o[0] = (j0 + 0.5 * fx) / rho;
+    o[1] = (j1 + 0.5 * fy) / rho;
+    o[2] = (j2 + 0.5 * fz) / rho;
+  }
+}
+
+// Outlet cells: the sensitivity of the reset velocity goes to the interior
+// neighbour's state through u = (sum f e + F/2)/rho: lam_j += g . (e_j - u)/rho.
+template <int Q>
+__global__ void k_outlet_adjoint(Geom g, int face, const double* f, const double* gu,
+                                 double* lam, double fx, double fy, double fz, long long stride) {
+  using L = Lattice<Q>;
+  const int ax = face / 2;
+  const int u1 = ax == 0 ? 1 : 0, u2 = ax == 2 ? 1 : 2;
+  const int Ld[3] = {g.nx, g.ny, g.nz};
+  const long long cells = (long long)Ld[u1] * Ld[u2];
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < cells;
+       k += (long long)gridDim.x * blockDim.x) {
+    int p[3];
+    p[u1] = (int)(k % Ld[u1]);
+    p[u2] = (int)(k / Ld[u1]);
+    p[ax] = (face % 2 == 0) ? 1 : Ld[ax] - 2;
+    const long long m = p[0] + (long long)g.nx * (p[1] + (long long)g.ny * p[2]);
+    double rho = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0;
+    for (int i = 0; i < Q; ++i) {
+      const double fi = f[(size_t)i * g.N + m];
+      rho += fi;
+      j0 += L::ex(i) * fi;
+      j1 += L::ey(i) * fi;
+      j2 += L::ez(i) * fi;
+    }
+    const double ux = (j0 + 0.5 * fx) / rho, uy = (j1 + 0.5 * fy) / rho, uz = (j2 + 0.5 * fz) / rho;
+    const double* gv = gu + ((size_t)face * stride + k) * 3;
+    for (int j = 0; j < Q; ++j)
+      lam[(size_t)j * g.N + m] +=
+          (gv[0] * (L::ex(j) - ux) + gv[1] * (L::ey(j) - uy) + gv[2] * (L::ez(j) - uz)) / rho;
+  }
+}
+
+// Table 1 chain alone: dJ/dX_s += sum_n dJ/deps_{n,s} r/|r| on the linear band,
+// for sensitivities given per recorded slot (the order of psc_get_solid_fraction).
+template <int D>
+__global__ void __launch_bounds__(BLOCK) k_rasterize_adjoint(Geom g, double h, int np, int cap,
+                                                           const int* tile_count,
+                                                           const int* tile_list,
+                                                           const PSnap* snap, const double* gs,
+                                                           int kout, double* gX) {
+  extern __shared__ double smem_d[];
+  LdsEntry* lds = reinterpret_cast<LdsEntry*>(smem_d);
+  const int tile = blockIdx.x;
+  const int cnt = load_tile_list(tile_count, tile_list, cap, snap, tile, lds, nullptr, np);
+  int x0, y0, z0;
+  tile_origin(g, tile, x0, y0, z0);
+  const int x = x0 + (int)(threadIdx.x % TX);
+  const int y = y0 + (int)((threadIdx.x / TX) % TY);
+  const int z = z0 + (int)(threadIdx.x / (TX * TY));
+  const bool active = x < g.nx && y < g.ny && z < g.nz;
+  Slots s;
+  s.n = 0;
+  if (cnt > 0) collect_slots<D>(g, x0, x, y, z, active, lds, cnt, h, s, nullptr);
+  if (!active) return;
+  const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
+  for (int k = 0; k < KSLOTS && k < kout; ++k) {
+    if (k >= s.n) break;
+    const double gk = gs[(size_t)n * kout + k];
+    if (gk == 0.0) continue;
+    const LdsEntry& P = lds[s.e[k]];
+    const double rx = min_image((double)x - P.x, g.periodic[0], g.nx);
+    const double ry = min_image((double)y - P.y, g.periodic[1], g.ny);
+    const double rz = D == 3 ? min_image((double)z - P.z, g.periodic[2], g.nz) : 0.0;
+    const double dist = sqrt(rx * rx + ry * ry + rz * rz);
+    const double lin = P.cs - dist;
+    if (!(dist < P.r + h && dist > P.r - h && lin > 0.0 && lin < 1.0)) continue;
+    const double gd = gk / dist;
+    atomicAdd(gX + 3 * P.id, gd * rx);
+    atomicAdd(gX + 3 * P.id + 1, gd * ry);
+    if (D == 3) atomicAdd(gX + 3 * P.id + 2, gd * rz);
+  }
+}
+
+int launch_adjoint(psclbm_ctx* c, const double* f, const double* lam_in, double* lam_out,
+                   const double* gF, const double* gT, double* gX, double* gU, double* gW,
+                   double* gface) {
+  AdjArgs a;
+  a.g = c->geom;
+  a.tau = c->cfg.tau;
+  a.omega = 1.0 / c->cfg.tau;
+  for (int k = 0; k < 3; ++k) a.force[k] = c->cfg.body_force[k];
+  a.h = c->cfg.shell_h;
+  a.np = c->np;
+  a.cap = c->cfg.max_tile_particles;
+  a.tile_count = c->tile_count;
+  a.tile_list = c->tile_list;
+  a.snap = c->snap;
+  a.f = f;
+  a.lam_in = lam_in;
+  a.lam_out = lam_out;
+  a.gF = gF;
+  a.gT = gT;
+  a.gX = gX;
+  a.gU = gU;
+  a.gW = gW;
+  a.gface = gface;
+  a.outlet_u = c->outlet_u;
+  a.outlet_g = c->outlet_g;
+  a.face_stride = c->face_stride;
+  a.inlet_mask = a.outlet_mask = a.moving_mask = 0;
+  for (int fc = 0; fc < 6; ++fc) {
+    if (c->geom.face[fc] == PSCLBM_INLET_EQ) a.inlet_mask |= 1u << fc;
+    if (c->geom.face[fc] == PSCLBM_OUTLET_EQ) a.outlet_mask |= 1u << fc;
+    if (c->geom.face[fc] == PSCLBM_MOVING_WALL) a.moving_mask |= 1u << fc;
+  }
+  const double* F = c->cfg.body_force;
+  const int fgrid = (int)((c->face_stride + 255) / 256 < 4096 ? (c->face_stride + 255) / 256 : 4096);
+  for (int fc = 0; fc < 6; ++fc) {
+    if (!((a.outlet_mask >> fc) & 1u)) continue;
+    k_outlet_velocity_canon<<<fgrid, 256, 0, c->stream>>>(c->geom, fc, f, F[0], F[1], F[2],
+                                                          c->outlet_u, c->face_stride);
+  }
+  const size_t lds = c->np > 0 ? (sizeof(LdsEntry) + 9 * sizeof(double)) *
+                                     (size_t)c->cfg.max_tile_particles
+                               : 0;
+  const bool walls = !(c->geom.periodic[0] && c->geom.periodic[1] && c->geom.periodic[2]);
+  if (c->geom.q == 9) {
+    if (walls) k_adjoint<9, true><<<c->ntiles, BLOCK, lds, c->stream>>>(a);
+    else k_adjoint<9, false><<<c->ntiles, BLOCK, lds, c->stream>>>(a);
+  } else {
+    if (walls) k_adjoint<19, true><<<c->ntiles, BLOCK, lds, c->stream>>>(a);
+    else k_adjoint<19, false><<<c->ntiles, BLOCK, lds, c->stream>>>(a);
+  }
+  int rc = hip_ok(hipGetLastError());
+  if (rc) return rc;
+  for (int fc = 0; fc < 6; ++fc) {
+    if (!((a.outlet_mask >> fc) & 1u)) continue;
+    if (c->geom.q == 9)
+      k_outlet_adjoint<9><<<fgrid, 256, 0, c->stream>>>(c->geom, fc, f, c->outlet_g, lam_out,
+                                                        F[0], F[1], F[2], c->face_stride);
+    else
+      k_outlet_adjoint<19><<<fgrid, 256, 0, c->stream>>>(c->geom, fc, f, c->outlet_g, lam_out,
+                                                         F[0], F[1], F[2], c->face_stride);
+  }
+  return hip_ok(hipGetLastError());
+}
+
+int launch_rasterize_adjoint(psclbm_ctx* c, const double* gs, int kslots, double* gX) {
+  const size_t lds = (sizeof(LdsEntry) + sizeof(double)) * (size_t)c->cfg.max_tile_particles;
+  if (c->geom.q == 9)
+    k_rasterize_adjoint<2><<<c->ntiles, BLOCK, lds, c->stream>>>(
+        c->geom, c->cfg.shell_h, c->np, c->cfg.max_tile_particles, c->tile_count, c->tile_list,
+        c->snap, gs, kslots, gX);
+  else
+    k_rasterize_adjoint<3><<<c->ntiles, BLOCK, lds, c->stream>>>(
+        c->geom, c->cfg.shell_h, c->np, c->cfg.max_tile_particles, c->tile_count, c->tile_list,
+        c->snap, gs, kslots, gX);
+  return hip_ok(hipGetLastError());
+}
+
+}  // namespace psclbm

@@ -154,6 +154,7 @@ struct psclbm_ctx {
   double* mass_part;
   int nblocks;
   double* outlet_u;
+  double* outlet_g;  // adjoint: dJ/du of each outlet cell's reset velocity
   long long face_stride;
   // DEM
   int nbin[3];
@@ -217,5 +218,9 @@ int launch_zero(psclbm_ctx* c, void* p, size_t bytes);
 int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, double* u,
                     double* w, const double* r, int n, const double* F, const double* T);
 int launch_dem_reset(psclbm_ctx* c);
+int launch_adjoint(psclbm_ctx* c, const double* f, const double* lam_in, double* lam_out,
+                   const double* gF, const double* gT, double* gX, double* gU, double* gW,
+                   double* gface);
+int launch_rasterize_adjoint(psclbm_ctx* c, const double* gs, int kslots, double* gX);
 inline int hip_ok(hipError_t e) { return e == hipSuccess ? PSCLBM_OK : PSCLBM_EHIP; }
 }  // namespace psclbm

@@ -78,6 +78,8 @@ SIGNATURES = {
     "psclbm_sync": (_I, [_VP]),
     "psclbm_strerror": (ctypes.c_char_p, [_I]),
     "lbm_step_count": (ctypes.c_longlong, [_VP]),
+    "lbm_step_adjoint": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "psc_rasterize_adjoint": (_I, [_VP, _VP, _I, _VP]),
 }
 
 _lib = None
@@ -202,6 +204,22 @@ def psclbm_sync(ctx: int) -> None:
 
 def lbm_step_count(ctx: int) -> int:
     return int(load().lbm_step_count(ctx))
+
+
+def lbm_step_adjoint(ctx: int, f: torch.Tensor, lam_in: torch.Tensor, lam_out: torch.Tensor,
+                     dJ_dF: Optional[torch.Tensor] = None, dJ_dT: Optional[torch.Tensor] = None,
+                     g_x: Optional[torch.Tensor] = None, g_u: Optional[torch.Tensor] = None,
+                     g_omega: Optional[torch.Tensor] = None,
+                     g_face: Optional[torch.Tensor] = None) -> None:
+    _check(load().lbm_step_adjoint(ctx, _ptr(f), _ptr(lam_in), _ptr(lam_out), _ptr(dJ_dF),
+                                   _ptr(dJ_dT), _ptr(g_x), _ptr(g_u), _ptr(g_omega),
+                                   _ptr(g_face)), "lbm_step_adjoint")
+
+
+def psc_rasterize_adjoint(ctx: int, g_slot_eps: torch.Tensor, kslots: int,
+                          g_x: torch.Tensor) -> None:
+    _check(load().psc_rasterize_adjoint(ctx, _ptr(g_slot_eps), kslots, _ptr(g_x)),
+           "psc_rasterize_adjoint")
 
 
 # ---------------------------------------------------------------------------
