@@ -17,6 +17,11 @@ The JSON line reports:
   hbm_bound      the 3D workload (D3Q19 tau=0.6, 256^3 periodic, 8000
                  spheres with prescribed velocities), whose distributions do
                  not fit in the on-chip caches, per form;
+  adjoint        the 2D inlet/outlet channel (D2Q9 tau=0.8 512x256, 64 fixed
+                 disks r=8): a differentiable run of the drag through
+                 torch.autograd (forward with checkpoints, backward by
+                 recompute + the hand-written FP64 adjoint); the time of the
+                 backward over that of the forward;
   cpu_baseline   the FP64 oracle timed on the host on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-3d]
@@ -96,6 +101,45 @@ def run_form(w, form, steps, warmup, coupled=True):
     return total_ms / steps, kern_ms
 
 
+def run_adjoint(w, steps, every, window):
+    """Forward and backward wall time of a differentiable FP64 run (the
+    drag summed over the last `window` of `steps` steps)."""
+    import torch
+    from paper_1901_09745_amd.autograd import psc_drag
+
+    lat, p = w.lattice, w.particles
+    dev = "cuda"
+    r = torch.tensor(p.r, device=dev)
+
+    def once(nsteps):
+        x = torch.tensor(p.x, device=dev, requires_grad=True)
+        u = torch.tensor(p.u, device=dev, requires_grad=True)
+        om = torch.tensor(p.omega, device=dev, requires_grad=True)
+        fu = torch.tensor(np.asarray(lat.face_u, dtype=np.float64), device=dev,
+                          requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        F, _ = psc_drag(x, u, om, fu, lat, r, nsteps, checkpoint_every=every,
+                        window=min(window, nsteps), precision="fp64")
+        J = F[:, 0].sum()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if not torch.isfinite(fu.grad).all():
+            raise RuntimeError("non-finite adjoint")
+        return (t1 - t0) * 1e3, (t2 - t1) * 1e3
+
+    once(min(steps, every))            # warm-up
+    fwd, bwd = once(steps)
+    return {"workload": "D2Q9 tau=0.8 512x256 channel, equilibrium inlet u=0.02, outlet "
+                        "rho=1, 64 fixed disks r=8; J = drag summed over the window",
+            "precision": "fp64", "steps": steps, "checkpoint_every": every, "window": window,
+            "forward_ms": fwd, "backward_ms": bwd, "ratio": bwd / fwd,
+            "forward_ms_per_step": fwd / steps, "backward_ms_per_step": bwd / steps}
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The FP64 oracle on the host: coupled steps of the same workload for
     about budget_s seconds."""
@@ -146,6 +190,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--adjoint-steps", type=int, default=400,
+                    help="steps of the differentiable channel run (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (the reference kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -227,6 +273,9 @@ def main():
                        **hbm} if hbm else None),
         "roofline": roof,
     }
+    if args.adjoint_steps > 0:
+        _log("bench: adjoint of the 2D channel run")
+        out["adjoint"] = run_adjoint(W.c4(), args.adjoint_steps, 100, 100)
     if not args.no_cpu:
         _log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(w2, args.cpu_budget)

@@ -100,3 +100,119 @@ def test_rasterize_adjoint_matches_central_differences(q):
         h = 1e-7
         d = (J(p.x + h * v) - J(p.x - h * v)) / (2 * h)
         assert d == pytest.approx((gX * v).sum(), rel=1e-5, abs=1e-8)
+
+
+
+def _c4_small():
+    # the inlet / outlet channel with fixed disks at 1/4 scale: 128 x 64, 4 disks r = 8
+    return W.c4(scale=0.25)
+
+
+def _oracle_run_grad(w, steps, window):
+    """Oracle adjoint over a run: autograd through the PyTorch statement of
+    the step, J = sum of F_x over all disks and over the last `window` steps."""
+    lat, p = w.lattice, w.particles
+    geo = TS.Geometry(lat)
+    f = torch.tensor(oracle.Lattice(lat).f.reshape(lat.q, -1))
+    X = torch.tensor(p.x, requires_grad=True)
+    U = torch.tensor(p.u, requires_grad=True)
+    Wt = torch.tensor(p.omega, requires_grad=True)
+    fu = torch.tensor(np.asarray(lat.face_u, dtype=np.float64), requires_grad=True)
+    J = torch.zeros((), dtype=torch.float64)
+    for t in range(steps):
+        f, F, T = TS.step(geo, f, X, U, Wt, p.r, fu)
+        if t >= steps - window:
+            J = J + F[:, 0].sum()
+    gX, gU, gW, gfu = torch.autograd.grad(J, [X, U, Wt, fu], allow_unused=True)
+    return float(J.detach()), gX.numpy(), gU.numpy(), gfu.numpy()
+
+
+def _c_drag(w, steps, window, x=None, u=None, uin=None):
+    """The same J from the C oracle (for central differences)."""
+    lat = w.lattice
+    if uin is not None:
+        lat = lat.replace(face_u=((uin, 0.0, 0.0),) + tuple(lat.face_u[1:]))
+    p = w.particles.copy()
+    if x is not None:
+        p.x = x
+    if u is not None:
+        p.u = u
+    L = oracle.Lattice(lat)
+    J = 0.0
+    for t in range(steps):
+        F, _ = L.step(p)
+        if t >= steps - window:
+            J += F[:, 0].sum()
+    return J
+
+
+def _gpu_run_grad(w, steps, window, precision, every):
+    from paper_1901_09745_amd.autograd import psc_drag
+    lat, p = w.lattice, w.particles
+    dev = "cuda"
+    x = torch.tensor(p.x, device=dev, requires_grad=True)
+    u = torch.tensor(p.u, device=dev, requires_grad=True)
+    om = torch.tensor(p.omega, device=dev, requires_grad=True)
+    fu = torch.tensor(np.asarray(lat.face_u, dtype=np.float64), device=dev, requires_grad=True)
+    F, T = psc_drag(x, u, om, fu, lat, torch.tensor(p.r, device=dev), steps,
+                    checkpoint_every=every, window=window, precision=precision)
+    J = F[:, 0].sum()
+    J.backward()
+    return float(J), x.grad.cpu().numpy(), u.grad.cpu().numpy(), fu.grad.cpu().numpy()
+
+
+STEPS, WINDOW = 100, 10
+
+
+@pytest.fixture(scope="module")
+def run_reference():
+    w = _c4_small()
+    return w, _oracle_run_grad(w, STEPS, WINDOW)
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-10), ("fp32", 2e-4)])
+def test_checkpointed_run_gradient_matches_oracle(run_reference, precision, tol):
+    # J = sum of F_x over the 4 disks and the last 10 of 100 steps; gradients
+    # w.r.t. all disk positions and velocities and the inlet velocity, through
+    # torch.autograd with checkpoint-and-recompute every 30 steps (ragged tail)
+    w, (J_ref, gX_ref, gU_ref, gfu_ref) = run_reference
+    print(f"case: c4 at 1/4 scale, {precision}", flush=True)
+    J, gX, gU, gfu = _gpu_run_grad(w, STEPS, WINDOW, precision, every=30)
+    assert J == pytest.approx(J_ref, rel=1e-12 if precision == "fp64" else 1e-4)
+    assert _rel(gX[:, :2], gX_ref[:, :2]) < tol
+    assert _rel(gU[:, :2], gU_ref[:, :2]) < tol
+    assert np.all(gX[:, 2] == 0) and np.all(gU[:, 2] == 0)
+    assert gfu[0, 0] == pytest.approx(gfu_ref[0, 0], rel=tol)
+    assert np.all(gfu[1:] == 0)
+
+
+def test_checkpointed_run_gradient_matches_central_differences(run_reference):
+    w, (J_ref, gX_ref, gU_ref, gfu_ref) = run_reference
+    J, gX, gU, gfu = _gpu_run_grad(w, STEPS, WINDOW, "fp64", every=17)
+    p = w.particles
+    # the position derivative has O(h^2) error 3.6e-9 at h = 1e-5 (it converges
+    # as h^2 to the adjoint value), roundoff ~1e-11
+    h = 1e-5
+    s = int(np.argmin(p.x[:, 0]))           # the disk nearest the inlet
+    xp, xm = p.x.copy(), p.x.copy()
+    xp[s, 0] += h
+    xm[s, 0] -= h
+    fd = (_c_drag(w, STEPS, WINDOW, x=xp) - _c_drag(w, STEPS, WINDOW, x=xm)) / (2 * h)
+    assert gX[s, 0] == pytest.approx(fd, rel=1e-6)
+    up, um = p.u.copy(), p.u.copy()
+    up[s, 1] += h
+    um[s, 1] -= h
+    fd = (_c_drag(w, STEPS, WINDOW, u=up) - _c_drag(w, STEPS, WINDOW, u=um)) / (2 * h)
+    assert gU[s, 1] == pytest.approx(fd, rel=1e-6, abs=1e-9 * np.abs(gU).max())
+    uin = w.lattice.face_u[0][0]
+    fd = (_c_drag(w, STEPS, WINDOW, uin=uin + h) - _c_drag(w, STEPS, WINDOW, uin=uin - h)) / (2 * h)
+    assert gfu[0, 0] == pytest.approx(fd, rel=1e-6)
+
+
+def test_checkpoint_interval_does_not_change_gradient():
+    w = _c4_small()
+    ref = _gpu_run_grad(w, 40, 5, "fp64", every=40)
+    for every in (1, 7):
+        got = _gpu_run_grad(w, 40, 5, "fp64", every=every)
+        for a, b in zip(got[1:], ref[1:]):
+            assert _rel(a, b) < 1e-13
