@@ -299,10 +299,19 @@ void or_weights(int nslot, const double* eps, double tau, int mode,
  * Open faces need at least three cells across their axis. */
 static void apply_open_layers(const or_config* c, double* f) {
   const int q = lat_q(c), N = c->nx * c->ny * c->nz;
-  for (int pass = 0; pass < 2; ++pass)
+  /* Every outlet cell takes the velocity of its interior neighbour in the
+   * state entering the step, before any layer is reset (where two outlet
+   * faces meet, the neighbour may itself be an outlet cell); a cell on two
+   * outlet faces takes the later face's neighbour. */
+  double* ub = NULL;
+  int* has = NULL;
+  int any_outlet = 0;
+  for (int face = 0; face < 6; ++face) any_outlet |= c->face_bc[face] == OR_OUTLET_EQ;
+  if (any_outlet) {
+    ub = (double*)calloc((size_t)3 * N, sizeof(double));
+    has = (int*)calloc((size_t)N, sizeof(int));
     for (int face = 0; face < 6; ++face) {
-      int kind = c->face_bc[face];
-      if (kind != (pass == 0 ? OR_OUTLET_EQ : OR_INLET_EQ)) continue;
+      if (c->face_bc[face] != OR_OUTLET_EQ) continue;
       int a = face / 2, L = dims(c, a);
       int layer = (face % 2 == 0) ? 0 : L - 1;
       int inward = (face % 2 == 0) ? 1 : -1;
@@ -312,21 +321,40 @@ static void apply_open_layers(const or_config* c, double* f) {
             int p[3] = {x, y, z};
             if (p[a] != layer) continue;
             int n = x + c->nx * (y + c->ny * z);
-            double fe[OR_QMAX];
-            if (kind == OR_INLET_EQ) {
-              or_feq(q, c->rho0, c->face_u[face], fe);
-            } else {
-              int pn[3] = {x, y, z};
-              pn[a] += inward;
-              int m = pn[0] + c->nx * (pn[1] + c->ny * pn[2]);
-              double fl[OR_QMAX], rho, u[3];
-              for (int i = 0; i < q; ++i) fl[i] = f[(size_t)i * N + m];
-              or_moments(q, fl, c->force, &rho, u);
-              or_feq(q, c->rho0, u, fe);
-            }
-            for (int i = 0; i < q; ++i) f[(size_t)i * N + n] = fe[i];
+            int pn[3] = {x, y, z};
+            pn[a] += inward;
+            int m = pn[0] + c->nx * (pn[1] + c->ny * pn[2]);
+            double fl[OR_QMAX], rho;
+            for (int i = 0; i < q; ++i) fl[i] = f[(size_t)i * N + m];
+            or_moments(q, fl, c->force, &rho, &ub[3 * (size_t)n]);
+            has[n] = 1;
           }
     }
+    for (int n = 0; n < N; ++n) {
+      if (!has[n]) continue;
+      double fe[OR_QMAX];
+      or_feq(q, c->rho0, &ub[3 * (size_t)n], fe);
+      for (int i = 0; i < q; ++i) f[(size_t)i * N + n] = fe[i];
+    }
+    free(ub);
+    free(has);
+  }
+  /* inlets afterwards: an inlet face wins where it meets an outlet */
+  for (int face = 0; face < 6; ++face) {
+    if (c->face_bc[face] != OR_INLET_EQ) continue;
+    int a = face / 2, L = dims(c, a);
+    int layer = (face % 2 == 0) ? 0 : L - 1;
+    double fe[OR_QMAX];
+    or_feq(q, c->rho0, c->face_u[face], fe);
+    for (int z = 0; z < c->nz; ++z)
+      for (int y = 0; y < c->ny; ++y)
+        for (int x = 0; x < c->nx; ++x) {
+          int p[3] = {x, y, z};
+          if (p[a] != layer) continue;
+          int n = x + c->nx * (y + c->ny * z);
+          for (int i = 0; i < q; ++i) f[(size_t)i * N + n] = fe[i];
+        }
+  }
 }
 
 /* ------------------------------------------------------------------------ */

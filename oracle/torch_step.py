@@ -88,27 +88,34 @@ def step(geo: Geometry, f: torch.Tensor, X: torch.Tensor, U: torch.Tensor, W: to
     Fb = torch.tensor(list(lat.force), dtype=torch.float64)
     two_d = q == 9
 
-    # --- inlet / outlet layers (outlets from the unmodified state first) ---
+    # --- inlet / outlet layers: every outlet takes its neighbour's velocity
+    # from the state entering the step (before any reset), the later face
+    # winning on a cell of two outlet faces; then the inlets ---
+    f_in = f
     f = f.clone()
-    for kind in ("outlet_eq", "inlet_eq"):
-        for face in range(6):
-            if lat.faces[face] != kind:
-                continue
-            a = face // 2
-            L = geo.dims[a]
-            layer = 0 if face % 2 == 0 else L - 1
-            cells = np.nonzero(geo.coords[:, a] == layer)[0]
-            if kind == "inlet_eq":
-                ub = face_u[face].expand(len(cells), 3)
-            else:
-                step_in = 1 if face % 2 == 0 else -1
-                nbr = cells + step_in * (1 if a == 0 else (lat.nx if a == 1 else lat.nx * lat.ny))
-                fn = f[:, nbr]
-                rho_n = fn.sum(dim=0)
-                ub = ((e_t.T @ fn).T + 0.5 * Fb) / rho_n[:, None]
-            fe = feq(e_t, w_t, torch.full((len(cells),), lat.rho0, dtype=torch.float64), ub)
-            idx = torch.as_tensor(cells)
-            f = f.index_copy(1, idx, fe)
+    resets = []
+    for face in range(6):
+        if lat.faces[face] != "outlet_eq":
+            continue
+        a = face // 2
+        L = geo.dims[a]
+        layer = 0 if face % 2 == 0 else L - 1
+        cells = np.nonzero(geo.coords[:, a] == layer)[0]
+        step_in = 1 if face % 2 == 0 else -1
+        nbr = cells + step_in * (1 if a == 0 else (lat.nx if a == 1 else lat.nx * lat.ny))
+        fn = f_in[:, nbr]
+        rho_n = fn.sum(dim=0)
+        resets.append((cells, ((e_t.T @ fn).T + 0.5 * Fb) / rho_n[:, None]))
+    for face in range(6):
+        if lat.faces[face] != "inlet_eq":
+            continue
+        a = face // 2
+        layer = 0 if face % 2 == 0 else geo.dims[a] - 1
+        cells = np.nonzero(geo.coords[:, a] == layer)[0]
+        resets.append((cells, face_u[face].expand(len(cells), 3)))
+    for cells, ub in resets:
+        fe = feq(e_t, w_t, torch.full((len(cells),), lat.rho0, dtype=torch.float64), ub)
+        f = f.index_copy(1, torch.as_tensor(cells), fe)
 
     # --- moments (Eq. 5), equilibrium (Eq. 3), Guo forcing (Eq. 4) ---
     rho = f.sum(dim=0)

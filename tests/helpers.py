@@ -93,7 +93,17 @@ CASES = {
     "d2q9_open": W.LatticeSpec(q=9, nx=100, ny=45, tau=0.8, faces=(
         W.INLET_EQ, W.OUTLET_EQ, W.BOUNCE_BACK, W.BOUNCE_BACK, W.PERIODIC, W.PERIODIC),
         face_u=((0.02, 0.0, 0),) + ((0, 0, 0),) * 5),
+    # x = nx - 1 = 128 starts a 64-cell row segment: its outlet velocity comes
+    # from the separate pre-pass, not from the neighbour lane
+    "d2q9_open_seam": W.LatticeSpec(q=9, nx=129, ny=40, tau=0.75, force=(1e-6, 0, 0), faces=(
+        W.INLET_EQ, W.OUTLET_EQ, W.BOUNCE_BACK, W.BOUNCE_BACK, W.PERIODIC, W.PERIODIC),
+        face_u=((0.015, 0.002, 0),) + ((0, 0, 0),) * 5),
     "d3q19_periodic": W.LatticeSpec(q=19, nx=70, ny=21, nz=18, tau=0.6, force=(1e-5, 0, 2e-6)),
+    # outlets on x = 0 (neighbour lane) and y = 0 (pre-pass), an inlet on
+    # x = nx - 1; the corners take the later outlet and then the inlet
+    "d3q19_open": W.LatticeSpec(q=19, nx=40, ny=30, nz=20, tau=0.7, faces=(
+        W.OUTLET_EQ, W.INLET_EQ, W.OUTLET_EQ, W.BOUNCE_BACK, W.PERIODIC, W.PERIODIC),
+        face_u=((0, 0, 0), (-0.02, 0.0, 0.003), (0, 0, 0), (0, 0, 0), (0, 0, 0), (0, 0, 0))),
     "d3q19_walls": W.LatticeSpec(q=19, nx=33, ny=26, nz=22, tau=0.65, force=(-1e-5, 0, 0), faces=(
         W.BOUNCE_BACK, W.MOVING_WALL, W.PERIODIC, W.PERIODIC, W.BOUNCE_BACK, W.BOUNCE_BACK),
         face_u=((0, 0, 0), (0, 0.01, -0.005), (0, 0, 0), (0, 0, 0), (0, 0, 0), (0, 0, 0))),
