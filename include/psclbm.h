@@ -242,6 +242,18 @@ int lbm_step_adjoint(psclbm_ctx* ctx, const double* d_f, const double* d_lambda_
                      double* d_g_x, double* d_g_u, double* d_g_omega,
                      double* d_g_face_velocity);
 
+/* Recompute for checkpoint-and-recompute adjoints: from the canonical FP64
+ * state d_f0 (Q*N doubles, caller-owned), runs nsteps lbm_step time steps
+ * (Eqs. 1-6, 10, 12-13, Table 1) with the particles of the last psc_rasterize
+ * and writes the state after step k (k = 1..nsteps) to d_ring + (k-1)*Q*N,
+ * canonical FP64 (caller-owned, nsteps*Q*N doubles, must not overlap d_f0).
+ * The arithmetic is FP64 for every precision form; each step reads one ring
+ * slot and writes the next, so no state copy is made.  The context's own
+ * state, step count, force / torque accumulators and mass are left as they
+ * were.  Errors: EINVAL (null pointers, nsteps < 1, overlap, N*8 bytes not
+ * below 4 GiB), ESTATE (no rasterisation), EHIP. */
+int lbm_recompute(psclbm_ctx* ctx, const double* d_f0, int nsteps, double* d_ring);
+
 /* Adjoint of the solid fractions alone (Eqs. 15-18, Table 1): for
  * sensitivities dJ/deps_{n,s} given per recorded slot in the layout of
  * psc_get_solid_fraction (d_g_slot_eps[N*kslots], slots in ascending particle

@@ -10,9 +10,12 @@ moving-wall faces): the path-wise sensitivities of a run in which the
 particle state is a fixed parameter.
 
 Memory: one canonical FP64 state per ``checkpoint_every`` steps is kept from
-the forward; the backward recomputes each segment into a ring of
-``checkpoint_every`` states, then walks it backwards.  Every step and every
-adjoint step runs in the HIP kernels; torch holds the buffers.
+the forward; the backward recomputes each segment (lbm_recompute, FP64, each
+step reading one ring slot and writing the next) into a ring of
+``checkpoint_every - 1`` states, then walks it backwards.  Every step and
+every adjoint step runs in the HIP kernels; torch holds the buffers.  The
+forward may run in any precision form; its checkpoints are the canonical FP64
+images of its state, and the recompute and adjoint are FP64.
 """
 from __future__ import annotations
 
@@ -77,18 +80,18 @@ class PscDrag(torch.autograd.Function):
         lam = torch.zeros((q, N), dtype=torch.float64, device=dev)
         lam2 = torch.empty_like(lam)
         nseg = len(ctx.checkpoints)
+        ring = torch.empty((max(k - 1, 1), q, N), dtype=torch.float64, device=dev)
         for j in reversed(range(nseg)):
             t0 = j * k
             t1 = min(steps, t0 + k)
-            # recompute the segment's states
-            G.set_f(ctx.checkpoints[j])
-            ring = [ctx.checkpoints[j]]
-            for t in range(t0, t1 - 1):
-                G.step(1)
-                ring.append(G.get_f())
+            ck = ctx.checkpoints[j].reshape(q, N)
+            # recompute the segment's states straight into the ring
+            if t1 - t0 > 1:
+                P.lbm_recompute(G.ctx, ck, t1 - t0 - 1, ring)
             for t in reversed(range(t0, t1)):
                 seeded = t >= steps - window
-                P.lbm_step_adjoint(G.ctx, ring[t - t0].reshape(q, N), lam, lam2,
+                state = ck if t == t0 else ring[t - t0 - 1]
+                P.lbm_step_adjoint(G.ctx, state, lam, lam2,
                                    gF if seeded else None, gT if seeded else None,
                                    gX, gU, gW, gface)
                 lam, lam2 = lam2, lam

@@ -363,6 +363,18 @@ int lbm_step_adjoint(psclbm_ctx* ctx, const double* d_f, const double* d_lambda_
                         d_g_omega, d_g_face_velocity);
 }
 
+int lbm_recompute(psclbm_ctx* ctx, const double* d_f0, int nsteps, double* d_ring) {
+  if (!ctx || !d_f0 || !d_ring || nsteps < 1) return PSCLBM_EINVAL;
+  if (!ctx->rasterized) return PSCLBM_ESTATE;
+  // the ring step addresses one direction's FP64 array with 32-bit byte offsets
+  if ((double)ctx->geom.N * sizeof(double) >= 4294967296.0) return PSCLBM_EINVAL;
+  const size_t QN = (size_t)ctx->geom.q * (size_t)ctx->geom.N;
+  const uintptr_t r0 = (uintptr_t)d_ring, r1 = r0 + (uintptr_t)nsteps * QN * sizeof(double);
+  const uintptr_t f0 = (uintptr_t)d_f0, f1 = f0 + QN * sizeof(double);
+  if (f0 < r1 && r0 < f1) return PSCLBM_EINVAL;
+  return launch_recompute(ctx, d_f0, nsteps, d_ring);
+}
+
 int psc_rasterize_adjoint(psclbm_ctx* ctx, const double* d_g_slot_eps, int kslots,
                           double* d_g_x) {
   if (!ctx || !d_g_slot_eps || !d_g_x || kslots < 1) return PSCLBM_EINVAL;

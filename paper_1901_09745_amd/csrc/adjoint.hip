@@ -62,6 +62,7 @@ struct AdjArgs {
   double* outlet_g;       // [6][face cells][3], dJ/du of that velocity
   long long face_stride;
   unsigned inlet_mask, outlet_mask, moving_mask;
+  unsigned outlet_wave;   // outlet faces (x only) whose neighbour is in the same wave
 };
 
 template <int Q>
@@ -107,9 +108,34 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
     d.sz = (unsigned)G.nx * (unsigned)G.ny;
     const double rho0 = G.rho0;
     const double F0 = a.force[0], F1 = a.force[1], F2 = a.force[2];
+    const int lane = (int)(threadIdx.x & 63);
     double f[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[i] = a.f[(size_t)i * N + n];
+
+    // moments of the state as loaded; an x-face outlet whose interior
+    // neighbour is in this wave takes that neighbour's velocity from its lane
+    double rho_in = 0.0, uin0 = 0.0, uin1 = 0.0, uin2 = 0.0;
+    double wu0 = 0.0, wu1 = 0.0, wu2 = 0.0;
+    if (a.outlet_wave) {
+      double j0 = 0.0, j1 = 0.0, j2 = 0.0;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        rho_in += f[i];
+        j0 += L::ex(i) * f[i];
+        j1 += L::ey(i) * f[i];
+        j2 += L::ez(i) * f[i];
+      }
+      uin0 = (j0 + 0.5 * F0) / rho_in;
+      uin1 = (j1 + 0.5 * F1) / rho_in;
+      uin2 = (j2 + 0.5 * F2) / rho_in;
+      int src = lane;
+      if ((a.outlet_wave & 1u) && x == 0) src = lane + 1;
+      if ((a.outlet_wave & 2u) && x == d.nx - 1) src = lane - 1;
+      wu0 = __shfl(uin0, src);
+      wu1 = __shfl(uin1, src);
+      wu2 = __shfl(uin2, src);
+    }
 
     // inlet / outlet reset (as in the forward: outlets first, an inlet wins)
     int reset = 0, rface = 0;
@@ -120,11 +146,15 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
         const bool on = fc == 0 ? x == 0 : fc == 1 ? x == d.nx - 1 : fc == 2 ? y == 0
                       : fc == 3 ? y == d.ny - 1 : fc == 4 ? z == 0 : z == d.nz - 1;
         if (((a.outlet_mask >> fc) & 1u) && on) {
-          const unsigned k = fc < 2 ? (unsigned)y + (unsigned)d.ny * z
-                                    : (fc < 4 ? (unsigned)x + (unsigned)d.nx * z
-                                              : (unsigned)x + (unsigned)d.nx * y);
-          const double* o = a.outlet_u + ((size_t)fc * a.face_stride + k) * 3;
-          ub0 = o[0]; ub1 = o[1]; ub2 = o[2];
+          if ((a.outlet_wave >> fc) & 1u) {
+            ub0 = wu0; ub1 = wu1; ub2 = wu2;
+          } else {
+            const unsigned k = fc < 2 ? (unsigned)y + (unsigned)d.ny * z
+                                      : (fc < 4 ? (unsigned)x + (unsigned)d.nx * z
+                                                : (unsigned)x + (unsigned)d.nx * y);
+            const double* o = a.outlet_u + ((size_t)fc * a.face_stride + k) * 3;
+            ub0 = o[0]; ub1 = o[1]; ub2 = o[2];
+          }
           reset = 2;
           rface = fc;
         }
@@ -209,22 +239,29 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
     const double cp = S <= 1.0 ? tm / (den * den) : -1.0 / (S * S);
     const double Bnp = S < 1.0 ? tm * (1.0 + tm) / (den * den) : 0.0;
 
-    // base adjoint terms
-    double ar = 0.0, aux = 0.0, auy = 0.0, auz = 0.0, LP = 0.0;
+    // base adjoint terms; L0 = sum_i lam*_i (f_{-i} - f^eq_{-i} - f_i), the part
+    // of lam* . Omega^s common to every particle; and the moments of w_i lam*_i
+    // (orders 0, 1, 2 in e_i), through which the particle terms close
+    double ar = 0.0, aux = 0.0, auy = 0.0, auz = 0.0, LP = 0.0, L0 = 0.0;
+    double m0 = 0.0, m1x = 0.0, m1y = 0.0, m1z = 0.0;
+    double mxx = 0.0, myy = 0.0, mzz = 0.0, mxy = 0.0, mxz = 0.0, myz = 0.0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int o = L::opp(i);
       const double ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
       const double eu = ex * ux + ey * uy + ez * uz;
-      const double fe = rho * L::w(i) * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+      const double rw = rho * L::w(i);
+      const double sq = 1.0 + 4.5 * eu * eu - 1.5 * uu;
+      const double fe = rw * (sq + 3.0 * eu);
+      const double fe_o = rw * (sq - 3.0 * eu);
       const double eF = ex * F0 + ey * F1 + ez * F2;
       const double Fi = kg * L::w(i) * (3.0 * (eF - (ux * F0 + uy * F1 + uz * F2)) + 9.0 * eu * eF);
       LP += ls[i] * (w * (f[i] - fe) - Fi);
+      L0 += ls[i] * (f[o] - fe_o - f[i]);
       // coefficient of f^eq_i: (1-B_n) w lam*_i - B_n lam*_{-i}
       const double cf = (1.0 - Bn) * w * ls[i] - Bn * ls[o];
       ar += cf * fe / rho;
       // df^eq_i/du = rho w_i (3 e + 9 (e.u) e - 3 u)
-      const double rw = rho * L::w(i);
       aux += cf * rw * (3.0 * ex + 9.0 * eu * ex - 3.0 * ux);
       auy += cf * rw * (3.0 * ey + 9.0 * eu * ey - 3.0 * uy);
       auz += cf * rw * (3.0 * ez + 9.0 * eu * ez - 3.0 * uz);
@@ -233,16 +270,34 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
       aux += cF * (-3.0 * F0 + 9.0 * eF * ex);
       auy += cF * (-3.0 * F1 + 9.0 * eF * ey);
       auz += cF * (-3.0 * F2 + 9.0 * eF * ez);
+      const double wl = L::w(i) * ls[i];
+      m0 += wl;
+      m1x += ex * wl;
+      m1y += ey * wl;
+      m1z += ez * wl;
+      mxx += ex * ex * wl;
+      myy += ey * ey * wl;
+      mzz += ez * ez * wl;
+      mxy += ex * ey * wl;
+      mxz += ex * ez * wl;
+      myz += ey * ez * wl;
     }
 
-    // covering particles
-    double Gk[KSLOTS], Ak[KSLOTS][3], Rk[KSLOTS][3], Mk[KSLOTS][3], SG = 0.0;
+    // covering particles, first pass: G_s = lam* . Omega^s + q_s . M_s with
+    //   lam* . f^eq(rho, u_s) = rho [m0 (1 - 1.5 u_s^2) + 3 u_s . m1 + 4.5 u_s.M2.u_s]
+    //   sum_i lam*_i df^eq_i(u_s)/du_s = rho [3 m1 + 9 M2 u_s - 3 m0 u_s]
+    // and every particle gradient term but the one carrying sum_s eps_s G_s;
+    // dJ/deps_s = B_n' (lam* . P) + c G_s + c' sum_t eps_t G_t enters dJ/dX_s
+    // through d eps / d X = r / |r| on the linear band of Table 1 (zero where
+    // clamped)
+    double SG = 0.0;
+    const double BLP = Bnp * LP;
 #pragma unroll
     for (int k = 0; k < KSLOTS; ++k) {
-      Gk[k] = 0.0;
-      for (int t = 0; t < 3; ++t) Ak[k][t] = Rk[k][t] = Mk[k][t] = 0.0;
       if (k >= s.n) continue;
-      const LdsEntry& P = lds[s.e[k]];
+      const int e = s.e[k];
+      const double epsk = s.eps[k];
+      const LdsEntry& P = lds[e];
       const double rx = min_image((double)x - P.x, d.px, d.nx);
       const double ry = min_image((double)y - P.y, d.py, d.ny);
       const double rz = D == 3 ? min_image((double)z - P.z, d.pz, d.nz) : 0.0;
@@ -250,10 +305,10 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
       const double usy = P.u[1] + P.w[2] * rx - P.w[0] * rz;
       const double usz = P.u[2] + P.w[0] * ry - P.w[1] * rx;
       const double us2 = usx * usx + usy * usy + usz * usz;
-      const double Bs = s.eps[k] * c;
+      const double Bs = epsk * c;
       // q = dJ/dm = -dJ/dF - dJ/dT x r
       double qx = 0.0, qy = 0.0, qz = 0.0;
-      const int id = s.id[k];
+      const int id = P.id;
       if (a.gF) {
         qx -= a.gF[3 * id];
         qy -= a.gF[3 * id + 1];
@@ -269,65 +324,35 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
         qz -= tx * ry - ty * rx;
       }
       const double Mx = rho * (usx - ux) + F0, My = rho * (usy - uy) + F1, Mz = rho * (usz - uz) + F2;
-      double LO = 0.0, Lfs = 0.0, dsx = 0.0, dsy = 0.0, dsz = 0.0;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const int o = L::opp(i);
-        const double ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
-        const double eu_o = -(ex * ux + ey * uy + ez * uz);
-        const double fe_o = rho * L::w(o) * (1.0 + 3.0 * eu_o + 4.5 * eu_o * eu_o - 1.5 * uu);
-        const double eus = ex * usx + ey * usy + ez * usz;
-        const double fs = rho * L::w(i) * (1.0 + 3.0 * eus + 4.5 * eus * eus - 1.5 * us2);
-        LO += ls[i] * (f[o] - fe_o + fs - f[i]);
-        Lfs += ls[i] * fs;
-        const double rw = ls[i] * rho * L::w(i);
-        dsx += rw * (3.0 * ex + 9.0 * eus * ex - 3.0 * usx);
-        dsy += rw * (3.0 * ey + 9.0 * eus * ey - 3.0 * usy);
-        dsz += rw * (3.0 * ez + 9.0 * eus * ez - 3.0 * usz);
-      }
-      Gk[k] = LO + qx * Mx + qy * My + qz * Mz;
-      SG += s.eps[k] * Gk[k];
+      const double M2x = mxx * usx + mxy * usy + mxz * usz;
+      const double M2y = mxy * usx + myy * usy + myz * usz;
+      const double M2z = mxz * usx + myz * usy + mzz * usz;
+      const double Lfs = rho * (m0 * (1.0 - 1.5 * us2) + 3.0 * (usx * m1x + usy * m1y + usz * m1z) +
+                                4.5 * (usx * M2x + usy * M2y + usz * M2z));
+      const double dsx = rho * (3.0 * m1x + 9.0 * M2x - 3.0 * usx * m0);
+      const double dsy = rho * (3.0 * m1y + 9.0 * M2y - 3.0 * usy * m0);
+      const double dsz = rho * (3.0 * m1z + 9.0 * M2z - 3.0 * usz * m0);
+      const double Gs = L0 + Lfs + qx * Mx + qy * My + qz * Mz;
+      SG += epsk * Gs;
       ar += Bs * Lfs / rho + Bs * (qx * (usx - ux) + qy * (usy - uy) + qz * (usz - uz));
       aux -= Bs * rho * qx;
       auy -= Bs * rho * qy;
       auz -= Bs * rho * qz;
-      Ak[k][0] = Bs * (dsx + rho * qx);
-      Ak[k][1] = Bs * (dsy + rho * qy);
-      Ak[k][2] = Bs * (dsz + rho * qz);
-      Rk[k][0] = rx;
-      Rk[k][1] = ry;
-      Rk[k][2] = rz;
-      // m x dJ/dT term of dJ/dr: dJ/dT x m
+      // dJ/du_s, and through u_s = U + Omega x r and m = B_s M: the parts of
+      // dJ/dr that are dJ/du_s x Omega and dJ/dT x m
+      const double ax = Bs * (dsx + rho * qx), ay = Bs * (dsy + rho * qy), az = Bs * (dsz + rho * qz);
       const double mx = Bs * Mx, my = Bs * My, mz = Bs * Mz;
-      Mk[k][0] = ty * mz - tz * my;
-      Mk[k][1] = tz * mx - tx * mz;
-      Mk[k][2] = tx * my - ty * mx;
-    }
-
-    // particle gradients
-#pragma unroll
-    for (int k = 0; k < KSLOTS; ++k) {
-      if (k >= s.n) continue;
-      const LdsEntry& P = lds[s.e[k]];
-      const double dJde = Bnp * LP + c * Gk[k] + cp * SG;
-      const double rx = Rk[k][0], ry = Rk[k][1], rz = Rk[k][2];
       const double dist = sqrt(rx * rx + ry * ry + rz * rz);
-      // d eps / d X = r / |r| on the linear band of Table 1 (zero when clamped)
       const double lin = P.cs - dist;
       const bool band = dist < P.r + a.h && dist > P.r - a.h && lin > 0.0 && lin < 1.0;
-      const double gd = band ? dJde / dist : 0.0;
-      const double ax = Ak[k][0], ay = Ak[k][1], az = Ak[k][2];
-      // dJ/dr from u_s = U + Omega x r: dJ/du_s x Omega
-      const double cx = ay * P.w[2] - az * P.w[1];
-      const double cy = az * P.w[0] - ax * P.w[2];
-      const double cz = ax * P.w[1] - ay * P.w[0];
-      double* ac = acc + 9 * s.e[k];
-      atomicAdd(ac + 0, gd * rx - (cx + Mk[k][0]));
-      atomicAdd(ac + 1, gd * ry - (cy + Mk[k][1]));
+      const double gd = band ? (BLP + c * Gs) / dist : 0.0;
+      double* ac = acc + 9 * e;
+      atomicAdd(ac + 0, gd * rx - ((ay * P.w[2] - az * P.w[1]) + (ty * mz - tz * my)));
+      atomicAdd(ac + 1, gd * ry - ((az * P.w[0] - ax * P.w[2]) + (tz * mx - tx * mz)));
       atomicAdd(ac + 3, ax);
       atomicAdd(ac + 4, ay);
       if constexpr (D == 3) {
-        atomicAdd(ac + 2, gd * rz - (cz + Mk[k][2]));
+        atomicAdd(ac + 2, gd * rz - ((ax * P.w[1] - ay * P.w[0]) + (tx * my - ty * mx)));
         atomicAdd(ac + 5, az);
         atomicAdd(ac + 6, ry * az - rz * ay);
         atomicAdd(ac + 7, rz * ax - rx * az);
@@ -335,27 +360,47 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
       atomicAdd(ac + 8, rx * ay - ry * ax);
     }
 
-    // sensitivity of the state entering the step
-    const double alpha = 1.0 - (1.0 - Bn) * w - Bn;
-    double lam[Q];
+    // second pass: the c' sum_t eps_t G_t part of dJ/deps_s
+    if (s.n > 0) {
+      const double cSG = cp * SG;
 #pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      const double ex = L::ex(j), ey = L::ey(j), ez = L::ez(j);
-      lam[j] = alpha * ls[j] + Bn * ls[L::opp(j)] + kappa + ar +
-               (aux * (ex - ux) + auy * (ey - uy) + auz * (ez - uz)) / rho;
+      for (int k = 0; k < KSLOTS; ++k) {
+        if (k >= s.n) continue;
+        const int e = s.e[k];
+        const LdsEntry& P = lds[e];
+        const double rx = min_image((double)x - P.x, d.px, d.nx);
+        const double ry = min_image((double)y - P.y, d.py, d.ny);
+        const double rz = D == 3 ? min_image((double)z - P.z, d.pz, d.nz) : 0.0;
+        const double dist = sqrt(rx * rx + ry * ry + rz * rz);
+        const double lin = P.cs - dist;
+        const bool band = dist < P.r + a.h && dist > P.r - a.h && lin > 0.0 && lin < 1.0;
+        if (!band) continue;
+        const double gd = cSG / dist;
+        double* ac = acc + 9 * e;
+        atomicAdd(ac + 0, gd * rx);
+        atomicAdd(ac + 1, gd * ry);
+        if constexpr (D == 3) atomicAdd(ac + 2, gd * rz);
+      }
     }
+
+    // sensitivity of the state entering the step; a reset cell passes it to
+    // the boundary velocity (f = f^eq(rho0, u_b)):
+    //   dJ/du_b = sum_j lam_j rho0 w_j (3 e_j + 9 (e_j.u_b) e_j - 3 u_b)
+    // and keeps none of its own
+    const double alpha = 1.0 - (1.0 - Bn) * w - Bn;
+    const double irho = 1.0 / rho;
+    double g0 = 0.0, g1 = 0.0, g2 = 0.0;
     if (reset) {
-      // f = f^eq(rho0, u_b): dJ/du_b = sum_j lam_j rho0 w_j (3 e_j + 9 (e_j.u_b) e_j - 3 u_b)
-      double g0 = 0.0, g1 = 0.0, g2 = 0.0;
 #pragma unroll
       for (int j = 0; j < Q; ++j) {
         const double ex = L::ex(j), ey = L::ey(j), ez = L::ez(j);
+        const double lj = alpha * ls[j] + Bn * ls[L::opp(j)] + kappa + ar +
+                          (aux * (ex - ux) + auy * (ey - uy) + auz * (ez - uz)) * irho;
         const double eu = ex * ub0 + ey * ub1 + ez * ub2;
-        const double rw = lam[j] * rho0 * L::w(j);
+        const double rw = lj * rho0 * L::w(j);
         g0 += rw * (3.0 * ex + 9.0 * eu * ex - 3.0 * ub0);
         g1 += rw * (3.0 * ey + 9.0 * eu * ey - 3.0 * ub1);
         g2 += rw * (3.0 * ez + 9.0 * eu * ez - 3.0 * ub2);
-        lam[j] = 0.0;
       }
       if (reset == 1) {
         if (a.gface) {
@@ -363,7 +408,7 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
           atomicAdd(a.gface + 3 * rface + 1, g1);
           atomicAdd(a.gface + 3 * rface + 2, g2);
         }
-      } else {
+      } else if (!((a.outlet_wave >> rface) & 1u)) {
         const unsigned k = rface < 2 ? (unsigned)y + (unsigned)d.ny * z
                                      : (rface < 4 ? (unsigned)x + (unsigned)d.nx * z
                                                   : (unsigned)x + (unsigned)d.nx * y);
@@ -373,8 +418,36 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
         o[2] = g2;
       }
     }
+    // in-wave outlets: the neighbour lane takes the outlet's dJ/du_b through
+    // its own u = (sum f e + F/2)/rho: lam_j += g . (e_j - u)/rho
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0;
+    if (a.outlet_wave) {
 #pragma unroll
-    for (int j = 0; j < Q; ++j) a.lam_out[(size_t)j * N + n] = lam[j];
+      for (int fc = 0; fc < 2; ++fc) {
+        if (!((a.outlet_wave >> fc) & 1u)) continue;
+        const bool mine = reset == 2 && rface == fc;
+        const int nbx = fc == 0 ? 1 : d.nx - 2;
+        const int src = x == nbx ? (fc == 0 ? lane - 1 : lane + 1) : lane;
+        const double v0 = __shfl(mine ? g0 : 0.0, src);
+        const double v1 = __shfl(mine ? g1 : 0.0, src);
+        const double v2 = __shfl(mine ? g2 : 0.0, src);
+        if (x == nbx) {
+          s0 += v0 / rho_in;
+          s1 += v1 / rho_in;
+          s2 += v2 / rho_in;
+        }
+      }
+    }
+    const double sb = -(s0 * uin0 + s1 * uin1 + s2 * uin2);
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      const double ex = L::ex(j), ey = L::ey(j), ez = L::ez(j);
+      double lj = alpha * ls[j] + Bn * ls[L::opp(j)] + kappa + ar +
+                  (aux * (ex - ux) + auy * (ey - uy) + auz * (ez - uz)) * irho;
+      if (reset) lj = 0.0;
+      lj += s0 * ex + s1 * ey + s2 * ez + sb;
+      a.lam_out[(size_t)j * N + n] = lj;
+    }
   }
 
   // flush the tile's particle gradients
@@ -531,10 +604,12 @@ int launch_adjoint(psclbm_ctx* c, const double* f, const double* lam_in, double*
     if (c->geom.face[fc] == PSCLBM_OUTLET_EQ) a.outlet_mask |= 1u << fc;
     if (c->geom.face[fc] == PSCLBM_MOVING_WALL) a.moving_mask |= 1u << fc;
   }
+  a.outlet_wave = outlet_wave_mask(c->geom, a.outlet_mask);
+  const unsigned separate = a.outlet_mask & ~a.outlet_wave;
   const double* F = c->cfg.body_force;
   const int fgrid = (int)((c->face_stride + 255) / 256 < 4096 ? (c->face_stride + 255) / 256 : 4096);
   for (int fc = 0; fc < 6; ++fc) {
-    if (!((a.outlet_mask >> fc) & 1u)) continue;
+    if (!((separate >> fc) & 1u)) continue;
     k_outlet_velocity_canon<<<fgrid, 256, 0, c->stream>>>(c->geom, fc, f, F[0], F[1], F[2],
                                                           c->outlet_u, c->face_stride);
   }
@@ -552,7 +627,7 @@ int launch_adjoint(psclbm_ctx* c, const double* f, const double* lam_in, double*
   int rc = hip_ok(hipGetLastError());
   if (rc) return rc;
   for (int fc = 0; fc < 6; ++fc) {
-    if (!((a.outlet_mask >> fc) & 1u)) continue;
+    if (!((separate >> fc) & 1u)) continue;
     if (c->geom.q == 9)
       k_outlet_adjoint<9><<<fgrid, 256, 0, c->stream>>>(c->geom, fc, f, c->outlet_g, lam_out,
                                                         F[0], F[1], F[2], c->face_stride);

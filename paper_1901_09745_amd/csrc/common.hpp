@@ -135,7 +135,20 @@ struct StepArgs {
   unsigned outlet_mask;    // faces of kind OUTLET_EQ
   unsigned open_mask;      // inlet | outlet
   unsigned moving_mask;    // faces of kind MOVING_WALL
+  unsigned outlet_wave;    // outlet faces served from the neighbour's lane
+  const void* src;         // ring step: canonical FP64 state read (f is written)
 };
+
+// Outlet faces whose cells share a wave with their interior neighbour, so that
+// the neighbour's velocity (and, in the adjoint, the sensitivity flowing back
+// to it) moves between lanes: the x faces, since a wave is one 64-cell x-row
+// segment of a tile; x = nx-1 only when it is not the first lane of a segment.
+inline unsigned outlet_wave_mask(const Geom& g, unsigned outlet_mask) {
+  unsigned m = 0;
+  if ((outlet_mask & 1u) && g.nx >= 2) m |= 1u;
+  if ((outlet_mask & 2u) && g.nx >= 2 && (g.nx - 1) % TX != 0) m |= 2u;
+  return m;
+}
 
 }  // namespace psclbm
 
@@ -213,6 +226,7 @@ int launch_get_macros(psclbm_ctx* c, double* rho, double* u);
 int launch_rasterize(psclbm_ctx* c, const psclbm_particles* p);
 int launch_solid_fraction(psclbm_ctx* c, double* eps, int* ids, double* seps, int k);
 int launch_step(psclbm_ctx* c);
+int launch_recompute(psclbm_ctx* c, const double* f0, int nsteps, double* ring);
 int launch_mass(psclbm_ctx* c, double* h_mass);
 int launch_zero(psclbm_ctx* c, void* p, size_t bytes);
 int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, double* u,

@@ -7,6 +7,9 @@
 //                          f*_i to A[opp(i)][n];
 //   odd step  (parity 1): cell n reads f_i from A[opp(i)][n - e_i] and writes
 //                          f*_i to A[i][n + e_i].
+// A third form (ring step, used to recompute states for the adjoint) reads a
+// canonical FP64 array and writes the canonical result into another:
+//   ring step (parity 2): cell n reads src[i][n] and writes f*_i to dst[i][n + e_i].
 // A link that leaves the domain through a non-periodic face is reflected into
 // the cell itself (halfway bounce-back, Eq. 6), which in both parities lands
 // on the location the same cell reads back next step; every location is read
@@ -233,7 +236,9 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
     // ---- load f as deviations g_i = f_i - w_i rho0 ----
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      if constexpr (PAR == 0) {
+      if constexpr (PAR == 2) {
+        g[i] = ST::ld(const_cast<S*>(static_cast<const S*>(a.src)) + (size_t)i * N, n, i, rho0);
+      } else if constexpr (PAR == 0) {
         g[i] = ST::ld(A + (size_t)i * N, n, i, rho0);
       } else {
         unsigned m = n;
@@ -248,18 +253,49 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
     if (a.open_mask) {
       bool reset = false;
       double ub0 = 0.0, ub1 = 0.0, ub2 = 0.0;
+      // x-face outlets: the velocity of the interior neighbour at this time
+      // level, from the neighbour's lane of this wave
+      double wu0 = 0.0, wu1 = 0.0, wu2 = 0.0;
+      if (a.outlet_wave) {
+        C r_ = 0, j0 = 0, j1 = 0, j2 = 0;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+          r_ += g[i];
+          j0 += (C)L::ex(i) * g[i];
+          j1 += (C)L::ey(i) * g[i];
+          j2 += (C)L::ez(i) * g[i];
+        }
+        const int lane = (int)(threadIdx.x & 63);
+        int src = lane;
+        if ((a.outlet_wave & 1u) && x == 0) src = lane + 1;
+        if ((a.outlet_wave & 2u) && x == d.nx - 1) src = lane - 1;
+        r_ = __shfl(r_, src);
+        j0 = __shfl(j0, src);
+        j1 = __shfl(j1, src);
+        j2 = __shfl(j2, src);
+        const C ir = (C)1 / ((C)rho0 + r_);
+        wu0 = (double)((j0 + (C)0.5 * F0) * ir);
+        wu1 = (double)((j1 + (C)0.5 * F1) * ir);
+        wu2 = (double)((j2 + (C)0.5 * F2) * ir);
+      }
 #pragma unroll
       for (int f = 0; f < 6; ++f) {  // outlets first, an inlet wins on a corner
         const bool on = f == 0 ? x == 0 : f == 1 ? x == d.nx - 1 : f == 2 ? y == 0
                       : f == 3 ? y == d.ny - 1 : f == 4 ? z == 0 : z == d.nz - 1;
         if (((a.outlet_mask >> f) & 1u) && on) {
-          const unsigned k = f < 2 ? (unsigned)y + (unsigned)d.ny * z
-                                   : (f < 4 ? (unsigned)x + (unsigned)d.nx * z
-                                            : (unsigned)x + (unsigned)d.nx * y);
-          const double* o = a.outlet_u + ((size_t)f * a.face_stride + k) * 3;
-          ub0 = o[0];
-          ub1 = o[1];
-          ub2 = o[2];
+          if ((a.outlet_wave >> f) & 1u) {
+            ub0 = wu0;
+            ub1 = wu1;
+            ub2 = wu2;
+          } else {
+            const unsigned k = f < 2 ? (unsigned)y + (unsigned)d.ny * z
+                                     : (f < 4 ? (unsigned)x + (unsigned)d.nx * z
+                                              : (unsigned)x + (unsigned)d.nx * y);
+            const double* o = a.outlet_u + ((size_t)f * a.face_stride + k) * 3;
+            ub0 = o[0];
+            ub1 = o[1];
+            ub2 = o[2];
+          }
           reset = true;
         }
       }
@@ -385,6 +421,7 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
         g[i] += rBw * (ds_s + ds_a);
         g[o] += rBw * (ds_s - ds_a);
       }
+      if (!a.facc) continue;  // ring step: no force accumulation
       const double mx = (double)(Bs * (rho * dvx + F0));
       const double my = (double)(Bs * (rho * dvy + F1));
       double* ac = acc + 6 * s.e[k];
@@ -433,11 +470,13 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
   }
 
   // ---- per-workgroup FP64 mass partial (sum of the stored deviations) ----
-  mass_dev = wave_sum(mass_dev);
   __shared__ double wsum[BLOCK / 64];
-  if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = mass_dev;
+  if (a.mass_part) {
+    mass_dev = wave_sum(mass_dev);
+    if ((threadIdx.x & 63) == 0) wsum[threadIdx.x >> 6] = mass_dev;
+  }
   __syncthreads();
-  if (threadIdx.x == 0) {
+  if (a.mass_part && threadIdx.x == 0) {
     double t = 0.0;
     for (int k = 0; k < BLOCK / 64; ++k) t += wsum[k];
     a.mass_part[blockIdx.x] = t;
@@ -445,7 +484,7 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
 
   // ---- flush the tile's force / torque partials (FP64); the barrier of the
   // mass reduction above orders the LDS accumulation before this read ----
-  if (cnt > 0) {
+  if (cnt > 0 && a.facc) {
     for (int e = threadIdx.x; e < cnt; e += BLOCK) {
       const double* ac = acc + 6 * e;
       double* dst = a.facc + 6 * (size_t)lds[e].id;
@@ -455,7 +494,7 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
     }
   }
   // ---- clear the other force buffer for the next step ----
-  if (a.np > 0) {
+  if (a.np > 0 && a.fzero) {
     const unsigned tot = 6u * (unsigned)a.np;
     for (unsigned k = blockIdx.x * BLOCK + threadIdx.x; k < tot; k += (unsigned)nb * BLOCK)
       a.fzero[k] = 0.0;
@@ -468,12 +507,12 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
 // ---------------------------------------------------------------------------
 template <int Q, int PREC>
 __global__ void k_outlet_velocity(Geom g, const void* f, int par, double fx, double fy,
-                                  double fz, double* out, long long stride) {
+                                  double fz, double* out, long long stride, unsigned faces) {
   using L = Lattice<Q>;
   using ST = Store<PREC, Q>;
   using S = typename Form<PREC>::S;
   const int face = blockIdx.y;
-  if (g.face[face] != PSCLBM_OUTLET_EQ) return;
+  if (!((faces >> face) & 1u)) return;
   const int ax = face / 2;
   const int u1 = ax == 0 ? 1 : 0, u2 = ax == 2 ? 1 : 2;
   const int Ld[3] = {g.nx, g.ny, g.nz};
@@ -789,6 +828,16 @@ template <int Q, int PREC>
 static int dispatch_step(psclbm_ctx* c, const StepArgs& a, int par, size_t lds_bytes) {
   const int nb = c->ntiles;
   const bool walls = !(c->geom.periodic[0] && c->geom.periodic[1] && c->geom.periodic[2]);
+  if (par == 2) {  // ring step: canonical FP64 in and out
+    if constexpr (PREC == PSCLBM_FP64) {
+      if (walls)
+        k_step<Q, PREC, 2, true><<<nb, BLOCK, lds_bytes, c->stream>>>(a);
+      else
+        k_step<Q, PREC, 2, false><<<nb, BLOCK, lds_bytes, c->stream>>>(a);
+      return hip_ok(hipGetLastError());
+    }
+    return PSCLBM_EINVAL;
+  }
   if (walls) {
     if (par == 0)
       k_step<Q, PREC, 0, true><<<nb, BLOCK, lds_bytes, c->stream>>>(a);
@@ -891,11 +940,12 @@ int launch_solid_fraction(psclbm_ctx* c, double* eps, int* ids, double* seps, in
   return hip_ok(hipGetLastError());
 }
 
-int launch_step(psclbm_ctx* c) {
-  const int par = (int)(c->steps & 1);
+// Arguments of one step from the context (state, forces and mass in place).
+static StepArgs step_args(psclbm_ctx* c) {
   StepArgs a;
   a.g = c->geom;
   a.f = c->f;
+  a.src = nullptr;
   a.tau = c->cfg.tau;
   for (int k = 0; k < 3; ++k) a.force[k] = c->cfg.body_force[k];
   a.h = c->cfg.shell_h;
@@ -919,19 +969,31 @@ int launch_step(psclbm_ctx* c) {
     if (c->geom.face[f] == PSCLBM_MOVING_WALL) a.moving_mask |= 1u << f;
   }
   a.open_mask = a.inlet_mask | a.outlet_mask;
-  const int has_outlet = a.outlet_mask != 0;
-  if (has_outlet) {
+  a.outlet_wave = outlet_wave_mask(c->geom, a.outlet_mask);
+  return a;
+}
+
+static size_t step_lds(const psclbm_ctx* c) {
+  return c->np > 0 ? (sizeof(LdsEntry) + 6 * sizeof(double)) * (size_t)c->cfg.max_tile_particles
+                   : 0;
+}
+
+int launch_step(psclbm_ctx* c) {
+  const int par = (int)(c->steps & 1);
+  StepArgs a = step_args(c);
+  // outlets whose neighbour is in another wave: velocities before the step
+  const unsigned separate = a.outlet_mask & ~a.outlet_wave;
+  if (separate) {
     const double* F = c->cfg.body_force;
     dim3 grid((unsigned)grid_for(c->face_stride), 6);
     PSCLBM_DISPATCH(c->geom.q, c->prec,
                     (k_outlet_velocity<Q, P><<<grid, 256, 0, c->stream>>>(
-                        c->geom, c->f, par, F[0], F[1], F[2], c->outlet_u, c->face_stride)));
+                        c->geom, c->f, par, F[0], F[1], F[2], c->outlet_u, c->face_stride,
+                        separate)));
     int rc = hip_ok(hipGetLastError());
     if (rc) return rc;
   }
-  const size_t lds = c->np > 0 ? (sizeof(LdsEntry) + 6 * sizeof(double)) *
-                                     (size_t)c->cfg.max_tile_particles
-                               : 0;
+  const size_t lds = step_lds(c);
   int rc;
   if (c->prec == PSCLBM_FP64)
     rc = dispatch_step_q<PSCLBM_FP64>(c, a, par, lds);
@@ -940,9 +1002,39 @@ int launch_step(psclbm_ctx* c) {
   else
     rc = dispatch_step_q<PSCLBM_FP32_FP16STORE>(c, a, par, lds);
   if (rc) return rc;
-  c->force_buf = next;
+  c->force_buf ^= 1;
   c->steps += 1;
   c->mass_valid = 1;
+  return PSCLBM_OK;
+}
+
+int launch_recompute(psclbm_ctx* c, const double* f0, int nsteps, double* ring) {
+  StepArgs a = step_args(c);
+  a.facc = nullptr;
+  a.fzero = nullptr;
+  a.mass_part = nullptr;
+  const unsigned separate = a.outlet_mask & ~a.outlet_wave;
+  const size_t lds = step_lds(c);
+  const size_t QN = (size_t)c->geom.q * (size_t)c->geom.N;
+  const double* F = c->cfg.body_force;
+  for (int k = 0; k < nsteps; ++k) {
+    const double* src = k == 0 ? f0 : ring + (size_t)(k - 1) * QN;
+    if (separate) {
+      dim3 grid((unsigned)grid_for(c->face_stride), 6);
+      if (c->geom.q == 9)
+        k_outlet_velocity<9, PSCLBM_FP64><<<grid, 256, 0, c->stream>>>(
+            c->geom, src, 0, F[0], F[1], F[2], c->outlet_u, c->face_stride, separate);
+      else
+        k_outlet_velocity<19, PSCLBM_FP64><<<grid, 256, 0, c->stream>>>(
+            c->geom, src, 0, F[0], F[1], F[2], c->outlet_u, c->face_stride, separate);
+      int rc = hip_ok(hipGetLastError());
+      if (rc) return rc;
+    }
+    a.src = src;
+    a.f = ring + (size_t)k * QN;
+    int rc = dispatch_step_q<PSCLBM_FP64>(c, a, 2, lds);
+    if (rc) return rc;
+  }
   return PSCLBM_OK;
 }
 

@@ -79,6 +79,7 @@ SIGNATURES = {
     "psclbm_strerror": (ctypes.c_char_p, [_I]),
     "lbm_step_count": (ctypes.c_longlong, [_VP]),
     "lbm_step_adjoint": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "lbm_recompute": (_I, [_VP, _VP, _I, _VP]),
     "psc_rasterize_adjoint": (_I, [_VP, _VP, _I, _VP]),
 }
 
@@ -214,6 +215,10 @@ def lbm_step_adjoint(ctx: int, f: torch.Tensor, lam_in: torch.Tensor, lam_out: t
     _check(load().lbm_step_adjoint(ctx, _ptr(f), _ptr(lam_in), _ptr(lam_out), _ptr(dJ_dF),
                                    _ptr(dJ_dT), _ptr(g_x), _ptr(g_u), _ptr(g_omega),
                                    _ptr(g_face)), "lbm_step_adjoint")
+
+
+def lbm_recompute(ctx: int, f0: torch.Tensor, nsteps: int, ring: torch.Tensor) -> None:
+    _check(load().lbm_recompute(ctx, _ptr(f0), nsteps, _ptr(ring)), "lbm_recompute")
 
 
 def psc_rasterize_adjoint(ctx: int, g_slot_eps: torch.Tensor, kslots: int,

@@ -103,6 +103,59 @@ def test_rasterize_adjoint_matches_central_differences(q):
 
 
 
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_recompute_ring_matches_in_place_steps(name):
+    # lbm_recompute writes the states an FP64 context reaches step by step,
+    # bit for bit, from an FP64 and from an FP32 context, and leaves the
+    # context's state, forces and mass alone
+    import paper_1901_09745_amd.psclbm as P
+    lat = CASES[name]
+    print(f"case: {name}", flush=True)
+    p = case_particles(lat)
+    q, N = lat.q, lat.ncells
+    f0 = torch.from_numpy(W.random_state(lat, 5).reshape(q, N)).cuda()
+    G = gpu_lattice(lat, p)
+    G.rasterize(P.DeviceParticles.from_host(p))
+    G.set_f(f0)
+    states = []
+    for _ in range(5):
+        G.step(1)
+        states.append(G.get_f().reshape(q, N))
+    want = torch.stack(states)
+    F0, T0 = G.forces()
+    m0 = G.mass()
+    for prec in ("fp64", "fp32"):
+        H = G if prec == "fp64" else gpu_lattice(lat, p, precision="fp32")
+        if prec == "fp32":
+            H.rasterize(P.DeviceParticles.from_host(p))
+        ring = torch.full((5, q, N), float("nan"), dtype=torch.float64, device="cuda")
+        P.lbm_recompute(H.ctx, f0, 5, ring)
+        H.sync()
+        assert torch.equal(ring, want), (prec, float((ring - want).abs().max()))
+    F1, T1 = G.forces()
+    assert torch.equal(F0, F1) and torch.equal(T0, T1)
+    assert torch.equal(G.get_f().reshape(q, N), states[-1])
+    assert G.mass() == m0
+
+
+def test_recompute_rejects_overlap_and_bad_counts():
+    import paper_1901_09745_amd.psclbm as P
+    lat = CASES["d2q9_periodic"]
+    p = case_particles(lat)
+    G = gpu_lattice(lat, p)
+    q, N = lat.q, lat.ncells
+    ring = torch.zeros((3, q, N), dtype=torch.float64, device="cuda")
+    with pytest.raises(P.PsclbmError):   # no rasterisation yet
+        P.lbm_recompute(G.ctx, ring[0], 1, ring[1:])
+    G.rasterize(P.DeviceParticles.from_host(p))
+    with pytest.raises(P.PsclbmError):
+        P.lbm_recompute(G.ctx, ring[1], 2, ring[0:])
+    with pytest.raises(P.PsclbmError):
+        P.lbm_recompute(G.ctx, ring[0], 0, ring[1:])
+    P.lbm_recompute(G.ctx, ring[0], 2, ring[1:])
+    G.sync()
+
+
 def _c4_small():
     # the inlet / outlet channel with fixed disks at 1/4 scale: 128 x 64, 4 disks r = 8
     return W.c4(scale=0.25)
@@ -158,7 +211,7 @@ def _gpu_run_grad(w, steps, window, precision, every):
                     checkpoint_every=every, window=window, precision=precision)
     J = F[:, 0].sum()
     J.backward()
-    return float(J), x.grad.cpu().numpy(), u.grad.cpu().numpy(), fu.grad.cpu().numpy()
+    return float(J.detach()), x.grad.cpu().numpy(), u.grad.cpu().numpy(), fu.grad.cpu().numpy()
 
 
 STEPS, WINDOW = 100, 10
