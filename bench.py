@@ -17,11 +17,13 @@ The JSON line reports:
   hbm_bound      the 3D workload (D3Q19 tau=0.6, 256^3 periodic, 8000
                  spheres with prescribed velocities), whose distributions do
                  not fit in the on-chip caches, per form;
-  adjoint        the 2D inlet/outlet channel (D2Q9 tau=0.8 512x256, 64 fixed
-                 disks r=8): a differentiable run of the drag through
-                 torch.autograd (forward with checkpoints, backward by
-                 recompute + the hand-written FP64 adjoint); the time of the
-                 backward over that of the forward;
+  adjoint        differentiable runs of the drag through torch.autograd
+                 (forward with checkpoints, backward by ring recompute + the
+                 hand-written FP64 adjoint): the time of the backward over
+                 that of the forward, on the 2D inlet/outlet channel (D2Q9
+                 tau=0.8 512x256, 64 fixed disks r=8, 400 steps) and on a
+                 20-step window of the 3D packing (D3Q19 384x192x192, 20000
+                 spheres);
   cpu_baseline   the FP64 oracle timed on the host on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-3d]
@@ -101,7 +103,7 @@ def run_form(w, form, steps, warmup, coupled=True):
     return total_ms / steps, kern_ms
 
 
-def run_adjoint(w, steps, every, window):
+def run_adjoint(w, steps, every, window, label):
     """Forward and backward wall time of a differentiable FP64 run (the
     drag summed over the last `window` of `steps` steps)."""
     import torch
@@ -133,8 +135,7 @@ def run_adjoint(w, steps, every, window):
 
     once(min(steps, every))            # warm-up
     fwd, bwd = once(steps)
-    return {"workload": "D2Q9 tau=0.8 512x256 channel, equilibrium inlet u=0.02, outlet "
-                        "rho=1, 64 fixed disks r=8; J = drag summed over the window",
+    return {"workload": label, "cells": w.lattice.ncells, "particles": p.n,
             "precision": "fp64", "steps": steps, "checkpoint_every": every, "window": window,
             "forward_ms": fwd, "backward_ms": bwd, "ratio": bwd / fwd,
             "forward_ms_per_step": fwd / steps, "backward_ms_per_step": bwd / steps}
@@ -192,6 +193,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--adjoint-steps", type=int, default=400,
                     help="steps of the differentiable channel run (0: skip)")
+    ap.add_argument("--adjoint-3d-steps", type=int, default=20,
+                    help="steps of the differentiable 3D packing window (0: skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (the reference kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -275,7 +278,20 @@ def main():
     }
     if args.adjoint_steps > 0:
         _log("bench: adjoint of the 2D channel run")
-        out["adjoint"] = run_adjoint(W.c4(), args.adjoint_steps, 100, 100)
+        adj = {"channel_2d": run_adjoint(
+            W.c4(), args.adjoint_steps, 100, 1,
+            "D2Q9 tau=0.8 512x256 channel, equilibrium inlet u=0.02, outlet rho=1, 64 fixed "
+            "disks r=8; J = drag at the last step")}
+        if args.adjoint_3d_steps > 0:
+            _log("bench: generating the 3D packing workload")
+            w5 = W.c5()
+            _log("bench: adjoint of a 3D packing window")
+            adj["packing_3d"] = run_adjoint(
+                w5, args.adjoint_3d_steps, 10, 1,
+                "D3Q19 tau=0.65 384x192x192, walls on x, 20000 spheres r~U(3,5) held fixed "
+                "over the window; J = drag at the last step")
+        adj["ratio"] = adj["channel_2d"]["ratio"]
+        out["adjoint"] = adj
     if not args.no_cpu:
         _log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(w2, args.cpu_budget)

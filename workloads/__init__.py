@@ -134,14 +134,19 @@ def _min_image(d: np.ndarray, L: float, periodic: bool) -> np.ndarray:
 
 def rsa(rng: np.random.Generator, radii: Sequence[float], box: Tuple[float, ...],
         periodic: Tuple[bool, ...], gap: float = 0.0, clearance: float = 0.0,
-        xrange: Optional[Tuple[float, float]] = None, max_trials: int = 50_000_000
-        ) -> np.ndarray:
+        xrange: Optional[Tuple[float, float]] = None, max_trials: int = 200_000_000,
+        multi: bool = False) -> np.ndarray:
     """Place disks/spheres of the given radii (in the given order) uniformly at
     random without overlap: a candidate is accepted when its distance to every
     placed particle is at least r_i + r_j + gap (nearest image on periodic
     axes).  On a walled axis the centre keeps ``clearance`` + r from the walls at
     -1/2 and L-1/2.  ``xrange`` optionally narrows the x placement window.
     Candidates are drawn in batches, the first acceptable one in a batch wins.
+    With ``multi`` (radii in descending order, for packings near the RSA
+    jamming limit) every candidate of a batch that clears the placed particles
+    at the current radius -- an upper bound of the radii still to come -- is
+    taken in draw order if it also clears those taken before it in the batch,
+    each with the next radius.
     Returns positions of shape (n, 3) (z = 0 in 2D).
     """
     dim = len(box)
@@ -158,7 +163,24 @@ def rsa(rng: np.random.Generator, radii: Sequence[float], box: Tuple[float, ...]
     offs = np.array(np.meshgrid(*[[-1, 0, 1]] * dim, indexing="ij")).reshape(dim, -1).T
     batch = 4
     trials = 0
-    for k in range(n):
+    if multi and n > 1 and np.any(np.diff(radii) > 0):
+        raise ValueError("rsa(multi=True) needs radii in descending order")
+
+    def insert(k, p):
+        nonlocal bins, cap
+        bb = tuple(int(v) for v in np.minimum(
+            np.floor(np.mod(p, np.asarray(box)) / np.asarray(bsz)).astype(np.int64),
+            np.asarray(nb) - 1))
+        if counts[bb] >= cap:
+            cap *= 2
+            nbins = -np.ones(tuple(nb) + (cap,), dtype=np.int64)
+            nbins[..., : cap // 2] = bins
+            bins = nbins
+        bins[bb + (int(counts[bb]),)] = k
+        counts[bb] += 1
+
+    k = 0
+    while k < n:
         r = radii[k]
         lo = np.zeros(dim)
         hi = np.zeros(dim)
@@ -195,19 +217,36 @@ def rsa(rng: np.random.Generator, radii: Sequence[float], box: Tuple[float, ...]
             need = (radii[safe] + r + gap) ** 2
             clash = ((d2 < need) & (ids >= 0)).any(axis=1)
             ok = np.nonzero(~clash)[0]
+            if ok.size and multi:
+                taken = []
+                for j in ok:
+                    if k + len(taken) >= n:
+                        break
+                    rj = radii[k + len(taken)]
+                    fine = True
+                    for (t, pt) in taken:
+                        d2t = 0.0
+                        for a in range(dim):
+                            da = float(_min_image(np.array([P[j, a] - pt[a]]), box[a],
+                                                  periodic[a])[0])
+                            d2t += da * da
+                        if d2t < (radii[t] + rj + gap) ** 2:
+                            fine = False
+                            break
+                    if fine:
+                        taken.append((k + len(taken), P[j]))
+                for (t, pt) in taken:
+                    pos[t, :dim] = pt
+                    insert(t, pt)
+                k += len(taken)
+                if ok[0] == 0 and batch > 4:
+                    batch //= 2
+                break
             if ok.size:
                 p = P[ok[0]]
                 pos[k, :dim] = p
-                bb = tuple(int(v) for v in np.minimum(
-                    np.floor(np.mod(p, np.asarray(box)) / np.asarray(bsz)).astype(np.int64),
-                    np.asarray(nb) - 1))
-                if counts[bb] >= cap:
-                    cap *= 2
-                    nbins = -np.ones(tuple(nb) + (cap,), dtype=np.int64)
-                    nbins[..., : cap // 2] = bins
-                    bins = nbins
-                bins[bb + (int(counts[bb]),)] = k
-                counts[bb] += 1
+                insert(k, p)
+                k += 1
                 if ok[0] == 0 and batch > 4:
                     batch //= 2
                 break
@@ -292,7 +331,7 @@ def c5(scale: float = 1.0, seed: int = 5) -> Workload:
     n = _scaled_count(20000, scale, 3)
     rng = np.random.default_rng(seed)
     radii = np.sort(rng.uniform(3.0, 5.0, size=n))[::-1]
-    x = rsa(rng, radii, (float(nx), float(ny), float(nz)), (False, True, True))
+    x = rsa(rng, radii, (float(nx), float(ny), float(nz)), (False, True, True), multi=True)
     lat = LatticeSpec(q=19, nx=nx, ny=ny, nz=nz, tau=0.65,
                       faces=(BOUNCE_BACK, BOUNCE_BACK, PERIODIC, PERIODIC, PERIODIC, PERIODIC))
     dem = DemSpec(g=(-1e-6, 0.0, 0.0))
