@@ -60,6 +60,23 @@ def force_scale(lat, f, p):
     return scale
 
 
+def force_floor(lat, f, p):
+    """Absolute rounding floor of each particle's Eq. 14 sum: u = (sum_i e_i
+    f_i + F/2)/rho carries up to (Q-1) eps of error from the direction sum
+    (|f_i| summing to rho), so each covered cell's summand B_s rho (u_s - u)
+    may differ by rho (Q-1) eps between two FP64 evaluations, on both sides:
+    2 (Q-1) eps sum_n rho_n over the particle's cells (B_s <= 1)."""
+    nslot, ids, eps, _ = oracle.rasterize(lat, p.x, p.r)
+    rho, _ = oracle.Lattice(lat, f).macros()
+    rho = rho.reshape(-1)
+    floor = np.zeros(p.n)
+    covered = np.nonzero(nslot)[0]
+    for k in range(ids.shape[1]):
+        sel = covered[nslot[covered] > k]
+        np.add.at(floor, ids[sel, k], rho[sel])
+    return 2 * (lat.q - 1) * np.finfo(np.float64).eps * floor
+
+
 WALLS_Y = (W.PERIODIC, W.PERIODIC, W.BOUNCE_BACK, W.BOUNCE_BACK, W.PERIODIC, W.PERIODIC)
 
 

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workloads as W
-from helpers import force_scale, relerr
+from helpers import force_floor, force_scale, relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -37,8 +37,9 @@ def _one_step_check(w, G, dp):
     f1 = G.get_f().cpu().numpy()
     assert relerr(f1, ref.f) < 1e-12
     scale = force_scale(w.lattice, f0, pc)
+    floor = force_floor(w.lattice, f0, pc)
     dF = np.abs(F.cpu().numpy() - F_ref).max(axis=1)
-    assert np.all(dF <= 1e-12 * scale + 1e-300)
+    assert np.all(dF <= 1e-12 * scale + floor + 1e-300), float((dF / (1e-12 * scale + floor)).max())
     return F_ref
 
 
