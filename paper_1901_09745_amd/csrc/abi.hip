@@ -62,7 +62,7 @@ int validate(const psclbm_config* c) {
 
 struct Layout {
   size_t f, err, scalar, tile_count, tile_list, snap, facc0, facc1, mass_part, outlet_u, outlet_g;
-  size_t bin_count, bin_list, cn0, cn1, cid0, cid1, fcontact, total;
+  size_t bin_count, bin_list, dem_src, cn0, cn1, cid0, cid1, total;
   int ntx, nty, ntz, ntiles;
   long long face_stride;
   int nbin[3];
@@ -111,7 +111,7 @@ Layout plan(const psclbm_config* c) {
   l.f = take((size_t)N * c->lattice * storage_bytes(c->precision));
   l.err = take(sizeof(unsigned) * 4);
   l.scalar = take(sizeof(double) * 4);
-  l.tile_count = take(sizeof(int) * (size_t)l.ntiles);
+  l.tile_count = take(sizeof(int) * 2 * (size_t)l.ntiles);
   l.tile_list = take(sizeof(int) * (size_t)l.ntiles * cap);
   l.snap = take(sizeof(PSnap) * (size_t)(np > 0 ? np : 1));
   l.facc0 = take(sizeof(double) * 6 * (size_t)(np > 0 ? np : 1));
@@ -120,13 +120,13 @@ Layout plan(const psclbm_config* c) {
   l.outlet_u = take(outlet ? sizeof(double) * 3 * 6 * (size_t)fs : 8);
   l.outlet_g = take(outlet ? sizeof(double) * 3 * 6 * (size_t)fs : 8);
   const int mc = np > 0 ? c->max_contacts : 1;
-  l.bin_count = take(sizeof(int) * nbins);
+  l.bin_count = take(sizeof(int) * 2 * nbins);
   l.bin_list = take(sizeof(int) * nbins * l.bin_cap * (np > 0 ? 1 : 0));
+  l.dem_src = take(sizeof(double) * 6 * (size_t)(np > 0 ? np : 1));
   l.cn0 = take(sizeof(int) * (size_t)(np > 0 ? np : 1));
   l.cn1 = take(sizeof(int) * (size_t)(np > 0 ? np : 1));
   l.cid0 = take(sizeof(int) * (size_t)(np > 0 ? np : 1) * mc);
   l.cid1 = take(sizeof(int) * (size_t)(np > 0 ? np : 1) * mc);
-  l.fcontact = take(sizeof(double) * 3 * (size_t)(np > 0 ? np : 1));
   l.total = off;
   return l;
 }
@@ -192,7 +192,10 @@ int lbm_init(const psclbm_config* cfg, void* d_workspace, size_t bytes, void* hi
   c->f = base + l.f;
   c->err = reinterpret_cast<unsigned*>(base + l.err);
   c->scalar = reinterpret_cast<double*>(base + l.scalar);
-  c->tile_count = reinterpret_cast<int*>(base + l.tile_count);
+  c->tile_count_buf[0] = reinterpret_cast<int*>(base + l.tile_count);
+  c->tile_count_buf[1] = c->tile_count_buf[0] + l.ntiles;
+  c->tile_cur = 0;
+  c->tile_count = c->tile_count_buf[0];
   c->tile_list = reinterpret_cast<int*>(base + l.tile_list);
   c->ntiles = l.ntiles;
   c->snap = reinterpret_cast<PSnap*>(base + l.snap);
@@ -208,13 +211,18 @@ int lbm_init(const psclbm_config* cfg, void* d_workspace, size_t bytes, void* hi
     c->bin_size[a] = l.bin_size[a];
   }
   c->bin_cap = l.bin_cap;
-  c->bin_count = reinterpret_cast<int*>(base + l.bin_count);
+  {
+    const size_t nbins = (size_t)l.nbin[0] * l.nbin[1] * l.nbin[2];
+    c->bin_count_buf[0] = reinterpret_cast<int*>(base + l.bin_count);
+    c->bin_count_buf[1] = c->bin_count_buf[0] + nbins;
+  }
+  c->bin_cur = 0;
   c->bin_list = reinterpret_cast<int*>(base + l.bin_list);
+  c->dem_src = reinterpret_cast<double*>(base + l.dem_src);
   c->contact_n[0] = reinterpret_cast<int*>(base + l.cn0);
   c->contact_n[1] = reinterpret_cast<int*>(base + l.cn1);
   c->contact_id[0] = reinterpret_cast<int*>(base + l.cid0);
   c->contact_id[1] = reinterpret_cast<int*>(base + l.cid1);
-  c->fcontact = reinterpret_cast<double*>(base + l.fcontact);
   // clear everything but the distributions, then set f = f^eq(rho0, 0)
   rc = launch_zero(c, base + l.err, l.total - l.err);
   if (!rc) rc = launch_init_equilibrium(c, nullptr, nullptr);

@@ -159,7 +159,9 @@ struct psclbm_ctx {
   int prec;
   void* f;
   unsigned* err;
-  int* tile_count;
+  int* tile_count;          // counts of the current tile lists (one of tile_count_buf)
+  int* tile_count_buf[2];    // double-buffered: each rasterisation clears the other
+  int tile_cur;
   int* tile_list;
   int ntiles;
   psclbm::PSnap* snap;
@@ -173,12 +175,13 @@ struct psclbm_ctx {
   int nbin[3];
   double bin_size[3];
   int bin_cap;
-  int* bin_count;
+  int* bin_count_buf[2];  // double-buffered: each binning clears the other
+  int bin_cur;
   int* bin_list;
+  double* dem_src;        // [n][6]: x, u at the start of the DEM sub-step
   int* contact_n[2];
   int* contact_id[2];
   int contact_cur;
-  double* fcontact;
   double* scalar;  // one FP64 device scalar for reductions
   // host-side state
   long long steps;

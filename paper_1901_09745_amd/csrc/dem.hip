@@ -3,11 +3,14 @@
 // including the jump-on / pull-off hysteresis, sub-cycled n_sub times per
 // coupling step with the hydrodynamic force and torque held fixed.
 //
-// Per sub-step: (1) bin the particles into a uniform grid whose bins are at
-// least 2 r_max + 1 wide, (2) one thread per particle gathers its contacts
-// from the neighbouring bins and the walls, sums their forces in ascending
-// partner order and records the new contact list, (3) one thread per particle
-// integrates with semi-implicit Euler.
+// Per sub-step, two kernels: (1) bin the particles into a uniform grid whose
+// bins are at least 2 r_max + 1 wide, copying each particle's position and
+// velocity into a workspace image; (2) one wave per particle gathers its
+// contacts from the neighbouring bins and the walls (reading the image, so
+// that no particle sees another's update), records the new contact list,
+// sums the forces over the wave and integrates the particle with
+// semi-implicit Euler.  The bin counts are double buffered: each binning
+// fills one set and clears the other.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -24,14 +27,16 @@ struct DemArgs {
   int nbin[3];
   double bin_size[3];
   int bin_cap;
-  int* bin_count;
+  int* bin_count;        // counts filled by this sub-step's binning
+  int* bin_stale;        // the other set, cleared by this binning
+  int nbins;
   int* bin_list;
+  double* src;           // [n][6] image of x, u at the start of the sub-step
   const int* prev_n;
   const int* prev_id;
   int* next_n;
   int* next_id;
   int max_contacts;
-  double* fc;
   double E;       // effective modulus of two bodies of the material (Eq. 25)
   double gamma;
   double eta_n;
@@ -91,9 +96,15 @@ __device__ inline int bin_coord(double x, int a, const DemArgs& d) {
   return b;
 }
 
-__global__ void k_dem_bin(DemArgs d, const double* x) {
+__global__ void k_dem_bin(DemArgs d, const double* x, const double* u) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  for (int b = i; b < d.nbins; b += gridDim.x * blockDim.x) d.bin_stale[b] = 0;
   if (i >= d.n) return;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    d.src[6 * i + a] = x[3 * i + a];
+    d.src[6 * i + 3 + a] = u[3 * i + a];
+  }
   const int bx = bin_coord(x[3 * i], 0, d);
   const int by = bin_coord(x[3 * i + 1], 1, d);
   const int bz = d.three_d ? bin_coord(x[3 * i + 2], 2, d) : 0;
@@ -133,17 +144,67 @@ __device__ inline bool was_in_contact(const int* ids, int n, int id) {
   return false;
 }
 
+struct IntArgs {
+  int n, three_d;
+  int L[3], periodic[3];
+  double dt;
+  double rho_p, rho_f;
+  double g[3];
+  int kinematic;
+  int wrap;
+  int fstride, tstride;  // element strides of the force / torque rows
+};
+
+// Semi-implicit Euler (Eq. 21) of particle i with hydrodynamic force F,
+// torque T and contact force fc: u += dt (F + fc + G)/m, x += dt u,
+// omega += dt T/I, then the wrap into [0, L) on periodic axes.
+__device__ inline void integrate_one(const IntArgs& p, int i, double* x, double* u, double* w,
+                                     double ri, const double* F, const double* T, double fc0,
+                                     double fc1, double fc2) {
+  const int D = p.three_d ? 3 : 2;
+  const double fc[3] = {fc0, fc1, fc2};
+  if (!p.kinematic) {
+    const double V = p.three_d ? (4.0 / 3.0) * M_PI * ri * ri * ri : M_PI * ri * ri;
+    const double m = p.rho_p * V;
+    const double I = p.three_d ? 0.4 * m * ri * ri : 0.5 * m * ri * ri;
+    for (int a = 0; a < D; ++a) {
+      const double G = (p.rho_p - p.rho_f) * V * p.g[a];
+      u[3 * i + a] += p.dt * (F[a] + fc[a] + G) / m;
+      x[3 * i + a] += p.dt * u[3 * i + a];
+    }
+    if (p.three_d) {
+      for (int a = 0; a < 3; ++a) w[3 * i + a] += p.dt * T[a] / I;
+    } else {
+      w[3 * i + 2] += p.dt * T[2] / I;
+    }
+  } else {
+    for (int a = 0; a < D; ++a) x[3 * i + a] += p.dt * u[3 * i + a];
+  }
+  if (p.wrap) {
+    for (int a = 0; a < D; ++a) {
+      if (!p.periodic[a]) continue;
+      const double L = (double)p.L[a];
+      if (x[3 * i + a] >= L) x[3 * i + a] -= L;
+      else if (x[3 * i + a] < 0.0) x[3 * i + a] += L;
+    }
+  }
+}
+
 // One wave per particle.  The lanes stride over the (neighbour bin, slot)
 // candidates and the walls; contacts are compacted into the new contact list
-// with a ballot, and the contact force is summed over the wave.
-__global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, const double* x, const double* u,
-                                                      const double* r) {
+// with a ballot, the contact force is summed over the wave, and lane 0
+// integrates the particle.  Positions and velocities of the sub-step are read
+// from the binning's image, the particle's update goes to x, u, w.
+__global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, IntArgs ia, double* x, double* u,
+                                                      double* w, const double* r,
+                                                      const double* Ff, const double* Tf) {
   const int i = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
   const int lane = (int)(threadIdx.x & 63);
   if (i >= d.n) return;  // uniform over the wave
   const int D = d.three_d ? 3 : 2;
-  const double xi0 = x[3 * i], xi1 = x[3 * i + 1], xi2 = d.three_d ? x[3 * i + 2] : 0.0;
-  const double ui0 = u[3 * i], ui1 = u[3 * i + 1], ui2 = d.three_d ? u[3 * i + 2] : 0.0;
+  const double* S = d.src;
+  const double xi0 = S[6 * i], xi1 = S[6 * i + 1], xi2 = d.three_d ? S[6 * i + 2] : 0.0;
+  const double ui0 = S[6 * i + 3], ui1 = S[6 * i + 4], ui2 = d.three_d ? S[6 * i + 5] : 0.0;
   const double ri = r[i];
   const int pn = d.prev_n[i];
   const int* prev = d.prev_id + (size_t)i * d.max_contacts;
@@ -209,9 +270,9 @@ __global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, const double* x
     if (valid) {
       const int j = d.bin_list[(size_t)b * d.bin_cap + slot];
       if (j != i) {
-        const double dv0 = min_img(x[3 * j] - xi0, d.periodic[0], d.L[0]);
-        const double dv1 = min_img(x[3 * j + 1] - xi1, d.periodic[1], d.L[1]);
-        const double dv2 = d.three_d ? min_img(x[3 * j + 2] - xi2, d.periodic[2], d.L[2]) : 0.0;
+        const double dv0 = min_img(S[6 * j] - xi0, d.periodic[0], d.L[0]);
+        const double dv1 = min_img(S[6 * j + 1] - xi1, d.periodic[1], d.L[1]);
+        const double dv2 = d.three_d ? min_img(S[6 * j + 2] - xi2, d.periodic[2], d.L[2]) : 0.0;
         const double dist = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
         const double rj = r[j];
         const double delta = ri + rj - dist;
@@ -221,8 +282,8 @@ __global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, const double* x
           const double F = jkr_force(Reff, d.E, d.gamma, delta, &dC);
           if (delta >= 0.0 || delta > -dC) {
             const double n0 = dv0 / dist, n1 = dv1 / dist, n2 = dv2 / dist;
-            double vrn = (u[3 * j] - ui0) * n0 + (u[3 * j + 1] - ui1) * n1;
-            if (d.three_d) vrn += (u[3 * j + 2] - ui2) * n2;
+            double vrn = (S[6 * j + 3] - ui0) * n0 + (S[6 * j + 4] - ui1) * n1;
+            if (d.three_d) vrn += (S[6 * j + 5] - ui2) * n2;
             const double fm = -F + d.eta_n * vrn;
             fs0 += fm * n0;
             fs1 += fm * n1;
@@ -248,61 +309,19 @@ __global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, const double* x
       atomicOr(d.err, ERR_CONTACTS);
       cnt = d.max_contacts;
     }
-    d.fc[3 * i] = fs0;
-    d.fc[3 * i + 1] = fs1;
-    d.fc[3 * i + 2] = fs2;
     d.next_n[i] = cnt;
+    integrate_one(ia, i, x, u, w, ri, Ff + (size_t)ia.fstride * i, Tf + (size_t)ia.tstride * i,
+                  fs0, fs1, fs2);
   }
 }
 
-struct IntArgs {
-  int n, three_d;
-  int L[3], periodic[3];
-  double dt;
-  double rho_p, rho_f;
-  double g[3];
-  int kinematic;
-  int wrap;
-  int fstride, tstride;  // element strides of the force / torque rows
-  int* bin_count;        // cleared here for the next binning (may be null)
-  int nbins;
-};
-
-__global__ void k_dem_integrate(IntArgs p, double* x, double* u, double* w, const double* r,
-                                const double* Ff, const double* Tf, const double* Fc) {
+// Kinematic particles (prescribed velocities): x += dt u.
+__global__ void k_dem_advect(IntArgs p, double* x, double* u, double* w, const double* r,
+                             const double* Ff, const double* Tf) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p.bin_count)
-    for (int b = i; b < p.nbins; b += gridDim.x * blockDim.x) p.bin_count[b] = 0;
   if (i >= p.n) return;
-  const int D = p.three_d ? 3 : 2;
-  if (!p.kinematic) {
-    const double ri = r[i];
-    const double V = p.three_d ? (4.0 / 3.0) * M_PI * ri * ri * ri : M_PI * ri * ri;
-    const double m = p.rho_p * V;
-    const double I = p.three_d ? 0.4 * m * ri * ri : 0.5 * m * ri * ri;
-    const double* F = Ff + (size_t)p.fstride * i;
-    const double* T = Tf + (size_t)p.tstride * i;
-    for (int a = 0; a < D; ++a) {
-      const double G = (p.rho_p - p.rho_f) * V * p.g[a];
-      u[3 * i + a] += p.dt * (F[a] + Fc[3 * i + a] + G) / m;
-      x[3 * i + a] += p.dt * u[3 * i + a];
-    }
-    if (p.three_d) {
-      for (int a = 0; a < 3; ++a) w[3 * i + a] += p.dt * T[a] / I;
-    } else {
-      w[3 * i + 2] += p.dt * T[2] / I;
-    }
-  } else {
-    for (int a = 0; a < D; ++a) x[3 * i + a] += p.dt * u[3 * i + a];
-  }
-  if (p.wrap) {
-    for (int a = 0; a < D; ++a) {
-      if (!p.periodic[a]) continue;
-      const double L = (double)p.L[a];
-      if (x[3 * i + a] >= L) x[3 * i + a] -= L;
-      else if (x[3 * i + a] < 0.0) x[3 * i + a] += L;
-    }
-  }
+  integrate_one(p, i, x, u, w, r[i], Ff + (size_t)p.fstride * i, Tf + (size_t)p.tstride * i,
+                0.0, 0.0, 0.0);
 }
 
 int launch_dem_reset(psclbm_ctx* c) {
@@ -336,13 +355,11 @@ int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doub
     T = F + 3;
     ia.fstride = ia.tstride = 6;
   }
-  ia.bin_count = nullptr;
-  ia.nbins = 0;
   const int blocks = (n + 127) / 128;
   if (prm->kinematic) {
     for (int s = 0; s < prm->n_sub; ++s) {
       ia.wrap = s == prm->n_sub - 1;
-      k_dem_integrate<<<blocks, 128, 0, c->stream>>>(ia, x, u, w, r, F, T, c->fcontact);
+      k_dem_advect<<<blocks, 128, 0, c->stream>>>(ia, x, u, w, r, F, T);
       int rc = hip_ok(hipGetLastError());
       if (rc) return rc;
     }
@@ -366,30 +383,31 @@ int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doub
     d.bin_size[a] = c->bin_size[a];
   }
   d.bin_cap = c->bin_cap;
-  d.bin_count = c->bin_count;
+  d.nbins = c->nbin[0] * c->nbin[1] * c->nbin[2];
   d.bin_list = c->bin_list;
+  d.src = c->dem_src;
   d.max_contacts = c->cfg.max_contacts;
-  d.fc = c->fcontact;
   d.E = E;
   d.gamma = prm->gamma;
   d.eta_n = prm->eta_n;
   d.err = c->err;
-  // bins are all-zero on entry (workspace init, then cleared after each use)
-  ia.bin_count = c->bin_count;
-  ia.nbins = c->nbin[0] * c->nbin[1] * c->nbin[2];
-  const int iblocks = (ia.nbins > n ? ia.nbins + 127 : n + 127) / 128;
+  const int bblocks = (d.nbins > n ? d.nbins + 127 : n + 127) / 128;
   for (int s = 0; s < prm->n_sub; ++s) {
     ia.wrap = s == prm->n_sub - 1;  // positions wrap once, after the last sub-step
     d.prev_n = c->contact_n[c->contact_cur];
     d.prev_id = c->contact_id[c->contact_cur];
     d.next_n = c->contact_n[c->contact_cur ^ 1];
     d.next_id = c->contact_id[c->contact_cur ^ 1];
-    k_dem_bin<<<blocks, 128, 0, c->stream>>>(d, x);
-    k_dem_contacts<<<(n + 3) / 4, 256, 0, c->stream>>>(d, x, u, r);
-    k_dem_integrate<<<iblocks, 128, 0, c->stream>>>(ia, x, u, w, r, F, T, c->fcontact);
+    // the counts to fill are all zero (workspace init, or cleared by the
+    // previous binning, which filled the other set)
+    d.bin_count = c->bin_count_buf[c->bin_cur ^ 1];
+    d.bin_stale = c->bin_count_buf[c->bin_cur];
+    k_dem_bin<<<bblocks, 128, 0, c->stream>>>(d, x, u);
+    k_dem_contacts<<<(n + 3) / 4, 256, 0, c->stream>>>(d, ia, x, u, w, r, F, T);
     int rc = hip_ok(hipGetLastError());
     if (rc) return rc;
     c->contact_cur ^= 1;
+    c->bin_cur ^= 1;
   }
   return PSCLBM_OK;
 }

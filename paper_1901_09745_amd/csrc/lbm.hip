@@ -651,44 +651,6 @@ __device__ inline double va3d(double r) {  // Eq. 17 (principal-value arctangent
          (r2 - 1.0 / 12.0) * atan(0.5 / s) - (4.0 / 3.0) * r2 * r * atan(0.25 / (r * s));
 }
 
-__global__ void k_snapshot(int n, int three_d, const double* x, const double* u, const double* w,
-                           const double* r, PSnap* snap, int* tile_count, int ntiles,
-                           double* f0, double* f1, unsigned* err) {
-  const long long tot = n > ntiles ? n : ntiles;
-  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < tot;
-       k += (long long)gridDim.x * blockDim.x) {
-    if (k < ntiles) tile_count[k] = 0;
-    if (k < n) {
-      PSnap P;
-      for (int a = 0; a < 3; ++a) {
-        P.x[a] = x[3 * k + a];
-        P.u[a] = u[3 * k + a];
-        P.w[a] = w[3 * k + a];
-      }
-      if (!three_d) {
-        P.x[2] = 0.0;
-        P.u[2] = 0.0;
-        P.w[0] = P.w[1] = 0.0;
-      }
-      P.r = r[k];
-      P.pad = 0.0;
-      const bool ok = P.r * P.r > (three_d ? 0.5 : 0.25) && P.r < 1e300;
-      if (!ok) {
-        atomicOr(err, ERR_RADIUS);
-        P.cs = -1e300;  // never covers a cell
-        P.r = 0.0;
-      } else {
-        P.cs = (three_d ? va3d(P.r) : va2d(P.r)) + 0.5;
-      }
-      snap[k] = P;
-      for (int a = 0; a < 6; ++a) {
-        f0[6 * k + a] = 0.0;
-        f1[6 * k + a] = 0.0;
-      }
-    }
-  }
-}
-
 // Tiles touched along one axis by the cell range [lo, hi]: emits at most two
 // runs of tile indices (the second after a periodic wrap).
 struct AxisRuns {
@@ -737,16 +699,53 @@ __device__ inline AxisRuns axis_runs(int lo, int hi, int L, int T, int periodic)
   return r;
 }
 
-// One wave per particle: the lanes stride over the tiles of the particle's
-// shell box (at most two runs per axis after a periodic wrap).
-__global__ void __launch_bounds__(256) k_bin(Geom g, int n, double h, const PSnap* snap,
-                                             int* tile_count, int* tile_list, int cap,
-                                             unsigned* err) {
-  const int s = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+// One wave per particle: the particle's snapshot (with V_a of Eq. 17 / 19),
+// its force / torque rows cleared in both buffers, and its entry in the list
+// of every tile of its shell box (at most two runs per axis after a periodic
+// wrap), the lanes striding over the tiles.  The list counts are double
+// buffered: this launch fills `count` (all zero on entry) and clears `stale`,
+// the counts of the previous rasterisation, for the next one.
+__global__ void __launch_bounds__(256) k_rasterize(Geom g, int n, int three_d, double h,
+                                                   const double* x, const double* u,
+                                                   const double* w, const double* r,
+                                                   PSnap* snap, int* count, int* stale,
+                                                   int* tile_list, int cap, double* f0,
+                                                   double* f1, unsigned* err) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (long long k = gid; k < g.ntx * (long long)g.nty * g.ntz;
+       k += (long long)gridDim.x * blockDim.x)
+    stale[k] = 0;
+  const int s = (int)(gid >> 6);
   const int lane = (int)(threadIdx.x & 63);
   if (s >= n) return;  // uniform over the wave
-  const PSnap P = snap[s];
-  if (!(P.r > 0.0)) return;
+  PSnap P;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    P.x[a] = x[3 * s + a];
+    P.u[a] = u[3 * s + a];
+    P.w[a] = w[3 * s + a];
+  }
+  if (!three_d) {
+    P.x[2] = 0.0;
+    P.u[2] = 0.0;
+    P.w[0] = P.w[1] = 0.0;
+  }
+  P.r = r[s];
+  P.pad = 0.0;
+  const bool ok = P.r * P.r > (three_d ? 0.5 : 0.25) && P.r < 1e300;
+  if (!ok) {
+    P.cs = -1e300;  // never covers a cell
+    P.r = 0.0;
+  } else {
+    P.cs = (three_d ? va3d(P.r) : va2d(P.r)) + 0.5;
+  }
+  if (lane == 0) {
+    snap[s] = P;
+    if (!ok) atomicOr(err, ERR_RADIUS);
+  }
+  if (lane < 6) f0[6 * s + lane] = 0.0;
+  else if (lane < 12) f1[6 * s + lane - 6] = 0.0;
+  if (!ok) return;
   const double R = P.r + h;
   const int L[3] = {g.nx, g.ny, g.nz};
   const int T[3] = {TX, TY, TZ};
@@ -755,7 +754,7 @@ __global__ void __launch_bounds__(256) k_bin(Geom g, int n, double h, const PSna
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     int lo, hi;
-    if (a == 2 && g.q == 9) {
+    if (a == 2 && !three_d) {
       lo = hi = 0;
     } else {
       lo = (int)ceil(P.x[a] - R);
@@ -774,7 +773,7 @@ __global__ void __launch_bounds__(256) k_bin(Geom g, int n, double h, const PSna
     const int ty = iy < la[1] ? runs[1].a0 + iy : runs[1].b0 + (iy - la[1]);
     const int tz = iz < la[2] ? runs[2].a0 + iz : runs[2].b0 + (iz - la[2]);
     const int t = tx + g.ntx * (ty + g.nty * tz);
-    const int slot = atomicAdd(&tile_count[t], 1);
+    const int slot = atomicAdd(&count[t], 1);
     if (slot < cap)
       tile_list[(size_t)t * cap + slot] = s;
     else
@@ -910,20 +909,19 @@ int launch_get_macros(psclbm_ctx* c, double* rho, double* u) {
 
 int launch_rasterize(psclbm_ctx* c, const psclbm_particles* p) {
   const int three_d = c->geom.q == 19;
-  const long long tot = p->n > c->ntiles ? p->n : c->ntiles;
-  if (p->n > 0 || c->ntiles > 0) {
-    k_snapshot<<<grid_for(tot), 256, 0, c->stream>>>(p->n, three_d, p->x, p->u, p->omega,
-                                                     p->radius, c->snap, c->tile_count, c->ntiles,
-                                                     c->facc[0], c->facc[1], c->err);
-    int rc = hip_ok(hipGetLastError());
-    if (rc) return rc;
-  }
-  if (p->n > 0) {
-    k_bin<<<(p->n + 3) / 4, 256, 0, c->stream>>>(c->geom, p->n, c->cfg.shell_h, c->snap,
-                                                      c->tile_count, c->tile_list,
-                                                      c->cfg.max_tile_particles, c->err);
-    return hip_ok(hipGetLastError());
-  }
+  const int next = c->tile_cur ^ 1;
+  long long blocks = ((long long)p->n + 3) / 4;
+  const long long clear_blocks = ((long long)c->ntiles + 255) / 256;
+  if (blocks < clear_blocks) blocks = clear_blocks < 4096 ? clear_blocks : 4096;
+  if (blocks < 1) blocks = 1;
+  k_rasterize<<<(unsigned)blocks, 256, 0, c->stream>>>(
+      c->geom, p->n, three_d, c->cfg.shell_h, p->x, p->u, p->omega, p->radius, c->snap,
+      c->tile_count_buf[next], c->tile_count_buf[c->tile_cur], c->tile_list,
+      c->cfg.max_tile_particles, c->facc[0], c->facc[1], c->err);
+  const int rc = hip_ok(hipGetLastError());
+  if (rc) return rc;
+  c->tile_cur = next;
+  c->tile_count = c->tile_count_buf[next];
   return PSCLBM_OK;
 }
 
