@@ -197,6 +197,21 @@ int dem_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double*
              double* d_omega, const double* d_radius, int n, const double* d_force,
              const double* d_torque);
 
+/* nsteps coupled time steps in the order of Sec. 2.5: each step rasterises
+ * the particles at their current state (psc_rasterize), takes one lbm_step
+ * and advances the particles by one dem_step driven by that step's force and
+ * torque, in place in d_x, d_u, d_omega (n particles, d_radius[n]).  The
+ * result is that of those three calls in turn, up to the order of the FP64
+ * sums of contact forces.  With n_sub == 1 the work of consecutive steps is
+ * fused: the DEM wave of a particle, having integrated it, writes its
+ * snapshot and enters it in the tile lists and DEM bins of the next step, so
+ * a step is two kernels (plus one at the start of the call).  Afterwards the
+ * context holds the last step's rasterisation and force / torque
+ * accumulators, as after the three calls.  Errors: those of psc_rasterize,
+ * lbm_step and dem_step (EINVAL, EHIP; sticky ESLOTS, ECONTACTS). */
+int coupled_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double* d_u,
+                 double* d_omega, const double* d_radius, int n, int nsteps);
+
 /* Forget all DEM contacts (no pair is bonded). */
 int dem_reset_contacts(psclbm_ctx* ctx);
 

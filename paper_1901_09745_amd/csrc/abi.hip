@@ -120,9 +120,9 @@ Layout plan(const psclbm_config* c) {
   l.outlet_u = take(outlet ? sizeof(double) * 3 * 6 * (size_t)fs : 8);
   l.outlet_g = take(outlet ? sizeof(double) * 3 * 6 * (size_t)fs : 8);
   const int mc = np > 0 ? c->max_contacts : 1;
-  l.bin_count = take(sizeof(int) * 2 * nbins);
+  l.bin_count = take(sizeof(int) * 3 * nbins);
   l.bin_list = take(sizeof(int) * nbins * l.bin_cap * (np > 0 ? 1 : 0));
-  l.dem_src = take(sizeof(double) * 6 * (size_t)(np > 0 ? np : 1));
+  l.dem_src = take(sizeof(double) * 12 * (size_t)(np > 0 ? np : 1));
   l.cn0 = take(sizeof(int) * (size_t)(np > 0 ? np : 1));
   l.cn1 = take(sizeof(int) * (size_t)(np > 0 ? np : 1));
   l.cid0 = take(sizeof(int) * (size_t)(np > 0 ? np : 1) * mc);
@@ -215,10 +215,13 @@ int lbm_init(const psclbm_config* cfg, void* d_workspace, size_t bytes, void* hi
     const size_t nbins = (size_t)l.nbin[0] * l.nbin[1] * l.nbin[2];
     c->bin_count_buf[0] = reinterpret_cast<int*>(base + l.bin_count);
     c->bin_count_buf[1] = c->bin_count_buf[0] + nbins;
+    c->bin_count_buf[2] = c->bin_count_buf[1] + nbins;
   }
   c->bin_cur = 0;
   c->bin_list = reinterpret_cast<int*>(base + l.bin_list);
-  c->dem_src = reinterpret_cast<double*>(base + l.dem_src);
+  c->dem_src[0] = reinterpret_cast<double*>(base + l.dem_src);
+  c->dem_src[1] = c->dem_src[0] + 6 * (size_t)(cfg->max_particles > 0 ? cfg->max_particles : 1);
+  c->src_cur = 0;
   c->contact_n[0] = reinterpret_cast<int*>(base + l.cn0);
   c->contact_n[1] = reinterpret_cast<int*>(base + l.cn1);
   c->contact_id[0] = reinterpret_cast<int*>(base + l.cid0);
@@ -275,7 +278,7 @@ int psc_rasterize(psclbm_ctx* ctx, const psclbm_particles* p) {
   if (!ctx || !p) return PSCLBM_EINVAL;
   if (p->n < 0 || p->n > ctx->cfg.max_particles) return PSCLBM_EINVAL;
   if (p->n > 0 && (!p->x || !p->u || !p->omega || !p->radius)) return PSCLBM_EINVAL;
-  int rc = launch_rasterize(ctx, p);
+  int rc = launch_rasterize(ctx, p, false);
   if (rc) return rc;
   ctx->np = p->n;
   ctx->rasterized = 1;
@@ -336,6 +339,24 @@ int dem_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double*
       return PSCLBM_EINVAL;
   }
   return launch_dem_step(ctx, prm, d_x, d_u, d_omega, d_radius, n, d_force, d_torque);
+}
+
+int coupled_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double* d_u,
+                 double* d_omega, const double* d_radius, int n, int nsteps) {
+  if (!ctx || !prm || nsteps < 1) return PSCLBM_EINVAL;
+  if (n < 0 || n > ctx->cfg.max_particles) return PSCLBM_EINVAL;
+  if (n > 0 && (!d_x || !d_u || !d_omega || !d_radius)) return PSCLBM_EINVAL;
+  if (prm->n_sub < 1 || !(prm->dt > 0.0) || !std::isfinite(prm->dt)) return PSCLBM_EINVAL;
+  if (!prm->kinematic) {
+    if (!(prm->rho_p > 0.0) || !(prm->E_p > 0.0) || !(prm->gamma >= 0.0) ||
+        !(prm->poisson > -1.0 && prm->poisson < 0.5) || !(prm->eta_n >= 0.0))
+      return PSCLBM_EINVAL;
+  }
+  const int rc = launch_coupled(ctx, prm, d_x, d_u, d_omega, d_radius, n, nsteps);
+  if (rc) return rc;
+  ctx->np = n;
+  ctx->rasterized = 1;
+  return PSCLBM_OK;
 }
 
 int dem_reset_contacts(psclbm_ctx* ctx) {

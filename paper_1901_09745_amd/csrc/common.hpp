@@ -175,10 +175,11 @@ struct psclbm_ctx {
   int nbin[3];
   double bin_size[3];
   int bin_cap;
-  int* bin_count_buf[2];  // double-buffered: each binning clears the other
-  int bin_cur;
+  int* bin_count_buf[3];  // each binning fills set cur+1 and clears set cur+2
+  int bin_cur;            // the set of the latest binning
   int* bin_list;
-  double* dem_src;        // [n][6]: x, u at the start of the DEM sub-step
+  double* dem_src[2];     // [n][6] images of x, u at a DEM sub-step's start
+  int src_cur;            // the image of the latest binning
   int* contact_n[2];
   int* contact_id[2];
   int contact_cur;
@@ -192,6 +193,41 @@ struct psclbm_ctx {
 };
 
 namespace psclbm {
+// Target of a DEM binning: the count set to fill (all zero on entry), the set
+// to clear for the binning after next, the bin lists and the image of x, u
+// the contact pass of that binning reads.
+struct DemBinOut {
+  int* count;  // null: no DEM binning
+  int* stale;
+  long long nbins;
+  int* bin_list;
+  int bin_cap;
+  int nbin[3];
+  double bin_size[3];
+  double* src;
+};
+
+inline DemBinOut dem_bin_out(const psclbm_ctx* c, bool on) {
+  DemBinOut b;
+  b.count = on ? c->bin_count_buf[(c->bin_cur + 1) % 3] : nullptr;
+  b.stale = c->bin_count_buf[(c->bin_cur + 2) % 3];
+  b.nbins = on ? (long long)c->nbin[0] * c->nbin[1] * c->nbin[2] : 0;
+  b.bin_list = c->bin_list;
+  b.bin_cap = c->bin_cap;
+  for (int a = 0; a < 3; ++a) {
+    b.nbin[a] = c->nbin[a];
+    b.bin_size[a] = c->bin_size[a];
+  }
+  b.src = c->dem_src[c->src_cur ^ 1];
+  return b;
+}
+
+// After a launch that binned through dem_bin_out: its sets become current.
+inline void dem_bins_advance(psclbm_ctx* c) {
+  c->bin_cur = (c->bin_cur + 1) % 3;
+  c->src_cur ^= 1;
+}
+
 // Sum of a double over the 64 lanes of a wave with DPP lane moves (no LDS
 // traffic): pairs and quads by quad permutes, rows of 16 by row shifts, then
 // row broadcasts 15 and 31 carry the row totals up to lane 63, whose value is
@@ -226,7 +262,9 @@ int launch_init_equilibrium(psclbm_ctx* c, const double* rho, const double* u);
 int launch_set_f(psclbm_ctx* c, const double* f);
 int launch_get_f(psclbm_ctx* c, double* f);
 int launch_get_macros(psclbm_ctx* c, double* rho, double* u);
-int launch_rasterize(psclbm_ctx* c, const psclbm_particles* p);
+int launch_rasterize(psclbm_ctx* c, const psclbm_particles* p, bool dem_bins);
+int launch_coupled(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, double* u, double* w,
+                   const double* r, int n, int nsteps);
 int launch_solid_fraction(psclbm_ctx* c, double* eps, int* ids, double* seps, int k);
 int launch_step(psclbm_ctx* c);
 int launch_recompute(psclbm_ctx* c, const double* f0, int nsteps, double* ring);

@@ -14,8 +14,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstring>
 
 #include "common.hpp"
+#include "tiles.hpp"
 
 namespace psclbm {
 
@@ -27,11 +29,9 @@ struct DemArgs {
   int nbin[3];
   double bin_size[3];
   int bin_cap;
-  int* bin_count;        // counts filled by this sub-step's binning
-  int* bin_stale;        // the other set, cleared by this binning
-  int nbins;
-  int* bin_list;
-  double* src;           // [n][6] image of x, u at the start of the sub-step
+  const int* bin_count;  // counts of the current binning
+  const int* bin_list;
+  const double* src;     // [n][6] image of x, u at the start of the sub-step
   const int* prev_n;
   const int* prev_id;
   int* next_n;
@@ -85,35 +85,17 @@ __device__ inline double jkr_force(double R, double E, double gamma, double delt
 }
 
 __device__ inline int bin_coord(double x, int a, const DemArgs& d) {
-  double v = x;
-  if (d.periodic[a]) {
-    v = fmod(v, (double)d.L[a]);
-    if (v < 0) v += d.L[a];
-  }
-  int b = (int)floor(v / d.bin_size[a]);
-  if (b < 0) b = 0;
-  if (b >= d.nbin[a]) b = d.nbin[a] - 1;
-  return b;
+  return dem_bin_coord(x, d.L[a], d.periodic[a], d.nbin[a], d.bin_size[a]);
 }
 
-__global__ void k_dem_bin(DemArgs d, const double* x, const double* u) {
+// One thread per particle: its bin in the target set and its image; the
+// grid also clears the set the binning after next fills.
+__global__ void k_dem_bin(DemBinOut b, Geom g, int n, int three_d, const double* x,
+                          const double* u, unsigned* err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  for (int b = i; b < d.nbins; b += gridDim.x * blockDim.x) d.bin_stale[b] = 0;
-  if (i >= d.n) return;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    d.src[6 * i + a] = x[3 * i + a];
-    d.src[6 * i + 3 + a] = u[3 * i + a];
-  }
-  const int bx = bin_coord(x[3 * i], 0, d);
-  const int by = bin_coord(x[3 * i + 1], 1, d);
-  const int bz = d.three_d ? bin_coord(x[3 * i + 2], 2, d) : 0;
-  const int b = bx + d.nbin[0] * (by + d.nbin[1] * bz);
-  const int k = atomicAdd(&d.bin_count[b], 1);
-  if (k < d.bin_cap)
-    d.bin_list[(size_t)b * d.bin_cap + k] = i;
-  else
-    atomicOr(d.err, ERR_CONTACTS);
+  for (long long k = i; k < b.nbins; k += (long long)gridDim.x * blockDim.x) b.stale[k] = 0;
+  if (i >= n) return;
+  dem_bin_insert(b, three_d, g, i, x + 3 * i, u + 3 * i, err);
 }
 
 // Distinct neighbour-bin offsets along one axis.
@@ -155,57 +137,93 @@ struct IntArgs {
   int fstride, tstride;  // element strides of the force / torque rows
 };
 
-// Semi-implicit Euler (Eq. 21) of particle i with hydrodynamic force F,
-// torque T and contact force fc: u += dt (F + fc + G)/m, x += dt u,
-// omega += dt T/I, then the wrap into [0, L) on periodic axes.
-__device__ inline void integrate_one(const IntArgs& p, int i, double* x, double* u, double* w,
-                                     double ri, const double* F, const double* T, double fc0,
-                                     double fc1, double fc2) {
+// Semi-implicit Euler (Eq. 21) with hydrodynamic force F, torque T and
+// contact force fc: u += dt (F + fc + G)/m, x += dt u, omega += dt T/I, then
+// the wrap into [0, L) on periodic axes (kinematic: x += dt u only).
+__device__ inline void integrate_state(const IntArgs& p, double ri, const double* F,
+                                       const double* T, const double* fc, double* x, double* u,
+                                       double* w) {
   const int D = p.three_d ? 3 : 2;
-  const double fc[3] = {fc0, fc1, fc2};
   if (!p.kinematic) {
     const double V = p.three_d ? (4.0 / 3.0) * M_PI * ri * ri * ri : M_PI * ri * ri;
     const double m = p.rho_p * V;
     const double I = p.three_d ? 0.4 * m * ri * ri : 0.5 * m * ri * ri;
     for (int a = 0; a < D; ++a) {
       const double G = (p.rho_p - p.rho_f) * V * p.g[a];
-      u[3 * i + a] += p.dt * (F[a] + fc[a] + G) / m;
-      x[3 * i + a] += p.dt * u[3 * i + a];
+      u[a] += p.dt * (F[a] + fc[a] + G) / m;
+      x[a] += p.dt * u[a];
     }
     if (p.three_d) {
-      for (int a = 0; a < 3; ++a) w[3 * i + a] += p.dt * T[a] / I;
+      for (int a = 0; a < 3; ++a) w[a] += p.dt * T[a] / I;
     } else {
-      w[3 * i + 2] += p.dt * T[2] / I;
+      w[2] += p.dt * T[2] / I;
     }
   } else {
-    for (int a = 0; a < D; ++a) x[3 * i + a] += p.dt * u[3 * i + a];
+    for (int a = 0; a < D; ++a) x[a] += p.dt * u[a];
   }
   if (p.wrap) {
     for (int a = 0; a < D; ++a) {
       if (!p.periodic[a]) continue;
       const double L = (double)p.L[a];
-      if (x[3 * i + a] >= L) x[3 * i + a] -= L;
-      else if (x[3 * i + a] < 0.0) x[3 * i + a] += L;
+      if (x[a] >= L) x[a] -= L;
+      else if (x[a] < 0.0) x[a] += L;
     }
   }
 }
 
+// Rasterisation of the next coupled step by the DEM wave of this one: the
+// tile set to fill (all zero on entry) and the one to clear, the snapshot and
+// the DEM binning of the updated particle.
+struct NextOut {
+  int build;
+  Geom g;
+  double h;
+  PSnap* snap;
+  int* tcount;
+  int* tstale;
+  long long ntiles;
+  int* tile_list;
+  int cap;
+  DemBinOut db;
+  unsigned* err;
+};
+
 // One wave per particle.  The lanes stride over the (neighbour bin, slot)
 // candidates and the walls; contacts are compacted into the new contact list
-// with a ballot, the contact force is summed over the wave, and lane 0
-// integrates the particle.  Positions and velocities of the sub-step are read
-// from the binning's image, the particle's update goes to x, u, w.
-__global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, IntArgs ia, double* x, double* u,
-                                                      double* w, const double* r,
-                                                      const double* Ff, const double* Tf) {
-  const int i = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+// with a ballot and the contact force is summed over the wave.  Every lane
+// then integrates the particle (the same values), lane 0 stores it, and with
+// nx.build the wave rasterises it for the next coupled step.  Positions and
+// velocities of the other particles are read from the binning's image, so no
+// particle sees another's update.  Kinematic particles skip the contacts.
+__global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, IntArgs ia, NextOut nx,
+                                                      double* x, double* u, double* w,
+                                                      const double* r, const double* Ff,
+                                                      const double* Tf) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (nx.build) {
+    for (long long k = gid; k < nx.ntiles; k += (long long)gridDim.x * blockDim.x)
+      nx.tstale[k] = 0;
+    if (nx.db.count)
+      for (long long k = gid; k < nx.db.nbins; k += (long long)gridDim.x * blockDim.x)
+        nx.db.stale[k] = 0;
+  }
+  const int i = (int)(gid >> 6);
   const int lane = (int)(threadIdx.x & 63);
   if (i >= d.n) return;  // uniform over the wave
   const int D = d.three_d ? 3 : 2;
+  const double ri = r[i];
+  double xs[3], us[3], ws[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    xs[a] = x[3 * i + a];
+    us[a] = u[3 * i + a];
+    ws[a] = w[3 * i + a];
+  }
+  double fsum[3] = {0.0, 0.0, 0.0};
+  if (!ia.kinematic) {
   const double* S = d.src;
   const double xi0 = S[6 * i], xi1 = S[6 * i + 1], xi2 = d.three_d ? S[6 * i + 2] : 0.0;
   const double ui0 = S[6 * i + 3], ui1 = S[6 * i + 4], ui2 = d.three_d ? S[6 * i + 5] : 0.0;
-  const double ri = r[i];
   const int pn = d.prev_n[i];
   const int* prev = d.prev_id + (size_t)i * d.max_contacts;
   int* next = d.next_id + (size_t)i * d.max_contacts;
@@ -301,18 +319,36 @@ __global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, IntArgs ia, dou
     }
     cnt += __popcll(m);
   }
-  fs0 = wave_sum(fs0);
-  fs1 = wave_sum(fs1);
-  fs2 = wave_sum(fs2);
+  fsum[0] = wave_sum(fs0);
+  fsum[1] = wave_sum(fs1);
+  fsum[2] = wave_sum(fs2);
   if (lane == 0) {
     if (cnt > d.max_contacts) {
       atomicOr(d.err, ERR_CONTACTS);
       cnt = d.max_contacts;
     }
     d.next_n[i] = cnt;
-    integrate_one(ia, i, x, u, w, ri, Ff + (size_t)ia.fstride * i, Tf + (size_t)ia.tstride * i,
-                  fs0, fs1, fs2);
   }
+  }
+  integrate_state(ia, ri, Ff + (size_t)ia.fstride * i, Tf + (size_t)ia.tstride * i, fsum, xs, us,
+                  ws);
+  if (lane == 0) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      x[3 * i + a] = xs[a];
+      u[3 * i + a] = us[a];
+      w[3 * i + a] = ws[a];
+    }
+  }
+  if (!nx.build) return;
+  PSnap P;
+  const bool ok = make_snap(d.three_d, xs, us, ws, ri, P);
+  if (lane == 0) {
+    nx.snap[i] = P;
+    if (!ok) atomicOr(nx.err, ERR_RADIUS);
+    if (nx.db.count) dem_bin_insert(nx.db, d.three_d, nx.g, i, xs, us, nx.err);
+  }
+  if (ok) bin_tiles(nx.g, d.three_d, nx.h, P, i, lane, nx.tcount, nx.tile_list, nx.cap, nx.err);
 }
 
 // Kinematic particles (prescribed velocities): x += dt u.
@@ -320,8 +356,9 @@ __global__ void k_dem_advect(IntArgs p, double* x, double* u, double* w, const d
                              const double* Ff, const double* Tf) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
-  integrate_one(p, i, x, u, w, r[i], Ff + (size_t)p.fstride * i, Tf + (size_t)p.tstride * i,
-                0.0, 0.0, 0.0);
+  const double z[3] = {0.0, 0.0, 0.0};
+  integrate_state(p, r[i], Ff + (size_t)p.fstride * i, Tf + (size_t)p.tstride * i, z, x + 3 * i,
+                  u + 3 * i, w + 3 * i);
 }
 
 int launch_dem_reset(psclbm_ctx* c) {
@@ -330,23 +367,23 @@ int launch_dem_reset(psclbm_ctx* c) {
                                sizeof(int) * (size_t)c->cfg.max_particles, c->stream));
 }
 
-int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, double* u, double* w,
-                    const double* r, int n, const double* F, const double* T) {
-  const int three_d = c->geom.q == 19;
-  const int L[3] = {c->geom.nx, c->geom.ny, c->geom.nz};
-  const double dts = prm->dt / prm->n_sub;
+static IntArgs int_args(const psclbm_ctx* c, const psclbm_dem_params* prm, int n,
+                        const double*& F, const double*& T) {
   IntArgs ia;
   ia.n = n;
-  ia.three_d = three_d;
+  ia.three_d = c->geom.q == 19;
+  ia.L[0] = c->geom.nx;
+  ia.L[1] = c->geom.ny;
+  ia.L[2] = c->geom.nz;
   for (int a = 0; a < 3; ++a) {
-    ia.L[a] = L[a];
     ia.periodic[a] = c->geom.periodic[a];
     ia.g[a] = prm->g[a];
   }
-  ia.dt = dts;
+  ia.dt = prm->dt / prm->n_sub;
   ia.rho_p = prm->rho_p;
   ia.rho_f = prm->rho_f;
   ia.kinematic = prm->kinematic ? 1 : 0;
+  ia.wrap = 1;
   // NULL force and torque: the FP64 accumulators of the most recent lbm_step
   ia.fstride = 3;
   ia.tstride = 3;
@@ -355,6 +392,51 @@ int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doub
     T = F + 3;
     ia.fstride = ia.tstride = 6;
   }
+  return ia;
+}
+
+// Effective modulus of two bodies of the material (Eq. 25); 0 when the
+// contact reach delta_C of the largest pair does not fit in the bin margin.
+static double dem_modulus(const psclbm_ctx* c, const psclbm_dem_params* prm) {
+  const double E = 1.0 / (2.0 * (1.0 - prm->poisson * prm->poisson) / prm->E_p);
+  const double Rm = c->cfg.max_radius;  // wall contact: R = r
+  const double a0 = std::cbrt(9.0 * M_PI * prm->gamma * Rm * Rm / E);
+  const double dC = a0 * a0 / (2.0 * std::cbrt(6.0) * Rm);
+  return dC < 1.0 ? E : 0.0;
+}
+
+// Contact-pass arguments on the current binning and contact lists.
+static DemArgs dem_args(const psclbm_ctx* c, const psclbm_dem_params* prm, int n, double E) {
+  DemArgs d;
+  d.n = n;
+  d.three_d = c->geom.q == 19;
+  d.L[0] = c->geom.nx;
+  d.L[1] = c->geom.ny;
+  d.L[2] = c->geom.nz;
+  for (int a = 0; a < 3; ++a) {
+    d.periodic[a] = c->geom.periodic[a];
+    d.nbin[a] = c->nbin[a];
+    d.bin_size[a] = c->bin_size[a];
+  }
+  d.bin_cap = c->bin_cap;
+  d.bin_count = c->bin_count_buf[c->bin_cur];
+  d.bin_list = c->bin_list;
+  d.src = c->dem_src[c->src_cur];
+  d.prev_n = c->contact_n[c->contact_cur];
+  d.prev_id = c->contact_id[c->contact_cur];
+  d.next_n = c->contact_n[c->contact_cur ^ 1];
+  d.next_id = c->contact_id[c->contact_cur ^ 1];
+  d.max_contacts = c->cfg.max_contacts;
+  d.E = E;
+  d.gamma = prm->gamma;
+  d.eta_n = prm->eta_n;
+  d.err = c->err;
+  return d;
+}
+
+int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, double* u, double* w,
+                    const double* r, int n, const double* F, const double* T) {
+  IntArgs ia = int_args(c, prm, n, F, T);
   const int blocks = (n + 127) / 128;
   if (prm->kinematic) {
     for (int s = 0; s < prm->n_sub; ++s) {
@@ -365,49 +447,87 @@ int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doub
     }
     return PSCLBM_OK;
   }
-  // the contact reach delta_C of the largest pair must fit in the bin margin
-  const double E = 1.0 / (2.0 * (1.0 - prm->poisson * prm->poisson) / prm->E_p);
-  {
-    const double Rm = c->cfg.max_radius;  // wall contact: R = r
-    const double a0 = std::cbrt(9.0 * M_PI * prm->gamma * Rm * Rm / E);
-    const double dC = a0 * a0 / (2.0 * std::cbrt(6.0) * Rm);
-    if (!(dC < 1.0)) return PSCLBM_EINVAL;
-  }
-  DemArgs d;
-  d.n = n;
-  d.three_d = three_d;
-  for (int a = 0; a < 3; ++a) {
-    d.L[a] = L[a];
-    d.periodic[a] = c->geom.periodic[a];
-    d.nbin[a] = c->nbin[a];
-    d.bin_size[a] = c->bin_size[a];
-  }
-  d.bin_cap = c->bin_cap;
-  d.nbins = c->nbin[0] * c->nbin[1] * c->nbin[2];
-  d.bin_list = c->bin_list;
-  d.src = c->dem_src;
-  d.max_contacts = c->cfg.max_contacts;
-  d.E = E;
-  d.gamma = prm->gamma;
-  d.eta_n = prm->eta_n;
-  d.err = c->err;
-  const int bblocks = (d.nbins > n ? d.nbins + 127 : n + 127) / 128;
+  const double E = dem_modulus(c, prm);
+  if (!(E > 0.0)) return PSCLBM_EINVAL;
+  NextOut nx;
+  std::memset(&nx, 0, sizeof(nx));
   for (int s = 0; s < prm->n_sub; ++s) {
     ia.wrap = s == prm->n_sub - 1;  // positions wrap once, after the last sub-step
-    d.prev_n = c->contact_n[c->contact_cur];
-    d.prev_id = c->contact_id[c->contact_cur];
-    d.next_n = c->contact_n[c->contact_cur ^ 1];
-    d.next_id = c->contact_id[c->contact_cur ^ 1];
-    // the counts to fill are all zero (workspace init, or cleared by the
-    // previous binning, which filled the other set)
-    d.bin_count = c->bin_count_buf[c->bin_cur ^ 1];
-    d.bin_stale = c->bin_count_buf[c->bin_cur];
-    k_dem_bin<<<bblocks, 128, 0, c->stream>>>(d, x, u);
-    k_dem_contacts<<<(n + 3) / 4, 256, 0, c->stream>>>(d, ia, x, u, w, r, F, T);
+    const DemBinOut b = dem_bin_out(c, true);
+    const long long bth = b.nbins > n ? b.nbins : n;
+    k_dem_bin<<<(unsigned)((bth + 127) / 128), 128, 0, c->stream>>>(b, c->geom, n,
+                                                                   c->geom.q == 19, x, u, c->err);
+    dem_bins_advance(c);
+    const DemArgs d = dem_args(c, prm, n, E);
+    k_dem_contacts<<<(n + 3) / 4, 256, 0, c->stream>>>(d, ia, nx, x, u, w, r, F, T);
     int rc = hip_ok(hipGetLastError());
     if (rc) return rc;
     c->contact_cur ^= 1;
-    c->bin_cur ^= 1;
+  }
+  return PSCLBM_OK;
+}
+
+int launch_coupled(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, double* u, double* w,
+                   const double* r, int n, int nsteps) {
+  psclbm_particles pp;
+  pp.n = n;
+  pp.x = x;
+  pp.u = u;
+  pp.omega = w;
+  pp.radius = r;
+  const psclbm_particles* p = &pp;
+  double E = 0.0;
+  if (!prm->kinematic) {
+    E = dem_modulus(c, prm);
+    if (!(E > 0.0)) return PSCLBM_EINVAL;
+  }
+  if (prm->n_sub != 1 || n == 0) {
+    // sub-cycled DEM: the three calls in turn
+    for (int t = 0; t < nsteps; ++t) {
+      int rc = launch_rasterize(c, p, false);
+      if (!rc) c->np = n;
+      if (!rc) rc = launch_step(c);
+      if (!rc && n > 0)
+        rc = launch_dem_step(c, prm, x, u, w, r, n, nullptr, nullptr);
+      if (rc) return rc;
+    }
+    return PSCLBM_OK;
+  }
+  // first step's rasterisation, with its DEM binning
+  int rc = launch_rasterize(c, p, !prm->kinematic);
+  if (rc) return rc;
+  c->np = n;
+  const size_t ntiles = (size_t)c->ntiles;
+  for (int t = 0; t < nsteps; ++t) {
+    rc = launch_step(c);
+    if (rc) return rc;
+    const bool build = t + 1 < nsteps;
+    const double* F = nullptr;
+    const double* T = nullptr;
+    const IntArgs ia = int_args(c, prm, n, F, T);
+    const DemArgs d = dem_args(c, prm, n, E);
+    NextOut nx;
+    std::memset(&nx, 0, sizeof(nx));
+    nx.build = build ? 1 : 0;
+    nx.g = c->geom;
+    nx.h = c->cfg.shell_h;
+    nx.snap = c->snap;
+    nx.tcount = c->tile_count_buf[c->tile_cur ^ 1];
+    nx.tstale = c->tile_count_buf[c->tile_cur];
+    nx.ntiles = (long long)ntiles;
+    nx.tile_list = c->tile_list;
+    nx.cap = c->cfg.max_tile_particles;
+    nx.db = dem_bin_out(c, build && !prm->kinematic);
+    nx.err = c->err;
+    k_dem_contacts<<<(n + 3) / 4, 256, 0, c->stream>>>(d, ia, nx, x, u, w, r, F, T);
+    rc = hip_ok(hipGetLastError());
+    if (rc) return rc;
+    if (!prm->kinematic) c->contact_cur ^= 1;
+    if (build) {
+      c->tile_cur ^= 1;
+      c->tile_count = c->tile_count_buf[c->tile_cur];
+      if (nx.db.count) dem_bins_advance(c);
+    }
   }
   return PSCLBM_OK;
 }

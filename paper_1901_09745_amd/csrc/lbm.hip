@@ -640,65 +640,6 @@ __global__ void k_reduce(const double* part, int n, double* out) {
 // ---------------------------------------------------------------------------
 // Rasterisation: particle snapshot, then tile binning (Table 1 Step 1).
 // ---------------------------------------------------------------------------
-__device__ inline double va2d(double r) {  // Eq. 19
-  const double s = sqrt(r * r - 0.25);
-  return 0.5 * s + r * r * atan(0.5 / s);
-}
-__device__ inline double va3d(double r) {  // Eq. 17 (principal-value arctangents)
-  const double r2 = r * r;
-  const double s = sqrt(r2 - 0.5);
-  return (1.0 / 12.0 - r2) * atan(0.5 * s / (0.5 - r2)) + s / 3.0 +
-         (r2 - 1.0 / 12.0) * atan(0.5 / s) - (4.0 / 3.0) * r2 * r * atan(0.25 / (r * s));
-}
-
-// Tiles touched along one axis by the cell range [lo, hi]: emits at most two
-// runs of tile indices (the second after a periodic wrap).
-struct AxisRuns {
-  int a0, a1, b0, b1;  // runs [a0, a1] and [b0, b1] (b0 > b1 when absent)
-};
-
-__device__ inline AxisRuns axis_runs(int lo, int hi, int L, int T, int periodic) {
-  AxisRuns r;
-  r.b0 = 1;
-  r.b1 = 0;
-  const int nt = (L + T - 1) / T;
-  if (!periodic) {
-    if (lo < 0) lo = 0;
-    if (hi > L - 1) hi = L - 1;
-    if (lo > hi) {
-      r.a0 = 1;
-      r.a1 = 0;
-      return r;
-    }
-    r.a0 = lo / T;
-    r.a1 = hi / T;
-    return r;
-  }
-  if (hi - lo + 1 >= L) {
-    r.a0 = 0;
-    r.a1 = nt - 1;
-    return r;
-  }
-  const int wl = ((lo % L) + L) % L;
-  const int wh = ((hi % L) + L) % L;
-  if (wl <= wh) {
-    r.a0 = wl / T;
-    r.a1 = wh / T;
-  } else {
-    const int t0 = wl / T, t1 = wh / T;
-    if (t1 >= t0) {
-      r.a0 = 0;
-      r.a1 = nt - 1;
-    } else {
-      r.a0 = t0;
-      r.a1 = nt - 1;
-      r.b0 = 0;
-      r.b1 = t1;
-    }
-  }
-  return r;
-}
-
 // One wave per particle: the particle's snapshot (with V_a of Eq. 17 / 19),
 // its force / torque rows cleared in both buffers, and its entry in the list
 // of every tile of its shell box (at most two runs per axis after a periodic
@@ -710,75 +651,27 @@ __global__ void __launch_bounds__(256) k_rasterize(Geom g, int n, int three_d, d
                                                    const double* w, const double* r,
                                                    PSnap* snap, int* count, int* stale,
                                                    int* tile_list, int cap, double* f0,
-                                                   double* f1, unsigned* err) {
+                                                   double* f1, unsigned* err, DemBinOut db) {
   const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   for (long long k = gid; k < g.ntx * (long long)g.nty * g.ntz;
        k += (long long)gridDim.x * blockDim.x)
     stale[k] = 0;
+  if (db.count)
+    for (long long k = gid; k < db.nbins; k += (long long)gridDim.x * blockDim.x) db.stale[k] = 0;
   const int s = (int)(gid >> 6);
   const int lane = (int)(threadIdx.x & 63);
   if (s >= n) return;  // uniform over the wave
   PSnap P;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    P.x[a] = x[3 * s + a];
-    P.u[a] = u[3 * s + a];
-    P.w[a] = w[3 * s + a];
-  }
-  if (!three_d) {
-    P.x[2] = 0.0;
-    P.u[2] = 0.0;
-    P.w[0] = P.w[1] = 0.0;
-  }
-  P.r = r[s];
-  P.pad = 0.0;
-  const bool ok = P.r * P.r > (three_d ? 0.5 : 0.25) && P.r < 1e300;
-  if (!ok) {
-    P.cs = -1e300;  // never covers a cell
-    P.r = 0.0;
-  } else {
-    P.cs = (three_d ? va3d(P.r) : va2d(P.r)) + 0.5;
-  }
+  const bool ok = make_snap(three_d, x + 3 * s, u + 3 * s, w + 3 * s, r[s], P);
   if (lane == 0) {
     snap[s] = P;
     if (!ok) atomicOr(err, ERR_RADIUS);
+    if (db.count) dem_bin_insert(db, three_d, g, s, x + 3 * s, u + 3 * s, err);
   }
   if (lane < 6) f0[6 * s + lane] = 0.0;
   else if (lane < 12) f1[6 * s + lane - 6] = 0.0;
   if (!ok) return;
-  const double R = P.r + h;
-  const int L[3] = {g.nx, g.ny, g.nz};
-  const int T[3] = {TX, TY, TZ};
-  AxisRuns runs[3];
-  int la[3], lt[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    int lo, hi;
-    if (a == 2 && !three_d) {
-      lo = hi = 0;
-    } else {
-      lo = (int)ceil(P.x[a] - R);
-      hi = (int)floor(P.x[a] + R);
-    }
-    runs[a] = axis_runs(lo, hi, L[a], T[a], g.periodic[a]);
-    la[a] = runs[a].a1 >= runs[a].a0 ? runs[a].a1 - runs[a].a0 + 1 : 0;
-    lt[a] = la[a] + (runs[a].b1 >= runs[a].b0 ? runs[a].b1 - runs[a].b0 + 1 : 0);
-  }
-  const int total = lt[0] * lt[1] * lt[2];
-  for (int k = lane; k < total; k += 64) {
-    const int ix = k % lt[0];
-    const int iy = (k / lt[0]) % lt[1];
-    const int iz = k / (lt[0] * lt[1]);
-    const int tx = ix < la[0] ? runs[0].a0 + ix : runs[0].b0 + (ix - la[0]);
-    const int ty = iy < la[1] ? runs[1].a0 + iy : runs[1].b0 + (iy - la[1]);
-    const int tz = iz < la[2] ? runs[2].a0 + iz : runs[2].b0 + (iz - la[2]);
-    const int t = tx + g.ntx * (ty + g.nty * tz);
-    const int slot = atomicAdd(&count[t], 1);
-    if (slot < cap)
-      tile_list[(size_t)t * cap + slot] = s;
-    else
-      atomicOr(err, ERR_SLOTS);
-  }
+  bin_tiles(g, three_d, h, P, s, lane, count, tile_list, cap, err);
 }
 
 template <int D>
@@ -907,21 +800,24 @@ int launch_get_macros(psclbm_ctx* c, double* rho, double* u) {
   return hip_ok(hipGetLastError());
 }
 
-int launch_rasterize(psclbm_ctx* c, const psclbm_particles* p) {
+int launch_rasterize(psclbm_ctx* c, const psclbm_particles* p, bool dem_bins) {
   const int three_d = c->geom.q == 19;
   const int next = c->tile_cur ^ 1;
+  DemBinOut db = dem_bin_out(c, dem_bins);
   long long blocks = ((long long)p->n + 3) / 4;
-  const long long clear_blocks = ((long long)c->ntiles + 255) / 256;
+  long long clear = c->ntiles > db.nbins ? c->ntiles : db.nbins;
+  const long long clear_blocks = (clear + 255) / 256;
   if (blocks < clear_blocks) blocks = clear_blocks < 4096 ? clear_blocks : 4096;
   if (blocks < 1) blocks = 1;
   k_rasterize<<<(unsigned)blocks, 256, 0, c->stream>>>(
       c->geom, p->n, three_d, c->cfg.shell_h, p->x, p->u, p->omega, p->radius, c->snap,
       c->tile_count_buf[next], c->tile_count_buf[c->tile_cur], c->tile_list,
-      c->cfg.max_tile_particles, c->facc[0], c->facc[1], c->err);
+      c->cfg.max_tile_particles, c->facc[0], c->facc[1], c->err, db);
   const int rc = hip_ok(hipGetLastError());
   if (rc) return rc;
   c->tile_cur = next;
   c->tile_count = c->tile_count_buf[next];
+  if (dem_bins) dem_bins_advance(c);
   return PSCLBM_OK;
 }
 

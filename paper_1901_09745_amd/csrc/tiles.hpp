@@ -251,4 +251,166 @@ __device__ __forceinline__ unsigned link(const Dims& d, int x, int y, int z, int
   return WALLS ? out : 0u;
 }
 
+// ---------------------------------------------------------------------------
+// Particle snapshot and tile binning (Table 1 Step 1), shared by the
+// rasterisation and by the DEM kernel that rasterises the next step.
+// ---------------------------------------------------------------------------
+__device__ inline double va2d(double r) {  // Eq. 19
+  const double s = sqrt(r * r - 0.25);
+  return 0.5 * s + r * r * atan(0.5 / s);
+}
+__device__ inline double va3d(double r) {  // Eq. 17 (principal-value arctangents)
+  const double r2 = r * r;
+  const double s = sqrt(r2 - 0.5);
+  return (1.0 / 12.0 - r2) * atan(0.5 * s / (0.5 - r2)) + s / 3.0 +
+         (r2 - 1.0 / 12.0) * atan(0.5 / s) - (4.0 / 3.0) * r2 * r * atan(0.25 / (r * s));
+}
+
+// Snapshot of a particle; false when the radius is outside the domain of
+// Eq. 17 / 19 (the snapshot then covers no cell).
+__device__ inline bool make_snap(int three_d, const double* x, const double* u, const double* w,
+                                 double r, PSnap& P) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    P.x[a] = x[a];
+    P.u[a] = u[a];
+    P.w[a] = w[a];
+  }
+  if (!three_d) {
+    P.x[2] = 0.0;
+    P.u[2] = 0.0;
+    P.w[0] = P.w[1] = 0.0;
+  }
+  P.r = r;
+  P.pad = 0.0;
+  const bool ok = P.r * P.r > (three_d ? 0.5 : 0.25) && P.r < 1e300;
+  if (!ok) {
+    P.cs = -1e300;
+    P.r = 0.0;
+  } else {
+    P.cs = (three_d ? va3d(P.r) : va2d(P.r)) + 0.5;
+  }
+  return ok;
+}
+
+// Tiles touched along one axis by the cell range [lo, hi]: at most two runs
+// of tile indices (the second after a periodic wrap).
+struct AxisRuns {
+  int a0, a1, b0, b1;  // runs [a0, a1] and [b0, b1] (b0 > b1 when absent)
+};
+
+__device__ inline AxisRuns axis_runs(int lo, int hi, int L, int T, int periodic) {
+  AxisRuns r;
+  r.b0 = 1;
+  r.b1 = 0;
+  const int nt = (L + T - 1) / T;
+  if (!periodic) {
+    if (lo < 0) lo = 0;
+    if (hi > L - 1) hi = L - 1;
+    if (lo > hi) {
+      r.a0 = 1;
+      r.a1 = 0;
+      return r;
+    }
+    r.a0 = lo / T;
+    r.a1 = hi / T;
+    return r;
+  }
+  if (hi - lo + 1 >= L) {
+    r.a0 = 0;
+    r.a1 = nt - 1;
+    return r;
+  }
+  const int wl = ((lo % L) + L) % L;
+  const int wh = ((hi % L) + L) % L;
+  if (wl <= wh) {
+    r.a0 = wl / T;
+    r.a1 = wh / T;
+  } else {
+    const int t0 = wl / T, t1 = wh / T;
+    if (t1 >= t0) {
+      r.a0 = 0;
+      r.a1 = nt - 1;
+    } else {
+      r.a0 = t0;
+      r.a1 = nt - 1;
+      r.b0 = 0;
+      r.b1 = t1;
+    }
+  }
+  return r;
+}
+
+// Enters particle s (snapshot P) in the list of every tile of its shell box
+// X +- (r + h); the 64 lanes of the calling wave stride over the tiles.
+__device__ inline void bin_tiles(const Geom& g, int three_d, double h, const PSnap& P, int s,
+                                 int lane, int* count, int* tile_list, int cap, unsigned* err) {
+  const double R = P.r + h;
+  const int L[3] = {g.nx, g.ny, g.nz};
+  const int T[3] = {TX, TY, TZ};
+  AxisRuns runs[3];
+  int la[3], lt[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    int lo, hi;
+    if (a == 2 && !three_d) {
+      lo = hi = 0;
+    } else {
+      lo = (int)ceil(P.x[a] - R);
+      hi = (int)floor(P.x[a] + R);
+    }
+    runs[a] = axis_runs(lo, hi, L[a], T[a], g.periodic[a]);
+    la[a] = runs[a].a1 >= runs[a].a0 ? runs[a].a1 - runs[a].a0 + 1 : 0;
+    lt[a] = la[a] + (runs[a].b1 >= runs[a].b0 ? runs[a].b1 - runs[a].b0 + 1 : 0);
+  }
+  const int total = lt[0] * lt[1] * lt[2];
+  for (int k = lane; k < total; k += 64) {
+    const int ix = k % lt[0];
+    const int iy = (k / lt[0]) % lt[1];
+    const int iz = k / (lt[0] * lt[1]);
+    const int tx = ix < la[0] ? runs[0].a0 + ix : runs[0].b0 + (ix - la[0]);
+    const int ty = iy < la[1] ? runs[1].a0 + iy : runs[1].b0 + (iy - la[1]);
+    const int tz = iz < la[2] ? runs[2].a0 + iz : runs[2].b0 + (iz - la[2]);
+    const int t = tx + g.ntx * (ty + g.nty * tz);
+    const int slot = atomicAdd(&count[t], 1);
+    if (slot < cap)
+      tile_list[(size_t)t * cap + slot] = s;
+    else
+      atomicOr(err, ERR_SLOTS);
+  }
+}
+
+// DEM bin of a position along axis a (uniform bins of width bin_size).
+__device__ inline int dem_bin_coord(double x, int L, int periodic, int nbin, double bin_size) {
+  double v = x;
+  if (periodic) {
+    v = fmod(v, (double)L);
+    if (v < 0) v += L;
+  }
+  int b = (int)floor(v / bin_size);
+  if (b < 0) b = 0;
+  if (b >= nbin) b = nbin - 1;
+  return b;
+}
+
+// Enters particle s (position x, velocity u) in its DEM bin of the target
+// set and writes its image; called by one lane per particle.
+__device__ inline void dem_bin_insert(const DemBinOut& b, int three_d, const Geom& g, int s,
+                                      const double* x, const double* u, unsigned* err) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    b.src[6 * s + a] = x[a];
+    b.src[6 * s + 3 + a] = u[a];
+  }
+  const int bx = dem_bin_coord(x[0], g.nx, g.periodic[0], b.nbin[0], b.bin_size[0]);
+  const int by = dem_bin_coord(x[1], g.ny, g.periodic[1], b.nbin[1], b.bin_size[1]);
+  const int bz = three_d ? dem_bin_coord(x[2], g.nz, g.periodic[2], b.nbin[2], b.bin_size[2]) : 0;
+  const int bin = bx + b.nbin[0] * (by + b.nbin[1] * bz);
+  const int k = atomicAdd(&b.count[bin], 1);
+  if (k < b.bin_cap)
+    b.bin_list[(size_t)bin * b.bin_cap + k] = s;
+  else
+    atomicOr(err, ERR_CONTACTS);
+}
+
 }  // namespace psclbm

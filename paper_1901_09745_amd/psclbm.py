@@ -79,6 +79,7 @@ SIGNATURES = {
     "psclbm_strerror": (ctypes.c_char_p, [_I]),
     "lbm_step_count": (ctypes.c_longlong, [_VP]),
     "lbm_step_adjoint": (_I, [_VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP, _VP]),
+    "coupled_step": (_I, [_VP, ctypes.POINTER(DemParams), _VP, _VP, _VP, _VP, _I, _I]),
     "lbm_recompute": (_I, [_VP, _VP, _I, _VP]),
     "psc_rasterize_adjoint": (_I, [_VP, _VP, _I, _VP]),
 }
@@ -187,6 +188,12 @@ def dem_step(ctx: int, prm: DemParams, x: torch.Tensor, u: torch.Tensor, omega: 
              torque: Optional[torch.Tensor]) -> None:
     _check(load().dem_step(ctx, ctypes.byref(prm), _ptr(x), _ptr(u), _ptr(omega), _ptr(radius),
                            radius.numel(), _ptr(force), _ptr(torque)), "dem_step")
+
+
+def coupled_step(ctx: int, prm: DemParams, x: torch.Tensor, u: torch.Tensor, omega: torch.Tensor,
+                 radius: torch.Tensor, nsteps: int = 1) -> None:
+    _check(load().coupled_step(ctx, ctypes.byref(prm), _ptr(x), _ptr(u), _ptr(omega),
+                               _ptr(radius), int(radius.numel()), nsteps), "coupled_step")
 
 
 def dem_reset_contacts(ctx: int) -> None:
@@ -358,6 +365,10 @@ class Lattice:
 
     def dem_step(self, dem_params: DemParams, p: DeviceParticles, F=None, T=None) -> None:
         dem_step(self.ctx, dem_params, p.x, p.u, p.omega, p.r, F, T)
+
+    def coupled_step(self, dem_params: DemParams, p: DeviceParticles, nsteps: int = 1) -> None:
+        coupled_step(self.ctx, dem_params, p.x, p.u, p.omega, p.r, nsteps)
+        self.n_particles = p.n
 
     def mass(self) -> float:
         return lbm_mass(self.ctx)

@@ -109,3 +109,65 @@ def test_kinematic_advection():
     w = W.c3(scale=0.25)
     pr, dp, _ = _dem_only(w.lattice, w.particles, W.DemSpec(kinematic=True, n_sub=3), 20)
     assert np.abs(dp.x.cpu().numpy() - pr.x).max() < 1e-12
+
+
+@pytest.mark.parametrize("case,calls", [("2d_dense", (40,)), ("2d_dense", (1, 13, 26)),
+                                        ("3d_walls", (15,)), ("2d_dense_nsub2", (12,))])
+def test_coupled_step_entry_matches_oracle(case, calls):
+    # coupled_step (rasterize -> step -> DEM with that step's forces, the next
+    # step's rasterisation fused into the DEM wave) against the oracle's
+    # coupled loop, over several calls; afterwards the context holds the last
+    # step's forces and rasterisation
+    import torch
+    import paper_1901_09745_amd.psclbm as P
+    print(f"case: {case} calls {calls}", flush=True)
+    if case.startswith("2d"):
+        lat, p = _dense_2d(seed=23)
+        dem = W.DemSpec(g=(0.0, -1e-5, 0.0), n_sub=2 if case.endswith("nsub2") else 1)
+    else:
+        lat, p = _walled_3d(seed=24)
+        dem = W.DemSpec(g=(-1e-5, 0.0, 0.0))
+    ref = oracle.Lattice(lat)
+    D = oracle.Dem(lat, dem, p.n)
+    pr = p.copy()
+    G = gpu_lattice(lat, p)
+    dp = P.DeviceParticles.from_host(p)
+    prm = P.make_dem_params(dem)
+    x_last = None
+    for k in calls:
+        for _ in range(k):
+            x_last = pr.copy()
+            F_ref, T_ref = ref.step(pr)
+            D.step(pr, F_ref, T_ref)
+        G.coupled_step(prm, dp, k)
+    G.sync()
+    assert relerr(G.get_f().cpu().numpy(), ref.f) < 1e-11
+    assert np.abs(dp.x.cpu().numpy() - pr.x).max() < 1e-9
+    assert np.abs(dp.u.cpu().numpy() - pr.u).max() < 1e-11
+    F, T = G.forces()
+    assert np.abs(F.cpu().numpy() - F_ref).max() < 1e-9 * np.abs(F_ref).max()
+    # the rasterisation is that of the last step's particle state
+    eps, ids, seps = G.solid_fraction()
+    _, _, _, esum = oracle.rasterize(lat, x_last.x, x_last.r)
+    e_ref = np.minimum(esum, 1.0).reshape(lat.shape)
+    assert np.abs(eps.cpu().numpy() - e_ref).max() < 1e-9
+
+
+def test_coupled_step_entry_kinematic():
+    # prescribed motion: the fused step advects and rasterises the next step
+    import paper_1901_09745_amd.psclbm as P
+    w = W.c3(scale=0.25)
+    lat, p = w.lattice, w.particles
+    dem = W.DemSpec(kinematic=True)
+    ref = oracle.Lattice(lat)
+    D = oracle.Dem(lat, dem, p.n)
+    pr = p.copy()
+    for _ in range(6):
+        F_ref, T_ref = ref.step(pr)
+        D.step(pr, F_ref, T_ref)
+    G = gpu_lattice(lat, p)
+    dp = P.DeviceParticles.from_host(p)
+    G.coupled_step(P.make_dem_params(dem), dp, 6)
+    G.sync()
+    assert relerr(G.get_f().cpu().numpy(), ref.f) < 1e-12
+    assert np.abs(dp.x.cpu().numpy() - pr.x).max() < 1e-12
