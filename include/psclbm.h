@@ -72,6 +72,10 @@ extern "C" {
 #define PSCLBM_FP64 0          /* FP64 storage of f, FP64 arithmetic */
 #define PSCLBM_FP32 1          /* FP32 storage of g_i = f_i - w_i rho0, FP32 arithmetic */
 #define PSCLBM_FP32_FP16STORE 2 /* FP16 storage of (f_i - w_i rho0) / w_i, FP32 arithmetic */
+
+/* Solid weighting of the partially saturated cells (Sec. 2.3). */
+#define PSCLBM_WEIGHT_MODIFIED 0
+#define PSCLBM_WEIGHT_ORIGINAL 1
 /* In every form the particle force/torque accumulation, the mass sum and the
  * DEM are FP64. */
 
@@ -89,6 +93,9 @@ typedef struct {
   double max_radius;          /* largest particle radius the DEM bins are sized for */
   int max_tile_particles;     /* capacity of each tile's particle list (e.g. 256) */
   int max_contacts;           /* DEM contact capacity per particle (e.g. 16) */
+  int weighting;              /* PSCLBM_WEIGHT_MODIFIED (Eqs. 12-14, Table 1 Step 5) or
+                                 PSCLBM_WEIGHT_ORIGINAL (Eqs. 7-9, 11: each particle's
+                                 weight from its own fraction, B_n their sum) */
 } psclbm_config;
 
 typedef struct {
@@ -251,7 +258,8 @@ long long lbm_step_count(const psclbm_ctx* ctx);
  *                faces), or NULL.
  * The particles are those of the last psc_rasterize (their state at step t).
  * The derivative of the Table 1 clamps is taken as zero at their kinks.
- * Errors: EINVAL, ESTATE (no rasterisation), EHIP. */
+ * Errors: EINVAL (also for the original weighting, which has no adjoint),
+ * ESTATE (no rasterisation), EHIP. */
 int lbm_step_adjoint(psclbm_ctx* ctx, const double* d_f, const double* d_lambda_in,
                      double* d_lambda_out, const double* d_dJ_dF, const double* d_dJ_dT,
                      double* d_g_x, double* d_g_u, double* d_g_omega,

@@ -34,6 +34,8 @@ int validate(const psclbm_config* c) {
   if (!(c->rho0 > 0.0) || !std::isfinite(c->rho0)) return PSCLBM_EINVAL;
   if (!(c->shell_h >= 0.0) || !std::isfinite(c->shell_h)) return PSCLBM_EINVAL;
   if (c->precision < PSCLBM_FP64 || c->precision > PSCLBM_FP32_FP16STORE) return PSCLBM_EINVAL;
+  if (c->weighting != PSCLBM_WEIGHT_MODIFIED && c->weighting != PSCLBM_WEIGHT_ORIGINAL)
+    return PSCLBM_EINVAL;
   for (int k = 0; k < 3; ++k)
     if (!std::isfinite(c->body_force[k])) return PSCLBM_EINVAL;
   const int L[3] = {c->nx, c->ny, c->nz};
@@ -387,6 +389,7 @@ int lbm_step_adjoint(psclbm_ctx* ctx, const double* d_f, const double* d_lambda_
                      double* d_g_face_velocity) {
   if (!ctx || !d_f || !d_lambda_in || !d_lambda_out) return PSCLBM_EINVAL;
   if (d_lambda_in == d_lambda_out) return PSCLBM_EINVAL;
+  if (ctx->cfg.weighting != PSCLBM_WEIGHT_MODIFIED) return PSCLBM_EINVAL;
   if (!ctx->rasterized) return PSCLBM_ESTATE;
   return launch_adjoint(ctx, d_f, d_lambda_in, d_lambda_out, d_dJ_dF, d_dJ_dT, d_g_x, d_g_u,
                         d_g_omega, d_g_face_velocity);

@@ -136,6 +136,7 @@ struct StepArgs {
   unsigned open_mask;      // inlet | outlet
   unsigned moving_mask;    // faces of kind MOVING_WALL
   unsigned outlet_wave;    // outlet faces served from the neighbour's lane
+  int original;            // original weighting (Eqs. 7-9, 11) instead of Eqs. 12-14
   const void* src;         // ring step: canonical FP64 state read (f is written)
 };
 

@@ -229,6 +229,7 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
 
   C g[Q];
   C rho = (C)1, ux = 0, uy = 0, uz = 0, uu = 0;
+  C Bn_cell = 0;
   const C F0 = (C)a.force[0], F1 = (C)a.force[1], F2 = (C)a.force[2];
   const double tm = a.tau - 0.5;
   double S_ = 0.0, den = 1.0, inv_den = 1.0;
@@ -344,14 +345,24 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
     const C uF = ux * F0 + uy * F1 + uz * F2;
 
     // Weights (Eq. 13 with Table 1 Step 5): B_n from the clamped cell total;
-    // each particle's share B_s is formed in the second pass below.
+    // each particle's share B_s is formed in the second pass below.  The
+    // original weighting (Eq. 9) takes each particle's B_s from its own
+    // fraction and B_n as their sum.
 #pragma unroll
     for (int k = 0; k < KSLOTS; ++k)
       if (k < s.n) S_ += s.eps[k];
     const double en = S_ < 1.0 ? S_ : 1.0;
     den = (1.0 - en) + tm;
     if (s.n > 0) inv_den = 1.0 / den;
-    const C Bn = s.n > 0 ? (C)(en * tm * inv_den) : (C)0;
+    double Bn_d = s.n > 0 ? en * tm * inv_den : 0.0;
+    if (a.original) {
+      Bn_d = 0.0;
+#pragma unroll
+      for (int k = 0; k < KSLOTS; ++k)
+        if (k < s.n) Bn_d += s.eps[k] * tm / ((1.0 - s.eps[k]) + tm);
+    }
+    const C Bn = (C)Bn_d;
+    Bn_cell = Bn;
     const C omB = (C)1 - Bn;
     const C relax = omB * omega;
 
@@ -394,7 +405,10 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
 #pragma unroll
     for (int k = 0; k < KSLOTS; ++k) {
       if (k >= s.n) continue;
-      const C Bs = (C)(s.eps[k] * bscale);
+      const C Bs = a.original ? (C)(s.eps[k] * tm / ((1.0 - s.eps[k]) + tm))
+                              : (C)(s.eps[k] * bscale);
+      // Eq. 14 weighs the momentum exchange by B_s; Eq. 11 by the cell's B_n
+      const C Bm = a.original ? Bn_cell : Bs;
       const LdsEntry& P = lds[s.e[k]];
       const double rx = min_image((double)x - P.x, d.px, d.nx);
       const double ry = min_image((double)y - P.y, d.py, d.ny);
@@ -422,13 +436,13 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
         g[o] += rBw * (ds_s - ds_a);
       }
       if (!a.facc) continue;  // ring step: no force accumulation
-      const double mx = (double)(Bs * (rho * dvx + F0));
-      const double my = (double)(Bs * (rho * dvy + F1));
+      const double mx = (double)(Bm * (rho * dvx + F0));
+      const double my = (double)(Bm * (rho * dvy + F1));
       double* ac = acc + 6 * s.e[k];
       atomicAdd(ac + 0, -mx);
       atomicAdd(ac + 1, -my);
       if constexpr (D == 3) {
-        const double mz = (double)(Bs * (rho * dvz + F2));
+        const double mz = (double)(Bm * (rho * dvz + F2));
         atomicAdd(ac + 2, -mz);
         atomicAdd(ac + 3, -(ry * mz - rz * my));
         atomicAdd(ac + 4, -(rz * mx - rx * mz));
@@ -864,6 +878,7 @@ static StepArgs step_args(psclbm_ctx* c) {
   }
   a.open_mask = a.inlet_mask | a.outlet_mask;
   a.outlet_wave = outlet_wave_mask(c->geom, a.outlet_mask);
+  a.original = c->cfg.weighting == PSCLBM_WEIGHT_ORIGINAL;
   return a;
 }
 

@@ -9,13 +9,14 @@
 
 namespace psclbm {
 
-// Minimum-image separation along one axis.
-__device__ inline double min_image(double d, int periodic, int L) {
-  if (periodic) {
-    if (d > 0.5 * L) d -= L;
-    else if (d < -0.5 * L) d += L;
-  }
-  return d;
+// Minimum-image separation along one axis, as selects (no branch): the
+// same sums d - L or d + L as a branch would take, d + 0 otherwise.
+__device__ __forceinline__ double min_image(double d, int periodic, int L) {
+  const double Ld = (double)L;
+  const double hL = 0.5 * Ld;
+  double t = d > hL ? -Ld : 0.0;
+  t = d < -hL ? Ld : t;
+  return periodic ? d + t : d;
 }
 
 // ---------------------------------------------------------------------------
@@ -60,6 +61,12 @@ __device__ inline void collect_slots(const Geom& g, int x0, int x, int y, int z,
                                      const LdsEntry* lds, int cnt, double h, Slots& s,
                                      unsigned* err) {
   s.n = 0;
+#pragma unroll
+  for (int j = 0; j < KSLOTS; ++j) {
+    s.id[j] = 0;
+    s.e[j] = 0;
+    s.eps[j] = 0.0;
+  }
   const int px = g.periodic[0], py = g.periodic[1], pz = g.periodic[2];
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int lane = (int)(threadIdx.x & 63);
@@ -85,7 +92,6 @@ __device__ inline void collect_slots(const Geom& g, int x0, int x, int y, int z,
     while (mask) {
       const int b = __ffsll(mask) - 1;
       mask &= mask - 1;
-      if (!active) continue;
       const int e = base + b;
       const LdsEntry& P = lds[e];
       const double dx = min_image((double)x - P.x, px, nx);
@@ -96,35 +102,26 @@ __device__ inline void collect_slots(const Geom& g, int x0, int x, int y, int z,
         d2 += dz * dz;
       }
       const double rh = P.r + h;
-      if (!(d2 < rh * rh)) continue;
-      // Table 1 Steps 3-4 on d = sqrt(d2); the root is taken only when the
+      // Table 1 Steps 3-4 on d = sqrt(d2); the root is taken only where the
       // fraction is not already fixed at 0 or 1 by the shell or the clamp
-      double eps;
       const double rl = P.r - h;
       const double c1 = P.cs - 1.0;
-      if (rl >= 0.0 && d2 <= rl * rl) {
-        eps = 1.0;
-      } else if (c1 >= 0.0 && d2 <= c1 * c1) {
-        eps = 1.0;
-      } else if (P.cs <= 0.0 || d2 >= P.cs * P.cs) {
-        eps = 0.0;
-      } else {
-        eps = pair_eps(sqrt(d2), P.r, P.cs, h);
-      }
-      if (!(eps > 0.0)) continue;
-      if (s.n >= KSLOTS) {
-        if (err) atomicOr(err, ERR_SLOTS);
-        continue;
-      }
+      const bool in_shell = active && d2 < rh * rh;
+      const bool inner = (rl >= 0.0 && d2 <= rl * rl) || (c1 >= 0.0 && d2 <= c1 * c1);
+      const bool outer = P.cs <= 0.0 || d2 >= P.cs * P.cs;
+      double eps = inner ? 1.0 : 0.0;
+      if (in_shell && !inner && !outer) eps = pair_eps(sqrt(d2), P.r, P.cs, h);
+      const bool take = in_shell && eps > 0.0;
+      if (take && s.n >= KSLOTS && err) atomicOr(err, ERR_SLOTS);
       // the list is in ascending id, so slots are appended in id order
 #pragma unroll
-      for (int j = 0; j < KSLOTS; ++j)
-        if (j == s.n) {
-          s.id[j] = P.id;
-          s.e[j] = e;
-          s.eps[j] = eps;
-        }
-      s.n += 1;
+      for (int j = 0; j < KSLOTS; ++j) {
+        const bool here = take && j == s.n;
+        s.id[j] = here ? P.id : s.id[j];
+        s.e[j] = here ? e : s.e[j];
+        s.eps[j] = here ? eps : s.eps[j];
+      }
+      s.n += (take && s.n < KSLOTS) ? 1 : 0;
     }
   }
 }

@@ -41,7 +41,8 @@ class Config(ctypes.Structure):
                 ("face_velocity", (ctypes.c_double * 3) * 6), ("rho0", ctypes.c_double),
                 ("shell_h", ctypes.c_double), ("precision", ctypes.c_int),
                 ("max_particles", ctypes.c_int), ("max_radius", ctypes.c_double),
-                ("max_tile_particles", ctypes.c_int), ("max_contacts", ctypes.c_int)]
+                ("max_tile_particles", ctypes.c_int), ("max_contacts", ctypes.c_int),
+                ("weighting", ctypes.c_int)]
 
 
 class ParticlesC(ctypes.Structure):
@@ -238,8 +239,12 @@ def psc_rasterize_adjoint(ctx: int, g_slot_eps: torch.Tensor, kslots: int,
 # Marshalling helpers
 # ---------------------------------------------------------------------------
 
+WEIGHTINGS = {"modified": 0, "original": 1}
+
+
 def make_config(spec, precision: str = "fp64", max_particles: int = 0, max_radius: float = 0.0,
-                max_tile_particles: int = 128, max_contacts: int = 16) -> Config:
+                max_tile_particles: int = 128, max_contacts: int = 16,
+                weighting: str = "modified") -> Config:
     """Config from a ``workloads.LatticeSpec``."""
     c = Config()
     c.lattice, c.nx, c.ny, c.nz = spec.q, spec.nx, spec.ny, spec.nz
@@ -257,6 +262,7 @@ def make_config(spec, precision: str = "fp64", max_particles: int = 0, max_radiu
     c.max_radius = max_radius
     c.max_tile_particles = max_tile_particles
     c.max_contacts = max_contacts
+    c.weighting = WEIGHTINGS[weighting]
     return c
 
 
@@ -297,11 +303,11 @@ class Lattice:
 
     def __init__(self, spec, precision: str = "fp64", max_particles: int = 0,
                  max_radius: float = 0.0, max_tile_particles: int = 128, max_contacts: int = 16,
-                 device: str = "cuda"):
+                 device: str = "cuda", weighting: str = "modified"):
         load()
         self.spec = spec
         self.cfg = make_config(spec, precision, max_particles, max_radius, max_tile_particles,
-                               max_contacts)
+                               max_contacts, weighting)
         nbytes = psclbm_workspace_bytes(self.cfg)
         if nbytes == 0:
             raise PsclbmError(EINVAL, "psclbm_workspace_bytes")

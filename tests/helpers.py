@@ -19,18 +19,18 @@ def oracle_run(lat, f0, p, steps, mode=0):
     return L, F, T
 
 
-def gpu_lattice(lat, p, precision="fp64", cap=64, rmax=None):
+def gpu_lattice(lat, p, precision="fp64", cap=64, rmax=None, weighting="modified"):
     import paper_1901_09745_amd.psclbm as P
     n = 0 if p is None else p.n
     rm = rmax if rmax is not None else (float(p.r.max()) if n else 1.0)
     return P.Lattice(lat, precision, max_particles=max(n, 1), max_radius=rm,
-                     max_tile_particles=cap)
+                     max_tile_particles=cap, weighting=weighting)
 
 
-def gpu_run(lat, f0, p, steps, precision="fp64", cap=64):
+def gpu_run(lat, f0, p, steps, precision="fp64", cap=64, weighting="modified"):
     import torch
     import paper_1901_09745_amd.psclbm as P
-    G = gpu_lattice(lat, p, precision, cap)
+    G = gpu_lattice(lat, p, precision, cap, weighting=weighting)
     if f0 is not None:
         G.set_f(torch.from_numpy(np.ascontiguousarray(f0)).cuda())
     dp = None if p is None or p.n == 0 else P.DeviceParticles.from_host(p)

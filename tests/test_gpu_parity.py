@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 import workloads as W
-from helpers import CASES, _particles, _print_case, force_scale, gpu_lattice, gpu_run, oracle_run, relerr
+from helpers import CASES, _particles, _print_case, case_particles, force_scale, gpu_lattice, gpu_run, oracle_run, relerr
 
 pytestmark = pytest.mark.gpu
 
@@ -42,6 +42,43 @@ def test_psc_steps_parity(name):
         scale = force_scale(lat, prev.f, p)
         assert np.all(np.abs(F - F_ref).max(axis=1) <= 1e-12 * scale + 1e-300)
         assert np.all(np.abs(T - T_ref).max(axis=1) <= 1e-12 * scale * 30 + 1e-300)
+
+
+@pytest.mark.parametrize("name", ["d2q9_periodic", "d2q9_walls", "d3q19_periodic",
+                                  "d3q19_walls"])
+def test_original_weighting_parity(name):
+    # Eqs. 7-9, 11: each particle weighted by its own fraction, B_n their sum
+    # (above one where the shells of the overlapping particles cross), the
+    # force weighted by B_n
+    lat = CASES[name]
+    _print_case(test="original weighting", name=name)
+    p = case_particles(lat)
+    f0 = W.random_state(lat, 12)
+    for steps in (1, 3):
+        ref, F_ref, T_ref = oracle_run(lat, f0, p, steps, mode=1)
+        _, f, F, T = gpu_run(lat, f0, p, steps, weighting="original")
+        assert relerr(f, ref.f) < 1e-12
+        prev, _, _ = oracle_run(lat, f0, p, steps - 1, mode=1)
+        scale = 2 * force_scale(lat, prev.f, p)   # B_n <= 2 with two covering particles
+        assert np.all(np.abs(F - F_ref).max(axis=1) <= 1e-12 * scale + 1e-300)
+        # where cells are shared by two particles the weighting matters
+        if oracle.rasterize(lat, p.x, p.r)[0].max() > 1:
+            ref0, _, _ = oracle_run(lat, f0, p, steps, mode=0)
+            assert relerr(ref0.f, ref.f) > 1e-8
+
+
+def test_original_weighting_has_no_adjoint():
+    import torch
+    import paper_1901_09745_amd.psclbm as P
+    lat = CASES["d2q9_periodic"]
+    p = case_particles(lat)
+    G = gpu_lattice(lat, p, weighting="original")
+    G.rasterize(P.DeviceParticles.from_host(p))
+    q, N = lat.q, lat.ncells
+    f = G.get_f().reshape(q, N)
+    lam = torch.zeros_like(f)
+    with pytest.raises(P.PsclbmError):
+        P.lbm_step_adjoint(G.ctx, f, lam, torch.empty_like(lam))
 
 
 @pytest.mark.parametrize("q", [9, 19])
