@@ -222,10 +222,14 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
   const double rho0 = a.g.rho0;
   double mass_dev = 0.0;
 
-  // ---- solid fractions of the covering particles (Table 1), whole wave ----
+  // ---- solid fractions of the covering particles (Table 1), whole wave; in
+  // 3D after the loads of f are issued, so that their latency overlaps the
+  // slot search (in 2D the registers this holds cost more than it saves) ----
   Slots s;
   s.n = 0;
-  if (cnt > 0) collect_slots<D>(a.g, x0, x, y, z, active, lds, cnt, a.h, s, a.err);
+  if constexpr (Q == 9) {
+    if (cnt > 0) collect_slots<D>(a.g, x0, x, y, z, active, lds, cnt, a.h, s, a.err);
+  }
 
   C g[Q];
   C rho = (C)1, ux = 0, uy = 0, uz = 0, uu = 0;
@@ -249,7 +253,12 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
           g[i] = ST::ld(A + (size_t)i * N, n, i, rho0);
       }
     }
+  }
+  if constexpr (Q == 19) {
+    if (cnt > 0) collect_slots<D>(a.g, x0, x, y, z, active, lds, cnt, a.h, s, a.err);
+  }
 
+  if (active) {
     // ---- inlet / outlet layers: reset to an equilibrium before collision ----
     if (a.open_mask) {
       bool reset = false;
