@@ -22,9 +22,11 @@ The JSON line reports:
                  (forward with checkpoints, backward by ring recompute + the
                  hand-written FP64 adjoint): the time of the backward over
                  that of the forward, on the 2D inlet/outlet channel (D2Q9
-                 tau=0.8 512x256, 64 fixed disks r=8, 400 steps) and on a
-                 20-step window of the 3D packing (D3Q19 384x192x192, 20000
-                 spheres);
+                 tau=0.8 512x256, 64 fixed disks r=8, 4000 steps, checkpoint
+                 every 100, J = drag of disk 0) and on a 500-step window of
+                 the 3D packing (D3Q19 384x192x192, 20000 spheres, checkpoint
+                 every 50, J = drag of the 100 lowest spheres), the latter
+                 with FP64 and with FP16-storage forwards;
   cpu_baseline   the FP64 oracle timed on the host on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-3d]
@@ -53,7 +55,7 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_form(w, form, steps, warmup, coupled=True):
+def run_form(w, form, steps, warmup, coupled=True, observe=False):
     """Time `steps` coupled steps of workload w in precision form `form`
     (coupled_step: rasterize -> fused collide-stream with forces -> DEM, the
     next step's rasterisation fused into the DEM kernel), then the step
@@ -89,6 +91,7 @@ def run_form(w, form, steps, warmup, coupled=True):
         # nsteps coupled steps in one call (rasterize -> step -> DEM each)
         P.coupled_step(ctx, prm, p.x, p.u, p.omega, p.r, nsteps)
 
+    mass0 = G.mass()
     run(warmup)
     torch.cuda.synchronize()
     G.sync()
@@ -115,21 +118,30 @@ def run_form(w, form, steps, warmup, coupled=True):
     mass = G.mass()
     if not np.isfinite(mass):
         raise RuntimeError("non-finite mass")
+    obs = None
+    if observe:
+        Fo = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
+        P.particle_forces(ctx, Fo, None)
+        _, uo = G.macros()
+        obs = {"F": Fo.clone(), "u": uo, "mass0": mass0, "mass1": mass}
     del G
-    return total_ms / steps, kern_ms
+    return total_ms / steps, kern_ms, obs
 
 
-def run_adjoint(w, steps, every, window, label):
-    """Forward and backward wall time of a differentiable FP64 run (the
-    drag summed over the last `window` of `steps` steps)."""
+def run_adjoint(lat, p, steps, every, label, select, precision="fp64", f0=None):
+    """Forward and backward wall time of a differentiable run from state f0
+    (None: rest): J = the x drag (Eq. 14) at the last of `steps` steps summed
+    over the particles `select`, with its gradient w.r.t. all particle
+    positions, velocities, spins and the face velocities (checkpoint every
+    `every` steps).  The run is made twice and the second one is timed."""
     import torch
     from paper_1901_09745_amd.autograd import psc_drag
 
-    lat, p = w.lattice, w.particles
     dev = "cuda"
     r = torch.tensor(p.r, device=dev)
+    sel = torch.as_tensor(select, device=dev)
 
-    def once(nsteps):
+    def once():
         x = torch.tensor(p.x, device=dev, requires_grad=True)
         u = torch.tensor(p.u, device=dev, requires_grad=True)
         om = torch.tensor(p.omega, device=dev, requires_grad=True)
@@ -137,24 +149,48 @@ def run_adjoint(w, steps, every, window, label):
                           requires_grad=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        F, _ = psc_drag(x, u, om, fu, lat, r, nsteps, checkpoint_every=every,
-                        window=min(window, nsteps), precision="fp64")
-        J = F[:, 0].sum()
+        F, _ = psc_drag(x, u, om, fu, lat, r, steps, checkpoint_every=every, window=1,
+                        precision=precision, f0=f0)
+        J = F[sel, 0].sum()
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         J.backward()
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        if not torch.isfinite(fu.grad).all():
+        gx = float(x.grad.abs().max())
+        if not (np.isfinite(gx) and torch.isfinite(fu.grad).all()):
             raise RuntimeError("non-finite adjoint")
-        return (t1 - t0) * 1e3, (t2 - t1) * 1e3
+        return (t1 - t0) * 1e3, (t2 - t1) * 1e3, float(J.detach()), gx
 
-    once(min(steps, every))            # warm-up
-    fwd, bwd = once(steps)
-    return {"workload": label, "cells": w.lattice.ncells, "particles": p.n,
-            "precision": "fp64", "steps": steps, "checkpoint_every": every, "window": window,
-            "forward_ms": fwd, "backward_ms": bwd, "ratio": bwd / fwd,
-            "forward_ms_per_step": fwd / steps, "backward_ms_per_step": bwd / steps}
+    once()                             # warm-up (allocator and code paths)
+    fwd, bwd, J, gx = once()
+    torch.cuda.empty_cache()
+    return {"workload": label, "cells": lat.ncells, "particles": p.n,
+            "forward_precision": precision, "adjoint_precision": "fp64", "steps": steps,
+            "checkpoint_every": every, "J": J, "max_abs_dJ_dX": gx, "forward_ms": fwd,
+            "backward_ms": bwd, "ratio": bwd / fwd, "forward_ms_per_step": fwd / steps,
+            "backward_ms_per_step": bwd / steps}
+
+
+def settle_packing(w, nsteps):
+    """The 3D packing after nsteps coupled steps from rest (FP16 storage, JKR
+    DEM, gravity): its canonical FP64 state and particle state."""
+    import torch
+    import paper_1901_09745_amd.psclbm as P
+    import workloads as W
+
+    p = w.particles
+    G = P.Lattice(w.lattice, "fp16", max_particles=p.n, max_radius=float(p.r.max()),
+                  max_tile_particles=64, max_contacts=16)
+    dp = P.DeviceParticles.from_host(p)
+    G.coupled_step(P.make_dem_params(w.dem), dp, nsteps)
+    f0 = G.get_f()
+    G.sync()
+    ps = W.Particles(dp.x.cpu().numpy(), dp.u.cpu().numpy(), dp.omega.cpu().numpy(),
+                     dp.r.cpu().numpy())
+    del G
+    torch.cuda.empty_cache()
+    return f0, ps
 
 
 def cpu_baseline(w, budget_s=15.0):
@@ -207,10 +243,12 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-3d", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
-    ap.add_argument("--adjoint-steps", type=int, default=400,
+    ap.add_argument("--adjoint-steps", type=int, default=4000,
                     help="steps of the differentiable channel run (0: skip)")
-    ap.add_argument("--adjoint-3d-steps", type=int, default=20,
+    ap.add_argument("--adjoint-3d-steps", type=int, default=500,
                     help="steps of the differentiable 3D packing window (0: skip)")
+    ap.add_argument("--settle-steps", type=int, default=500,
+                    help="coupled steps that settle the 3D packing before its window")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (the reference kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -238,7 +276,7 @@ def main():
     res = {}
     for form in forms:
         _log(f"bench: 2D coupled step, form {form}")
-        ms, kms = run_form(w2, form, args.steps, args.warmup)
+        ms, kms, _ = run_form(w2, form, args.steps, args.warmup)
         N = w2.lattice.ncells
         bytes_launch = 2 * 9 * STORE_BYTES[form] * N
         res[form] = {"mlups": N / (ms * 1e-3) / 1e6, "ms_per_step": ms,
@@ -247,12 +285,15 @@ def main():
     head = "fp32" if "fp32" in res else forms[0]
 
     hbm = {}
+    obs3 = {}
     if not args.no_3d:
         _log("bench: generating the 3D workload")
         w3 = W.c3()
         for form in forms:
             _log(f"bench: 3D step, form {form}")
-            ms, kms = run_form(w3, form, max(20, args.steps // 4), max(5, args.warmup // 4))
+            ms, kms, ob = run_form(w3, form, max(20, args.steps // 4), max(5, args.warmup // 4),
+                                   observe=True)
+            obs3[form] = ob
             N = w3.lattice.ncells
             b = 2 * 19 * STORE_BYTES[form] * N
             hbm[form] = {"mlups": N / (ms * 1e-3) / 1e6, "ms_per_step": ms,
@@ -261,6 +302,20 @@ def main():
                          "frac_of_hbm_peak": b / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
                          "bytes_per_launch": b}
 
+    if "fp64" in obs3:
+        # accuracy of each form against the FP64 form on the same trajectory
+        # (prescribed particle motion, the same step count); FP64 itself
+        # matches the oracle within 1e-12
+        import torch
+        ref = obs3["fp64"]
+        for form, ob in obs3.items():
+            du = float((ob["u"] - ref["u"]).abs().max() / ref["u"].abs().max())
+            dF = float((ob["F"] - ref["F"]).abs().max() / ref["F"].abs().max())
+            hbm[form]["vs_fp64"] = {
+                "velocity_max_rel_err": du, "drag_max_rel_err": dF,
+                "mass_drift_rel": (ob["mass1"] - ob["mass0"]) / ob["mass0"]}
+        obs3.clear()
+        torch.cuda.empty_cache()
     N = w2.lattice.ncells
     ach = res[head]["step_kernel_GBs"]
     roof = {"kernel": f"k_step<9,{head}> (fused PSC collide-stream)", "bound": "hbm",
@@ -294,18 +349,27 @@ def main():
     }
     if args.adjoint_steps > 0:
         _log("bench: adjoint of the 2D channel run")
+        w4 = W.c4()
         adj = {"channel_2d": run_adjoint(
-            W.c4(), args.adjoint_steps, 100, 1,
-            "D2Q9 tau=0.8 512x256 channel, equilibrium inlet u=0.02, outlet rho=1, 64 fixed "
-            "disks r=8; J = drag at the last step")}
+            w4.lattice, w4.particles, args.adjoint_steps, 100,
+            "D2Q9 tau=0.8 512x256 channel from rest, equilibrium inlet u=0.02, outlet rho=1, "
+            "64 fixed disks r=8; J = x drag of disk 0 at the last step", [0])}
         if args.adjoint_3d_steps > 0:
             _log("bench: generating the 3D packing workload")
             w5 = W.c5()
-            _log("bench: adjoint of a 3D packing window")
-            adj["packing_3d"] = run_adjoint(
-                w5, args.adjoint_3d_steps, 10, 1,
-                "D3Q19 tau=0.65 384x192x192, walls on x, 20000 spheres r~U(3,5) held fixed "
-                "over the window; J = drag at the last step")
+            _log(f"bench: settling the 3D packing for {args.settle_steps} coupled steps")
+            f0, p5 = settle_packing(w5, args.settle_steps)
+            lowest = np.argsort(p5.x[:, 0])[:100].tolist()
+            label = (f"D3Q19 tau=0.65 384x192x192, walls on x, 20000 spheres r~U(3,5) after "
+                     f"{args.settle_steps} coupled steps from rest (FP16 storage, JKR DEM, "
+                     "gravity 1e-6 along -x), held fixed over the window; J = x drag (along "
+                     "gravity) of the 100 lowest spheres at the last step")
+            for prec in ("fp64", "fp16"):
+                _log(f"bench: adjoint of a 3D packing window, {prec} forward")
+                adj[f"packing_3d_{prec}"] = run_adjoint(
+                    w5.lattice, p5, args.adjoint_3d_steps, 50, label, lowest, precision=prec,
+                    f0=f0)
+            del f0
         adj["ratio"] = adj["channel_2d"]["ratio"]
         out["adjoint"] = adj
     if not args.no_cpu:
