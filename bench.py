@@ -23,10 +23,11 @@ The JSON line reports:
                  hand-written FP64 adjoint): the time of the backward over
                  that of the forward, on the 2D inlet/outlet channel (D2Q9
                  tau=0.8 512x256, 64 fixed disks r=8, 4000 steps, checkpoint
-                 every 100, J = drag of disk 0) and on a 500-step window of
-                 the 3D packing (D3Q19 384x192x192, 20000 spheres, checkpoint
-                 every 50, J = drag of the 100 lowest spheres), the latter
-                 with FP64 and with FP16-storage forwards;
+                 every 100, J = drag of disk 0) and on the last 500 steps of
+                 a 20000-step settling run of the 3D packing (D3Q19
+                 384x192x192, 20000 spheres, FP16 storage, checkpoint every
+                 50, J = drag of the 100 lowest spheres), the window with FP64
+                 and with FP16-storage forwards;
   cpu_baseline   the FP64 oracle timed on the host on a bounded sample.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-3d]
@@ -183,14 +184,22 @@ def settle_packing(w, nsteps):
     G = P.Lattice(w.lattice, "fp16", max_particles=p.n, max_radius=float(p.r.max()),
                   max_tile_particles=64, max_contacts=16)
     dp = P.DeviceParticles.from_host(p)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
     G.coupled_step(P.make_dem_params(w.dem), dp, nsteps)
+    G.sync()
+    ms = (time.perf_counter() - t0) * 1e3 / nsteps
     f0 = G.get_f()
     G.sync()
     ps = W.Particles(dp.x.cpu().numpy(), dp.u.cpu().numpy(), dp.omega.cpu().numpy(),
                      dp.r.cpu().numpy())
     del G
     torch.cuda.empty_cache()
-    return f0, ps
+    info = {"steps": nsteps, "form": "fp16", "ms_per_step": ms,
+            "mlups": w.lattice.ncells / (ms * 1e-3) / 1e6,
+            "note": "coupled steps (rasterize + PSC collide-stream + JKR DEM) in one call, "
+                    "wall clock"}
+    return f0, ps, info
 
 
 def cpu_baseline(w, budget_s=15.0):
@@ -247,7 +256,7 @@ def main():
                     help="steps of the differentiable channel run (0: skip)")
     ap.add_argument("--adjoint-3d-steps", type=int, default=500,
                     help="steps of the differentiable 3D packing window (0: skip)")
-    ap.add_argument("--settle-steps", type=int, default=500,
+    ap.add_argument("--settle-steps", type=int, default=19500,
                     help="coupled steps that settle the 3D packing before its window")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (the reference kernel that "
@@ -358,7 +367,8 @@ def main():
             _log("bench: generating the 3D packing workload")
             w5 = W.c5()
             _log(f"bench: settling the 3D packing for {args.settle_steps} coupled steps")
-            f0, p5 = settle_packing(w5, args.settle_steps)
+            f0, p5, settle = settle_packing(w5, args.settle_steps)
+            adj["packing_3d_settle"] = settle
             lowest = np.argsort(p5.x[:, 0])[:100].tolist()
             label = (f"D3Q19 tau=0.65 384x192x192, walls on x, 20000 spheres r~U(3,5) after "
                      f"{args.settle_steps} coupled steps from rest (FP16 storage, JKR DEM, "

@@ -554,8 +554,9 @@ __global__ void __launch_bounds__(BLOCK) k_rasterize_adjoint(Geom g, double h, i
   if (cnt > 0) collect_slots<D>(g, x0, x, y, z, active, lds, cnt, h, s, nullptr);
   if (!active) return;
   const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
-  for (int k = 0; k < KSLOTS && k < kout; ++k) {
-    if (k >= s.n) break;
+#pragma unroll
+  for (int k = 0; k < KSLOTS; ++k) {
+    if (k >= kout || k >= s.n) break;
     const double gk = gs[(size_t)n * kout + k];
     if (gk == 0.0) continue;
     const LdsEntry& P = lds[s.e[k]];

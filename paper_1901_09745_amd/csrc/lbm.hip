@@ -721,11 +721,20 @@ __global__ void __launch_bounds__(BLOCK) k_solid_fraction(Geom g, double h, int 
   if (cnt > 0) collect_slots<D>(g, x0, c.x, c.y, c.z, active, lds, cnt, h, s, err);
   if (!active) return;
   double S_ = 0.0;
-  for (int k = 0; k < s.n; ++k) S_ += s.eps[k];
+#pragma unroll
+  for (int k = 0; k < KSLOTS; ++k)
+    if (k < s.n) S_ += s.eps[k];
   if (eps_total) eps_total[c.n] = S_ < 1.0 ? S_ : 1.0;
-  for (int k = 0; k < kout; ++k) {
+  // the recorded slots (static register indices), then padding
+#pragma unroll
+  for (int k = 0; k < KSLOTS; ++k) {
+    if (k >= kout) break;
     if (ids) ids[(size_t)c.n * kout + k] = k < s.n ? s.id[k] : -1;
     if (seps) seps[(size_t)c.n * kout + k] = k < s.n ? s.eps[k] : 0.0;
+  }
+  for (int k = KSLOTS; k < kout; ++k) {
+    if (ids) ids[(size_t)c.n * kout + k] = -1;
+    if (seps) seps[(size_t)c.n * kout + k] = 0.0;
   }
 }
 
