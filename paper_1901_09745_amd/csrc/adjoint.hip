@@ -78,6 +78,7 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
   using L = Lattice<Q>;
   constexpr int D = L::D;
   extern __shared__ double smem_d[];
+  __shared__ SlotLds slot_lds;
   const Geom& G = a.g;
   const int tile = blockIdx.x;
   LdsEntry* lds = reinterpret_cast<LdsEntry*>(smem_d);
@@ -98,7 +99,7 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
   const unsigned n = (unsigned)x + (unsigned)G.nx * ((unsigned)y + (unsigned)G.ny * (unsigned)z);
   Slots s;
   s.n = 0;
-  if (cnt > 0) collect_slots<D>(G, x0, x, y, z, active, lds, cnt, a.h, s, nullptr);
+  if (cnt > 0) collect_slots<D>(G, x0, x, y, z, active, lds, cnt, a.h, s, nullptr, slot_lds);
 
   if (active) {
     Dims d;
@@ -540,6 +541,7 @@ __global__ void __launch_bounds__(BLOCK) k_rasterize_adjoint(Geom g, double h, i
                                                            const PSnap* snap, const double* gs,
                                                            int kout, double* gX) {
   extern __shared__ double smem_d[];
+  __shared__ SlotLds slot_lds;
   LdsEntry* lds = reinterpret_cast<LdsEntry*>(smem_d);
   const int tile = blockIdx.x;
   const int cnt = load_tile_list(tile_count, tile_list, cap, snap, tile, lds, nullptr, np);
@@ -551,7 +553,7 @@ __global__ void __launch_bounds__(BLOCK) k_rasterize_adjoint(Geom g, double h, i
   const bool active = x < g.nx && y < g.ny && z < g.nz;
   Slots s;
   s.n = 0;
-  if (cnt > 0) collect_slots<D>(g, x0, x, y, z, active, lds, cnt, h, s, nullptr);
+  if (cnt > 0) collect_slots<D>(g, x0, x, y, z, active, lds, cnt, h, s, nullptr, slot_lds);
   if (!active) return;
   const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
 #pragma unroll

@@ -200,6 +200,7 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
   using ST = Store<PREC, Q>;
   constexpr int D = L::D;
   extern __shared__ double smem_d[];
+  __shared__ SlotLds slot_lds;
   S* __restrict__ A = static_cast<S*>(a.f);
   const int nb = gridDim.x;
   const int tile = xcd_tile(blockIdx.x, nb);
@@ -228,7 +229,7 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
   Slots s;
   s.n = 0;
   if constexpr (Q == 9) {
-    if (cnt > 0) collect_slots<D>(a.g, x0, x, y, z, active, lds, cnt, a.h, s, a.err);
+    if (cnt > 0) collect_slots<D>(a.g, x0, x, y, z, active, lds, cnt, a.h, s, a.err, slot_lds);
   }
 
   C g[Q];
@@ -255,7 +256,7 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
     }
   }
   if constexpr (Q == 19) {
-    if (cnt > 0) collect_slots<D>(a.g, x0, x, y, z, active, lds, cnt, a.h, s, a.err);
+    if (cnt > 0) collect_slots<D>(a.g, x0, x, y, z, active, lds, cnt, a.h, s, a.err, slot_lds);
   }
 
   if (active) {
@@ -704,6 +705,7 @@ __global__ void __launch_bounds__(BLOCK) k_solid_fraction(Geom g, double h, int 
                                                         int* ids, double* seps, int kout,
                                                         unsigned* err) {
   extern __shared__ double smem_d[];
+  __shared__ SlotLds slot_lds;
   LdsEntry* lds = reinterpret_cast<LdsEntry*>(smem_d);
   const int tile = blockIdx.x;
   const int cnt = load_tile_list(tile_count, tile_list, cap, snap, tile, lds, nullptr, np);
@@ -718,7 +720,7 @@ __global__ void __launch_bounds__(BLOCK) k_solid_fraction(Geom g, double h, int 
   c.n = c.x + (long long)g.nx * (c.y + (long long)g.ny * c.z);
   Slots s;
   s.n = 0;
-  if (cnt > 0) collect_slots<D>(g, x0, c.x, c.y, c.z, active, lds, cnt, h, s, err);
+  if (cnt > 0) collect_slots<D>(g, x0, c.x, c.y, c.z, active, lds, cnt, h, s, err, slot_lds);
   if (!active) return;
   double S_ = 0.0;
 #pragma unroll

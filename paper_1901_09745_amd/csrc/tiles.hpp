@@ -50,79 +50,166 @@ struct Slots {
   double eps[KSLOTS];
 };
 
-// The cells of one wave form one x-row of the tile (TX == 64): the wave
-// first keeps the list entries whose shell r + h reaches the row (a ballot
-// over the list, conservative), then each cell tests only those.  All 64
-// lanes must call this (active == false for cells outside the lattice).
+// Workgroup LDS of the slot search: per cell, the slots found so far.
+struct SlotLds {
+  int n[BLOCK];
+  int e[KSLOTS][BLOCK];
+  double eps[KSLOTS][BLOCK];
+};
+
+// Inclusive prefix sum of an int over the 64 lanes of a wave.
+__device__ __forceinline__ int wave_scan_incl(int v) {
+  const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+// The cells of one wave form one x-row of the tile (TX == 64), so a list
+// entry's y and z separations are the same for the whole wave.  Phase 1: each
+// lane takes one list entry and, when its shell r + h reaches the row, the
+// chord of the row the shell can cover (the lanes whose cell centres lie
+// within sqrt((r + h)^2 - dy^2 - dz^2) of the centre's nearest image, widened
+// by 1e-6; on periodic x narrower than 64 + 2 (r + h) + 2 the whole row).
+// Phase 2: the (entry, cell) pairs of all chords, laid out entry by entry, are
+// taken 64 at a time, one per lane: Table 1 for the pair, and a slot of its
+// cell in LDS when the fraction is positive.  Phase 3: each cell reads its
+// slots and orders them by particle id.  At most KSLOTS slots are kept per
+// cell (more set ERR_SLOTS).  All 64 lanes must call this.
 static_assert(TX == 64, "one wave per tile row");
 
 template <int D>
 __device__ inline void collect_slots(const Geom& g, int x0, int x, int y, int z, bool active,
                                      const LdsEntry* lds, int cnt, double h, Slots& s,
-                                     unsigned* err) {
-  s.n = 0;
-#pragma unroll
-  for (int j = 0; j < KSLOTS; ++j) {
-    s.id[j] = 0;
-    s.e[j] = 0;
-    s.eps[j] = 0.0;
-  }
+                                     unsigned* err, SlotLds& sl) {
   const int px = g.periodic[0], py = g.periodic[1], pz = g.periodic[2];
   const int nx = g.nx, ny = g.ny, nz = g.nz;
-  const int lane = (int)(threadIdx.x & 63);
+  const int tid = (int)threadIdx.x;
+  const int lane = tid & 63;
+  const int wbase = tid - lane;
+  const bool row = y < ny && z < nz;  // uniform over the wave
+  const int xlim = (nx - 1 - x0) < 63 ? (nx - 1 - x0) : 63;
+  const double Lx = (double)nx;
   const double xc = (double)x0 + 31.5;
-  for (int base = 0; base < cnt; base += 64) {
+  sl.n[tid] = 0;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  for (int base = 0; row && base < cnt; base += 64) {
+    // phase 1: chords
     const int ec = base + lane;
-    bool cand = false;
+    int chord = 0, lo = 0, wrap = 0;
+    double dyz2 = 0.0, sh = 0.0;
     if (ec < cnt) {
       const LdsEntry& P = lds[ec];
-      const double rh = P.r + h;
       const double dy = min_image((double)y - P.y, py, ny);
-      double r2 = dy * dy;
+      dyz2 = dy * dy;
       if constexpr (D == 3) {
         const double dz = min_image((double)z - P.z, pz, nz);
-        r2 += dz * dz;
+        dyz2 += dz * dz;
       }
-      if (r2 < rh * rh) {
-        const double half = sqrt(rh * rh - r2);
-        cand = fabs(min_image(xc - P.x, px, nx)) < 31.5 + half + 1e-6;
+      const double rh = P.r + h;
+      if (dyz2 < rh * rh) {
+        const double half = sqrt(rh * rh - dyz2);
+        const double ddx = xc - P.x;
+        double t = ddx > 0.5 * Lx ? -Lx : 0.0;
+        t = ddx < -0.5 * Lx ? Lx : t;
+        sh = px ? t : 0.0;
+        wrap = px && Lx < 66.0 + 2.0 * rh;
+        int hi;
+        if (wrap) {
+          lo = 0;
+          hi = xlim;
+        } else {
+          const double c0 = (P.x - sh) - (double)x0;  // centre's image, in lanes
+          const double l = ceil(c0 - half - 1e-6), u = floor(c0 + half + 1e-6);
+          lo = l < 0.0 ? 0 : (int)l;
+          hi = u > (double)xlim ? xlim : (int)u;
+        }
+        chord = hi >= lo ? hi - lo + 1 : 0;
       }
     }
-    unsigned long long mask = __ballot(cand);
-    while (mask) {
-      const int b = __ffsll(mask) - 1;
-      mask &= mask - 1;
-      const int e = base + b;
-      const LdsEntry& P = lds[e];
-      const double dx = min_image((double)x - P.x, px, nx);
-      const double dy = min_image((double)y - P.y, py, ny);
-      double d2 = dx * dx + dy * dy;
-      if constexpr (D == 3) {
-        const double dz = min_image((double)z - P.z, pz, nz);
-        d2 += dz * dz;
+    const int incl = wave_scan_incl(chord);
+    const int off = incl - chord;
+    const int total = __shfl(incl, 63, 64);
+    const unsigned long long cmask = __ballot(chord > 0);
+    // phase 2: one (entry, cell) pair per lane
+    for (int jb = 0; jb < total; jb += 64) {
+      const int j = jb + lane;
+      int b = 0;
+      for (unsigned long long m = cmask; m; m &= m - 1) {
+        const int c = __ffsll(m) - 1;
+        if (j >= __builtin_amdgcn_readlane(off, c)) b = c;
       }
-      const double rh = P.r + h;
+      const int lob = __shfl(lo, b, 64);
+      const int offb = __shfl(off, b, 64);
+      const int wrapb = __shfl(wrap, b, 64);
+      const double dyz2b = __shfl(dyz2, b, 64);
+      const double shb = __shfl(sh, b, 64);
+      const bool valid = j < total;
+      const int cl = lob + (j - offb);  // cell lane of the pair
+      const int e = base + b;
+      const LdsEntry& P = lds[valid ? e : 0];
+      double dx = (double)(x0 + cl) - P.x;
+      dx = wrapb ? min_image(dx, px, nx) : dx + shb;
+      const double d2 = dx * dx + dyz2b;
       // Table 1 Steps 3-4 on d = sqrt(d2); the root is taken only where the
       // fraction is not already fixed at 0 or 1 by the shell or the clamp
+      const double rh = P.r + h;
       const double rl = P.r - h;
       const double c1 = P.cs - 1.0;
-      const bool in_shell = active && d2 < rh * rh;
+      const bool in_shell = valid && d2 < rh * rh;
       const bool inner = (rl >= 0.0 && d2 <= rl * rl) || (c1 >= 0.0 && d2 <= c1 * c1);
       const bool outer = P.cs <= 0.0 || d2 >= P.cs * P.cs;
       double eps = inner ? 1.0 : 0.0;
       if (in_shell && !inner && !outer) eps = pair_eps(sqrt(d2), P.r, P.cs, h);
-      const bool take = in_shell && eps > 0.0;
-      if (take && s.n >= KSLOTS && err) atomicOr(err, ERR_SLOTS);
-      // the list is in ascending id, so slots are appended in id order
-#pragma unroll
-      for (int j = 0; j < KSLOTS; ++j) {
-        const bool here = take && j == s.n;
-        s.id[j] = here ? P.id : s.id[j];
-        s.e[j] = here ? e : s.e[j];
-        s.eps[j] = here ? eps : s.eps[j];
+      if (in_shell && eps > 0.0) {
+        const int c = wbase + cl;
+        const int k = atomicAdd(&sl.n[c], 1);
+        if (k < KSLOTS) {
+          sl.e[k][c] = e;
+          sl.eps[k][c] = eps;
+        } else if (err) {
+          atomicOr(err, ERR_SLOTS);
+        }
       }
-      s.n += (take && s.n < KSLOTS) ? 1 : 0;
     }
+  }
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  // phase 3: this cell's slots, in ascending particle id
+  int n = sl.n[tid];
+  n = n < KSLOTS ? n : KSLOTS;
+  if (!active) n = 0;
+  s.n = n;
+#pragma unroll
+  for (int k = 0; k < KSLOTS; ++k) {
+    const bool has = k < n;
+    s.e[k] = has ? sl.e[k][tid] : 0;
+    s.eps[k] = has ? sl.eps[k][tid] : 0.0;
+    s.id[k] = has ? lds[s.e[k]].id : 0x7fffffff;
+  }
+  if (__any(n > 1)) {
+    // compare-exchange network on (id, e, eps): (0,1) (2,3) (0,2) (1,3) (1,2)
+    auto cx = [&](int i, int k) {
+      const bool sw = s.id[k] < s.id[i];
+      const int ti = s.id[i], te = s.e[i];
+      const double tp = s.eps[i];
+      s.id[i] = sw ? s.id[k] : ti;
+      s.e[i] = sw ? s.e[k] : te;
+      s.eps[i] = sw ? s.eps[k] : tp;
+      s.id[k] = sw ? ti : s.id[k];
+      s.e[k] = sw ? te : s.e[k];
+      s.eps[k] = sw ? tp : s.eps[k];
+    };
+    static_assert(KSLOTS == 4, "sorting network for four slots");
+    cx(0, 1);
+    cx(2, 3);
+    cx(0, 2);
+    cx(1, 3);
+    cx(1, 2);
   }
 }
 
