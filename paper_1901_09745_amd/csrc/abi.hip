@@ -64,7 +64,7 @@ int validate(const psclbm_config* c) {
 
 struct Layout {
   size_t f, err, scalar, tile_count, tile_list, snap, facc0, facc1, mass_part, outlet_u, outlet_g;
-  size_t bin_count, bin_list, dem_src, cn0, cn1, cid0, cid1, total;
+  size_t bin_count, bin_rec, cn0, cn1, cid0, cid1, total;
   int ntx, nty, ntz, ntiles;
   long long face_stride;
   int nbin[3];
@@ -123,8 +123,7 @@ Layout plan(const psclbm_config* c) {
   l.outlet_g = take(outlet ? sizeof(double) * 3 * 6 * (size_t)fs : 8);
   const int mc = np > 0 ? c->max_contacts : 1;
   l.bin_count = take(sizeof(int) * 3 * nbins);
-  l.bin_list = take(sizeof(int) * nbins * l.bin_cap * (np > 0 ? 1 : 0));
-  l.dem_src = take(sizeof(double) * 12 * (size_t)(np > 0 ? np : 1));
+  l.bin_rec = take(sizeof(double) * 8 * 3 * nbins * l.bin_cap * (np > 0 ? 1 : 0));
   l.cn0 = take(sizeof(int) * (size_t)(np > 0 ? np : 1));
   l.cn1 = take(sizeof(int) * (size_t)(np > 0 ? np : 1));
   l.cid0 = take(sizeof(int) * (size_t)(np > 0 ? np : 1) * mc);
@@ -220,10 +219,11 @@ int lbm_init(const psclbm_config* cfg, void* d_workspace, size_t bytes, void* hi
     c->bin_count_buf[2] = c->bin_count_buf[1] + nbins;
   }
   c->bin_cur = 0;
-  c->bin_list = reinterpret_cast<int*>(base + l.bin_list);
-  c->dem_src[0] = reinterpret_cast<double*>(base + l.dem_src);
-  c->dem_src[1] = c->dem_src[0] + 6 * (size_t)(cfg->max_particles > 0 ? cfg->max_particles : 1);
-  c->src_cur = 0;
+  {
+    const size_t nrec = (size_t)l.nbin[0] * l.nbin[1] * l.nbin[2] * l.bin_cap * 8;
+    for (int k = 0; k < 3; ++k)
+      c->bin_rec[k] = reinterpret_cast<double*>(base + l.bin_rec) + (cfg->max_particles > 0 ? k * nrec : 0);
+  }
   c->contact_n[0] = reinterpret_cast<int*>(base + l.cn0);
   c->contact_n[1] = reinterpret_cast<int*>(base + l.cn1);
   c->contact_id[0] = reinterpret_cast<int*>(base + l.cid0);

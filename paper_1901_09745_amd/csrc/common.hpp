@@ -177,10 +177,8 @@ struct psclbm_ctx {
   double bin_size[3];
   int bin_cap;
   int* bin_count_buf[3];  // each binning fills set cur+1 and clears set cur+2
+  double* bin_rec[3];     // per set: [bin][slot][8] = x, u, r, id of the entry
   int bin_cur;            // the set of the latest binning
-  int* bin_list;
-  double* dem_src[2];     // [n][6] images of x, u at a DEM sub-step's start
-  int src_cur;            // the image of the latest binning
   int* contact_n[2];
   int* contact_id[2];
   int contact_cur;
@@ -195,39 +193,36 @@ struct psclbm_ctx {
 
 namespace psclbm {
 // Target of a DEM binning: the count set to fill (all zero on entry), the set
-// to clear for the binning after next, the bin lists and the image of x, u
-// the contact pass of that binning reads.
+// to clear for the binning after next, and the records of the filled set:
+// each binned particle's position, velocity, radius and id, which the contact
+// pass of that binning reads.
 struct DemBinOut {
   int* count;  // null: no DEM binning
   int* stale;
   long long nbins;
-  int* bin_list;
+  double* rec;
   int bin_cap;
   int nbin[3];
   double bin_size[3];
-  double* src;
 };
 
 inline DemBinOut dem_bin_out(const psclbm_ctx* c, bool on) {
   DemBinOut b;
-  b.count = on ? c->bin_count_buf[(c->bin_cur + 1) % 3] : nullptr;
+  const int fill = (c->bin_cur + 1) % 3;
+  b.count = on ? c->bin_count_buf[fill] : nullptr;
   b.stale = c->bin_count_buf[(c->bin_cur + 2) % 3];
   b.nbins = on ? (long long)c->nbin[0] * c->nbin[1] * c->nbin[2] : 0;
-  b.bin_list = c->bin_list;
+  b.rec = c->bin_rec[fill];
   b.bin_cap = c->bin_cap;
   for (int a = 0; a < 3; ++a) {
     b.nbin[a] = c->nbin[a];
     b.bin_size[a] = c->bin_size[a];
   }
-  b.src = c->dem_src[c->src_cur ^ 1];
   return b;
 }
 
-// After a launch that binned through dem_bin_out: its sets become current.
-inline void dem_bins_advance(psclbm_ctx* c) {
-  c->bin_cur = (c->bin_cur + 1) % 3;
-  c->src_cur ^= 1;
-}
+// After a launch that binned through dem_bin_out: its set becomes current.
+inline void dem_bins_advance(psclbm_ctx* c) { c->bin_cur = (c->bin_cur + 1) % 3; }
 
 // Sum of a double over the 64 lanes of a wave with DPP lane moves (no LDS
 // traffic): pairs and quads by quad permutes, rows of 16 by row shifts, then

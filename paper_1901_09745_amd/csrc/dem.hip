@@ -4,13 +4,13 @@
 // coupling step with the hydrodynamic force and torque held fixed.
 //
 // Per sub-step, two kernels: (1) bin the particles into a uniform grid whose
-// bins are at least 2 r_max + 1 wide, copying each particle's position and
-// velocity into a workspace image; (2) one wave per particle gathers its
-// contacts from the neighbouring bins and the walls (reading the image, so
-// that no particle sees another's update), records the new contact list,
-// sums the forces over the wave and integrates the particle with
-// semi-implicit Euler.  The bin counts are double buffered: each binning
-// fills one set and clears the other.
+// bins are at least 2 r_max + 1 wide, each bin entry a record of the
+// particle's position, velocity, radius and id; (2) one wave per particle
+// gathers its contacts from the records of the neighbouring bins and the
+// walls (so that no particle sees another's update), records the new contact
+// list, sums the forces over the wave and integrates the particle with
+// semi-implicit Euler.  The bin counts and records are triple buffered: each
+// binning fills one set and clears the set the binning after it fills.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -30,8 +30,7 @@ struct DemArgs {
   double bin_size[3];
   int bin_cap;
   const int* bin_count;  // counts of the current binning
-  const int* bin_list;
-  const double* src;     // [n][6] image of x, u at the start of the sub-step
+  const double* bin_rec; // its records: x, u, r, id at the start of the sub-step
   const int* prev_n;
   const int* prev_id;
   int* next_n;
@@ -91,11 +90,11 @@ __device__ inline int bin_coord(double x, int a, const DemArgs& d) {
 // One thread per particle: its bin in the target set and its image; the
 // grid also clears the set the binning after next fills.
 __global__ void k_dem_bin(DemBinOut b, Geom g, int n, int three_d, const double* x,
-                          const double* u, unsigned* err) {
+                          const double* u, const double* r, unsigned* err) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   for (long long k = i; k < b.nbins; k += (long long)gridDim.x * blockDim.x) b.stale[k] = 0;
   if (i >= n) return;
-  dem_bin_insert(b, three_d, g, i, x + 3 * i, u + 3 * i, err);
+  dem_bin_insert(b, three_d, g, i, x + 3 * i, u + 3 * i, r[i], err);
 }
 
 // Distinct neighbour-bin offsets along one axis.
@@ -212,6 +211,12 @@ __global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, IntArgs ia, Nex
   if (i >= d.n) return;  // uniform over the wave
   const int D = d.three_d ? 3 : 2;
   const double ri = r[i];
+  // the particle's previous snapshot: its c_s is reused while r is unchanged
+  double r_prev = -1.0, cs_prev = 0.0;
+  if (nx.build) {
+    r_prev = nx.snap[i].r;
+    cs_prev = nx.snap[i].cs;
+  }
   double xs[3], us[3], ws[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -221,9 +226,8 @@ __global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, IntArgs ia, Nex
   }
   double fsum[3] = {0.0, 0.0, 0.0};
   if (!ia.kinematic) {
-  const double* S = d.src;
-  const double xi0 = S[6 * i], xi1 = S[6 * i + 1], xi2 = d.three_d ? S[6 * i + 2] : 0.0;
-  const double ui0 = S[6 * i + 3], ui1 = S[6 * i + 4], ui2 = d.three_d ? S[6 * i + 5] : 0.0;
+  const double xi0 = xs[0], xi1 = xs[1], xi2 = d.three_d ? xs[2] : 0.0;
+  const double ui0 = us[0], ui1 = us[1], ui2 = d.three_d ? us[2] : 0.0;
   const int pn = d.prev_n[i];
   const int* prev = d.prev_id + (size_t)i * d.max_contacts;
   int* next = d.next_id + (size_t)i * d.max_contacts;
@@ -286,13 +290,14 @@ __global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, IntArgs ia, Nex
     bool have = false;
     int id = 0;
     if (valid) {
-      const int j = d.bin_list[(size_t)b * d.bin_cap + slot];
+      const double* rc = d.bin_rec + ((size_t)b * d.bin_cap + slot) * 8;
+      const int j = (int)rc[7];
       if (j != i) {
-        const double dv0 = min_img(S[6 * j] - xi0, d.periodic[0], d.L[0]);
-        const double dv1 = min_img(S[6 * j + 1] - xi1, d.periodic[1], d.L[1]);
-        const double dv2 = d.three_d ? min_img(S[6 * j + 2] - xi2, d.periodic[2], d.L[2]) : 0.0;
+        const double dv0 = min_img(rc[0] - xi0, d.periodic[0], d.L[0]);
+        const double dv1 = min_img(rc[1] - xi1, d.periodic[1], d.L[1]);
+        const double dv2 = d.three_d ? min_img(rc[2] - xi2, d.periodic[2], d.L[2]) : 0.0;
         const double dist = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
-        const double rj = r[j];
+        const double rj = rc[6];
         const double delta = ri + rj - dist;
         if (delta >= 0.0 || was_in_contact(prev, pn, j)) {
           const double Reff = 1.0 / (1.0 / ri + 1.0 / rj);
@@ -300,8 +305,8 @@ __global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, IntArgs ia, Nex
           const double F = jkr_force(Reff, d.E, d.gamma, delta, &dC);
           if (delta >= 0.0 || delta > -dC) {
             const double n0 = dv0 / dist, n1 = dv1 / dist, n2 = dv2 / dist;
-            double vrn = (S[6 * j + 3] - ui0) * n0 + (S[6 * j + 4] - ui1) * n1;
-            if (d.three_d) vrn += (S[6 * j + 5] - ui2) * n2;
+            double vrn = (rc[3] - ui0) * n0 + (rc[4] - ui1) * n1;
+            if (d.three_d) vrn += (rc[5] - ui2) * n2;
             const double fm = -F + d.eta_n * vrn;
             fs0 += fm * n0;
             fs1 += fm * n1;
@@ -342,11 +347,11 @@ __global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, IntArgs ia, Nex
   }
   if (!nx.build) return;
   PSnap P;
-  const bool ok = make_snap(d.three_d, xs, us, ws, ri, P);
+  const bool ok = make_snap(d.three_d, xs, us, ws, ri, P, r_prev, cs_prev);
   if (lane == 0) {
     nx.snap[i] = P;
     if (!ok) atomicOr(nx.err, ERR_RADIUS);
-    if (nx.db.count) dem_bin_insert(nx.db, d.three_d, nx.g, i, xs, us, nx.err);
+    if (nx.db.count) dem_bin_insert(nx.db, d.three_d, nx.g, i, xs, us, ri, nx.err);
   }
   if (ok) bin_tiles(nx.g, d.three_d, nx.h, P, i, lane, nx.tcount, nx.tile_list, nx.cap, nx.err);
 }
@@ -420,8 +425,7 @@ static DemArgs dem_args(const psclbm_ctx* c, const psclbm_dem_params* prm, int n
   }
   d.bin_cap = c->bin_cap;
   d.bin_count = c->bin_count_buf[c->bin_cur];
-  d.bin_list = c->bin_list;
-  d.src = c->dem_src[c->src_cur];
+  d.bin_rec = c->bin_rec[c->bin_cur];
   d.prev_n = c->contact_n[c->contact_cur];
   d.prev_id = c->contact_id[c->contact_cur];
   d.next_n = c->contact_n[c->contact_cur ^ 1];
@@ -456,7 +460,8 @@ int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doub
     const DemBinOut b = dem_bin_out(c, true);
     const long long bth = b.nbins > n ? b.nbins : n;
     k_dem_bin<<<(unsigned)((bth + 127) / 128), 128, 0, c->stream>>>(b, c->geom, n,
-                                                                   c->geom.q == 19, x, u, c->err);
+                                                                   c->geom.q == 19, x, u, r,
+                                                                   c->err);
     dem_bins_advance(c);
     const DemArgs d = dem_args(c, prm, n, E);
     k_dem_contacts<<<(n + 3) / 4, 256, 0, c->stream>>>(d, ia, nx, x, u, w, r, F, T);

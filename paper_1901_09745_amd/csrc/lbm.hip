@@ -690,7 +690,7 @@ __global__ void __launch_bounds__(256) k_rasterize(Geom g, int n, int three_d, d
   if (lane == 0) {
     snap[s] = P;
     if (!ok) atomicOr(err, ERR_RADIUS);
-    if (db.count) dem_bin_insert(db, three_d, g, s, x + 3 * s, u + 3 * s, err);
+    if (db.count) dem_bin_insert(db, three_d, g, s, x + 3 * s, u + 3 * s, r[s], err);
   }
   if (lane < 6) f0[6 * s + lane] = 0.0;
   else if (lane < 12) f1[6 * s + lane - 6] = 0.0;

@@ -351,9 +351,12 @@ __device__ inline double va3d(double r) {  // Eq. 17 (principal-value arctangent
 }
 
 // Snapshot of a particle; false when the radius is outside the domain of
-// Eq. 17 / 19 (the snapshot then covers no cell).
+// Eq. 17 / 19 (the snapshot then covers no cell).  c_s = V_a(r) + 1/2 is
+// taken from (r_known, cs_known) when r equals r_known (a previous snapshot
+// of the same particle).
 __device__ inline bool make_snap(int three_d, const double* x, const double* u, const double* w,
-                                 double r, PSnap& P) {
+                                 double r, PSnap& P, double r_known = -1.0,
+                                 double cs_known = 0.0) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     P.x[a] = x[a];
@@ -371,6 +374,8 @@ __device__ inline bool make_snap(int three_d, const double* x, const double* u, 
   if (!ok) {
     P.cs = -1e300;
     P.r = 0.0;
+  } else if (r == r_known) {
+    P.cs = cs_known;
   } else {
     P.cs = (three_d ? va3d(P.r) : va2d(P.r)) + 0.5;
   }
@@ -477,24 +482,29 @@ __device__ inline int dem_bin_coord(double x, int L, int periodic, int nbin, dou
   return b;
 }
 
-// Enters particle s (position x, velocity u) in its DEM bin of the target
-// set and writes its image; called by one lane per particle.
+// Enters particle s (position x, velocity u, radius r) in its DEM bin of the
+// target set with its record; called by one lane per particle.
 __device__ inline void dem_bin_insert(const DemBinOut& b, int three_d, const Geom& g, int s,
-                                      const double* x, const double* u, unsigned* err) {
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    b.src[6 * s + a] = x[a];
-    b.src[6 * s + 3 + a] = u[a];
-  }
+                                      const double* x, const double* u, double r,
+                                      unsigned* err) {
   const int bx = dem_bin_coord(x[0], g.nx, g.periodic[0], b.nbin[0], b.bin_size[0]);
   const int by = dem_bin_coord(x[1], g.ny, g.periodic[1], b.nbin[1], b.bin_size[1]);
   const int bz = three_d ? dem_bin_coord(x[2], g.nz, g.periodic[2], b.nbin[2], b.bin_size[2]) : 0;
   const int bin = bx + b.nbin[0] * (by + b.nbin[1] * bz);
   const int k = atomicAdd(&b.count[bin], 1);
-  if (k < b.bin_cap)
-    b.bin_list[(size_t)bin * b.bin_cap + k] = s;
-  else
+  if (k < b.bin_cap) {
+    double* rc = b.rec + ((size_t)bin * b.bin_cap + k) * 8;
+    rc[0] = x[0];
+    rc[1] = x[1];
+    rc[2] = x[2];
+    rc[3] = u[0];
+    rc[4] = u[1];
+    rc[5] = u[2];
+    rc[6] = r;
+    rc[7] = (double)s;
+  } else {
     atomicOr(err, ERR_CONTACTS);
+  }
 }
 
 }  // namespace psclbm

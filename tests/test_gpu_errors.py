@@ -100,3 +100,36 @@ def test_argument_errors():
     with pytest.raises(P.PsclbmError) as e:   # more particles than max_particles
         G.rasterize(P.DeviceParticles.from_host(p))
     assert e.value.code == P.EINVAL
+
+
+def test_coupled_step_argument_errors():
+    P = _P()
+    lat = W.LatticeSpec(q=9, nx=64, ny=32)
+    G = P.Lattice(lat, "fp64", max_particles=2, max_radius=3.0)
+    x = np.array([[20.0, 10.0, 0.0], [40.0, 20.0, 0.0]])
+    p = W.Particles(x, np.zeros((2, 3)), np.zeros((2, 3)), np.array([3.0, 2.5]))
+    dp = P.DeviceParticles.from_host(p)
+    prm = P.make_dem_params(W.DemSpec())
+    for nsteps in (0, -1):
+        with pytest.raises(P.PsclbmError) as e:
+            G.coupled_step(prm, dp, nsteps)
+        assert e.value.code == P.EINVAL
+    bad = P.make_dem_params(W.DemSpec(n_sub=0))
+    with pytest.raises(P.PsclbmError) as e:
+        G.coupled_step(bad, dp, 1)
+    assert e.value.code == P.EINVAL
+    bad = P.make_dem_params(W.DemSpec(poisson=0.5))
+    with pytest.raises(P.PsclbmError) as e:
+        G.coupled_step(bad, dp, 1)
+    assert e.value.code == P.EINVAL
+    three = W.Particles(np.zeros((3, 3)), np.zeros((3, 3)), np.zeros((3, 3)), np.ones(3) * 2)
+    with pytest.raises(P.PsclbmError) as e:   # more particles than max_particles
+        G.coupled_step(prm, P.DeviceParticles.from_host(three), 1)
+    assert e.value.code == P.EINVAL
+    import ctypes
+    rc = P.load().coupled_step(G.ctx, ctypes.byref(prm), None, None, None, None, 2, 1)
+    assert rc == P.EINVAL   # null particle arrays
+    # a valid call still works after the rejected ones, and the state moved
+    G.coupled_step(prm, dp, 3)
+    assert P.lbm_step_count(G.ctx) == 3
+    G.sync()

@@ -57,6 +57,18 @@ def test_2d_workload_full_size():
     _one_step_check(w, G, dp)
 
 
+def test_2d_workload_coupled_entry_full_size():
+    # the benchmarked call: 20 coupled steps in one coupled_step call (the
+    # next rasterisation fused into the DEM kernel), then one step checked
+    # against the oracle from the GPU's state
+    import paper_1901_09745_amd.psclbm as P
+    w = W.c2()
+    print(f"case: {w.description}, coupled_step", flush=True)
+    G, dp = _gpu(w)
+    G.coupled_step(P.make_dem_params(w.dem), dp, 20)
+    _one_step_check(w, G, dp)
+
+
 def test_3d_workload_full_size():
     # D3Q19 tau=0.6 256^3 periodic, 8000 spheres with prescribed velocities
     import paper_1901_09745_amd.psclbm as P
