@@ -92,8 +92,9 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
   int x0, y0, z0;
   tile_origin(G, tile, x0, y0, z0);
   const int x = x0 + (int)(threadIdx.x % TX);
-  const int y = y0 + (int)((threadIdx.x / TX) % TY);
-  const int z = z0 + (int)(threadIdx.x / (TX * TY));
+  // y and z are those of the wave's row: uniform over the wave (scalar)
+  const int y = __builtin_amdgcn_readfirstlane(y0 + (int)((threadIdx.x / TX) % TY));
+  const int z = __builtin_amdgcn_readfirstlane(z0 + (int)(threadIdx.x / (TX * TY)));
   const bool active = x < G.nx && y < G.ny && z < G.nz;
   const unsigned N = (unsigned)G.N;
   const unsigned n = (unsigned)x + (unsigned)G.nx * ((unsigned)y + (unsigned)G.ny * (unsigned)z);
@@ -548,8 +549,9 @@ __global__ void __launch_bounds__(BLOCK) k_rasterize_adjoint(Geom g, double h, i
   int x0, y0, z0;
   tile_origin(g, tile, x0, y0, z0);
   const int x = x0 + (int)(threadIdx.x % TX);
-  const int y = y0 + (int)((threadIdx.x / TX) % TY);
-  const int z = z0 + (int)(threadIdx.x / (TX * TY));
+  // y and z are those of the wave's row: uniform over the wave (scalar)
+  const int y = __builtin_amdgcn_readfirstlane(y0 + (int)((threadIdx.x / TX) % TY));
+  const int z = __builtin_amdgcn_readfirstlane(z0 + (int)(threadIdx.x / (TX * TY)));
   const bool active = x < g.nx && y < g.ny && z < g.nz;
   Slots s;
   s.n = 0;

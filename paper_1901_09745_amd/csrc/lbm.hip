@@ -215,8 +215,9 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
   int x0, y0, z0;
   tile_origin(a.g, tile, x0, y0, z0);
   const int x = x0 + (int)(threadIdx.x % TX);
-  const int y = y0 + (int)((threadIdx.x / TX) % TY);
-  const int z = z0 + (int)(threadIdx.x / (TX * TY));
+  // y and z are those of the wave's row: uniform over the wave (scalar)
+  const int y = __builtin_amdgcn_readfirstlane(y0 + (int)((threadIdx.x / TX) % TY));
+  const int z = __builtin_amdgcn_readfirstlane(z0 + (int)(threadIdx.x / (TX * TY)));
   const bool active = x < d.nx && y < d.ny && z < d.nz;
   const unsigned n = (unsigned)x + d.sy * (unsigned)y + d.sz * (unsigned)z;
   const unsigned N = (unsigned)a.g.N;
