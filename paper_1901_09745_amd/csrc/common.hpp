@@ -192,6 +192,33 @@ struct psclbm_ctx {
 };
 
 namespace psclbm {
+// e . v for a lattice vector e with components in {-1, 0, 1} known at
+// compile time after unrolling: only the nonzero components are summed, as
+// the compiler may not drop 0 * v (IEEE), and +-1 * v is exact.
+template <typename T>
+__device__ __forceinline__ T edot(int ex, int ey, int ez, T a, T b, T c) {
+  if (ex != 0) {
+    T r = ex > 0 ? a : -a;
+    if (ey != 0) r = ey > 0 ? r + b : r - b;
+    if (ez != 0) r = ez > 0 ? r + c : r - c;
+    return r;
+  }
+  if (ey != 0) {
+    T r = ey > 0 ? b : -b;
+    if (ez != 0) r = ez > 0 ? r + c : r - c;
+    return r;
+  }
+  if (ez != 0) return ez > 0 ? c : -c;
+  return T(0);
+}
+
+// acc += e v for a lattice component e in {-1, 0, 1}.
+template <typename T>
+__device__ __forceinline__ void eacc(int e, T& acc, T v) {
+  if (e > 0) acc += v;
+  if (e < 0) acc -= v;
+}
+
 // Target of a DEM binning: the count set to fill (all zero on entry), the set
 // to clear for the binning after next, and the records of the filled set:
 // each binned particle's position, velocity, radius and id, which the contact

@@ -192,8 +192,12 @@ __device__ inline Cell cell_of(const Geom& g, long long n) {
 // ---------------------------------------------------------------------------
 // The fused collide-stream step.
 // ---------------------------------------------------------------------------
+// The 3D FP32 and FP16 forms sit at 96 VGPRs, the last count that fits five
+// waves per SIMD; the hint keeps them there.
 template <int Q, int PREC, int PAR, bool WALLS>
-__global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
+__global__ void __launch_bounds__(BLOCK)
+    __attribute__((amdgpu_waves_per_eu(Q == 19 && PREC != PSCLBM_FP64 ? 5 : 1)))
+    k_step(const StepArgs a) {
   using L = Lattice<Q>;
   using C = typename Form<PREC>::C;
   using S = typename Form<PREC>::S;
@@ -273,9 +277,9 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           r_ += g[i];
-          j0 += (C)L::ex(i) * g[i];
-          j1 += (C)L::ey(i) * g[i];
-          j2 += (C)L::ez(i) * g[i];
+          eacc(L::ex(i), j0, g[i]);
+          eacc(L::ey(i), j1, g[i]);
+          eacc(L::ez(i), j2, g[i]);
         }
         const int lane = (int)(threadIdx.x & 63);
         int src = lane;
@@ -327,7 +331,7 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
         const C uq = u0 * u0 + u1 * u1 + u2 * u2;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          const C eu = (C)L::ex(i) * u0 + (C)L::ey(i) * u1 + (C)L::ez(i) * u2;
+          const C eu = edot(L::ex(i), L::ey(i), L::ez(i), u0, u1, u2);
           g[i] = (C)L::w(i) * (C)rho0 * ((C)3 * eu + (C)4.5 * eu * eu - (C)1.5 * uq);
         }
       }
@@ -390,8 +394,8 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
       const int o = L::opp(i);
       if (o < i) continue;
       const C wi = (C)L::w(i);
-      const C eu = (C)L::ex(i) * ux + (C)L::ey(i) * uy + (C)L::ez(i) * uz;
-      const C eF = (C)L::ex(i) * F0 + (C)L::ey(i) * F1 + (C)L::ez(i) * F2;
+      const C eu = edot(L::ex(i), L::ey(i), L::ez(i), ux, uy, uz);
+      const C eF = edot(L::ex(i), L::ey(i), L::ez(i), F0, F1, F2);
       const C sym = drho + rho * ((C)4.5 * eu * eu - (C)1.5 * uu);
       const C fn_i = g[i] - wi * (sym + rho * (C)3 * eu);
       const C fn_o = g[o] - wi * (sym - rho * (C)3 * eu);
@@ -427,7 +431,7 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
       // rigid-body velocity of particle s at the cell centre
       const C usx = (C)(P.u[0] + P.w[1] * rz - P.w[2] * ry);
       const C usy = (C)(P.u[1] + P.w[2] * rx - P.w[0] * rz);
-      const C usz = (C)(P.u[2] + P.w[0] * ry - P.w[1] * rx);
+      const C usz = D == 3 ? (C)(P.u[2] + P.w[0] * ry - P.w[1] * rx) : (C)0;
       const C dvx = usx - ux, dvy = usy - uy, dvz = usz - uz;
       const C svx = usx + ux, svy = usy + uy, svz = usz + uz;
       const C du2 = dvx * svx + dvy * svy + dvz * svz;  // |u_s|^2 - |u|^2
@@ -438,8 +442,8 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
         const int o = L::opp(i);
         if (o < i) continue;
         const C rBw = rB * (C)L::w(i);
-        const C de = (C)L::ex(i) * dvx + (C)L::ey(i) * dvy + (C)L::ez(i) * dvz;
-        const C se = (C)L::ex(i) * svx + (C)L::ey(i) * svy + (C)L::ez(i) * svz;
+        const C de = edot(L::ex(i), L::ey(i), L::ez(i), dvx, dvy, dvz);
+        const C se = edot(L::ex(i), L::ey(i), L::ez(i), svx, svy, svz);
         // 4.5 [(e.u_s)^2 - (e.u)^2] - 1.5 (|u_s|^2 - |u|^2), and 3 e.(u_s - u)
         const C ds_s = (C)4.5 * de * se - (C)1.5 * du2;
         const C ds_a = (C)3 * de;
@@ -482,7 +486,7 @@ __global__ void __launch_bounds__(BLOCK) k_step(const StepArgs a) {
               uw1 += a.g.face_u[f][1];
               uw2 += a.g.face_u[f][2];
             }
-          const double eu = L::ex(i) * uw0 + L::ey(i) * uw1 + L::ez(i) * uw2;
+          const double eu = edot(L::ex(i), L::ey(i), L::ez(i), uw0, uw1, uw2);
           v -= (C)(6.0 * L::w(i) * eu) * rho;
         }
       }
