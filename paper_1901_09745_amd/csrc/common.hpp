@@ -262,6 +262,55 @@ __device__ __forceinline__ double dpp_move(double v) {
   return __hiloint2double(hi, lo);
 }
 
+template <int CTRL>
+__device__ __forceinline__ float dpp_move(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_move(int v) {
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, true);
+}
+
+// Butterfly over aligned lane blocks of 2, 4 and 8 (DPP quad_perm [1,0,3,2],
+// quad_perm [2,3,0,1], row_half_mirror): a block merges with its partner
+// block when both hold one key (>= 0) throughout.  merge_flags gives the
+// merge decision of each level (bit l of the result) and whether this lane
+// leads its final block; merge_sum then sums a value over the final block.
+// Every lane of the wave must be active.
+__device__ __forceinline__ unsigned merge_flags(int key, int lane, bool& lead) {
+  int uni = key >= 0 ? 1 : 0;
+  unsigned m = 0;
+  lead = key >= 0;
+  {
+    const bool mm = uni && dpp_move<0xB1>(uni) && key == dpp_move<0xB1>(key);
+    m |= mm ? 1u : 0u;
+    if (mm && (lane & 1)) lead = false;
+    uni = mm ? 1 : 0;
+  }
+  {
+    const bool mm = uni && dpp_move<0x4E>(uni) && key == dpp_move<0x4E>(key);
+    m |= mm ? 2u : 0u;
+    if (mm && (lane & 2)) lead = false;
+    uni = mm ? 1 : 0;
+  }
+  {
+    const bool mm = uni && dpp_move<0x141>(uni) && key == dpp_move<0x141>(key);
+    m |= mm ? 4u : 0u;
+    if (mm && (lane & 4)) lead = false;
+  }
+  return m;
+}
+template <typename T>
+__device__ __forceinline__ T merge_sum(T v, unsigned m) {
+  T w = dpp_move<0xB1>(v);
+  if (m & 1u) v += w;
+  w = dpp_move<0x4E>(v);
+  if (m & 2u) v += w;
+  w = dpp_move<0x141>(v);
+  if (m & 4u) v += w;
+  return v;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
   v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
   v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]

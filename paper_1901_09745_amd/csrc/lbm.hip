@@ -409,17 +409,18 @@ __global__ void __launch_bounds__(BLOCK)
   }
 
   // ---- pass 2 (covered cells): sum_s B_s [f^eq_i(rho, u_s) - f^eq_i(rho, u)]
-  // and the momentum exchange of Eq. 14, m_s = B_s [rho (u_s - u) + F],
-  // accumulated per list entry with LDS atomics (the LDS unit serialises
-  // same-entry lanes without costing vector instructions) ----
-  if (s.n > 0) {
+  // and the momentum exchange of Eq. 14, m_s = B_s [rho (u_s - u) + F]
+  // (force, then torque about the particle centre), added to the list
+  // entry's FP64 accumulators in LDS ----
+  {
     // share of each particle: Eq. 13 when the fractions sum to at most one,
     // else eps_{n,s} / sum (the clamped total has B_n = 1)
     double bscale = tm * inv_den;
     if (S_ > 1.0) bscale = 1.0 / S_;
-#pragma unroll
-    for (int k = 0; k < KSLOTS; ++k) {
-      if (k >= s.n) continue;
+    constexpr int NV = D == 3 ? 6 : 3;
+    // slot k of this cell: the equilibrium difference into g and, unless the
+    // step accumulates no force (the ring step), the negated exchange into mv
+    auto slot_update = [&](int k, C (&mv)[NV]) {
       const C Bs = a.original ? (C)(s.eps[k] * tm / ((1.0 - s.eps[k]) + tm))
                               : (C)(s.eps[k] * bscale);
       // Eq. 14 weighs the momentum exchange by B_s; Eq. 11 by the cell's B_n
@@ -450,19 +451,69 @@ __global__ void __launch_bounds__(BLOCK)
         g[i] += rBw * (ds_s + ds_a);
         g[o] += rBw * (ds_s - ds_a);
       }
-      if (!a.facc) continue;  // ring step: no force accumulation
-      const double mx = (double)(Bm * (rho * dvx + F0));
-      const double my = (double)(Bm * (rho * dvy + F1));
-      double* ac = acc + 6 * s.e[k];
-      atomicAdd(ac + 0, -mx);
-      atomicAdd(ac + 1, -my);
+      if (!a.facc) return;
+      const C mx = Bm * (rho * dvx + F0);
+      const C my = Bm * (rho * dvy + F1);
+      const C cx = (C)rx, cy = (C)ry;
+      mv[0] = -mx;
+      mv[1] = -my;
       if constexpr (D == 3) {
-        const double mz = (double)(Bm * (rho * dvz + F2));
-        atomicAdd(ac + 2, -mz);
-        atomicAdd(ac + 3, -(ry * mz - rz * my));
-        atomicAdd(ac + 4, -(rz * mx - rx * mz));
+        const C mz = Bm * (rho * dvz + F2);
+        const C cz = (C)rz;
+        mv[2] = -mz;
+        mv[3] = -(cy * mz - cz * my);
+        mv[4] = -(cz * mx - cx * mz);
+        mv[5] = -(cx * my - cy * mx);
+      } else {
+        mv[2] = -(cx * my - cy * mx);
       }
-      atomicAdd(ac + 5, -(rx * my - ry * mx));
+    };
+    auto accumulate = [&](int e, const C (&mv)[NV]) {
+      double* ac = acc + 6 * e;
+      atomicAdd(ac + 0, (double)mv[0]);
+      atomicAdd(ac + 1, (double)mv[1]);
+      if constexpr (D == 3) {
+        atomicAdd(ac + 2, (double)mv[2]);
+        atomicAdd(ac + 3, (double)mv[3]);
+        atomicAdd(ac + 4, (double)mv[4]);
+        atomicAdd(ac + 5, (double)mv[5]);
+      } else {
+        atomicAdd(ac + 5, (double)mv[2]);
+      }
+    };
+    if constexpr (PREC == PSCLBM_FP64 || D == 3) {
+      // every covered lane adds its own exchange (the LDS unit serialises
+      // lanes of one entry; the block sums below would cost FP64 registers)
+      if (s.n > 0) {
+#pragma unroll
+        for (int k = 0; k < KSLOTS; ++k) {
+          if (k >= s.n) continue;
+          C mv[NV];
+          slot_update(k, mv);
+          if (a.facc) accumulate(s.e[k], mv);
+        }
+      }
+    } else {
+      // slot by slot over the wave: the exchange is first summed over
+      // aligned blocks of up to 8 lanes whose slot holds the same entry, and
+      // only each block's leader adds it to LDS
+      const int lane = (int)(threadIdx.x & 63);
+#pragma unroll
+      for (int k = 0; k < KSLOTS; ++k) {
+        const bool has = k < s.n;
+        if (!__any(has)) break;  // uniform over the wave
+        C mv[NV];
+#pragma unroll
+        for (int j = 0; j < NV; ++j) mv[j] = 0;
+        if (has) slot_update(k, mv);
+        if (a.facc) {
+          bool lead;
+          const unsigned mf = merge_flags(has ? s.e[k] : -1, lane, lead);
+#pragma unroll
+          for (int j = 0; j < NV; ++j) mv[j] = merge_sum(mv[j], mf);
+          if (lead) accumulate(s.e[k], mv);
+        }
+      }
     }
   }
 
