@@ -213,7 +213,6 @@ __global__ void __launch_bounds__(BLOCK)
   LdsEntry* lds = reinterpret_cast<LdsEntry*>(smem_d);
   double* acc = reinterpret_cast<double*>(lds + a.cap);
   const int cnt = load_tile_list(a.tile_count, a.tile_list, a.cap, a.snap, tile, lds, acc, a.np);
-  if (cnt > 0) __syncthreads();
 
   const Dims d = dims_of(a.g);
   int x0, y0, z0;
@@ -765,7 +764,6 @@ __global__ void __launch_bounds__(BLOCK) k_solid_fraction(Geom g, double h, int 
   LdsEntry* lds = reinterpret_cast<LdsEntry*>(smem_d);
   const int tile = blockIdx.x;
   const int cnt = load_tile_list(tile_count, tile_list, cap, snap, tile, lds, nullptr, np);
-  __syncthreads();
   int x0, y0, z0;
   tile_origin(g, tile, x0, y0, z0);
   Cell c;

@@ -57,14 +57,17 @@ struct SlotLds {
   double eps[KSLOTS][BLOCK];
 };
 
-// Inclusive prefix sum of an int over the 64 lanes of a wave.
+// Inclusive prefix sum of an int over the 64 lanes of a wave, in DPP steps:
+// shifts by 1, 2, 4 and 8 within each row of 16 lanes, then the row totals
+// carried up by the row broadcasts of lanes 15 and 31.  Every lane of the
+// wave must be active.
 __device__ __forceinline__ int wave_scan_incl(int v) {
-  const int lane = (int)(threadIdx.x & 63);
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int t = __shfl_up(v, d, 64);
-    if (lane >= d) v += t;
-  }
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xF, 0xF, false);  // row_shr:1
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xF, 0xF, false);  // row_shr:2
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xF, 0xF, false);  // row_shr:4
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xF, 0xF, false);  // row_shr:8
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xA, 0xF, false);  // row_bcast:15 -> rows 1, 3
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xC, 0xF, false);  // row_bcast:31 -> rows 2, 3
   return v;
 }
 
@@ -100,8 +103,8 @@ __device__ inline void collect_slots(const Geom& g, int x0, int x, int y, int z,
   for (int base = 0; row && base < cnt; base += 64) {
     // phase 1: chords
     const int ec = base + lane;
-    int chord = 0, lo = 0, wrap = 0;
-    double dyz2 = 0.0, sh = 0.0;
+    int chord = 0, lo = 0, wrap = 0, shc = 0;
+    double dyz2 = 0.0;
     if (ec < cnt) {
       const LdsEntry& P = lds[ec];
       const double dy = min_image((double)y - P.y, py, ny);
@@ -112,29 +115,33 @@ __device__ inline void collect_slots(const Geom& g, int x0, int x, int y, int z,
       }
       const double rh = P.r + h;
       if (dyz2 < rh * rh) {
-        const double half = sqrt(rh * rh - dyz2);
+        // x-image of the centre nearest the row's middle: shc 1 is -Lx, 2 is +Lx
         const double ddx = xc - P.x;
-        double t = ddx > 0.5 * Lx ? -Lx : 0.0;
-        t = ddx < -0.5 * Lx ? Lx : t;
-        sh = px ? t : 0.0;
+        if (px) shc = ddx > 0.5 * Lx ? 1 : (ddx < -0.5 * Lx ? 2 : 0);
         wrap = px && Lx < 66.0 + 2.0 * rh;
         int hi;
         if (wrap) {
           lo = 0;
           hi = xlim;
         } else {
-          const double c0 = (P.x - sh) - (double)x0;  // centre's image, in lanes
-          const double l = ceil(c0 - half - 1e-6), u = floor(c0 + half + 1e-6);
-          lo = l < 0.0 ? 0 : (int)l;
-          hi = u > (double)xlim ? xlim : (int)u;
+          // the chord only bounds the cells examined (their membership is
+          // decided in phase 2), so FP32 with a margin of 1e-3 lanes will do
+          const double sh = shc == 1 ? -Lx : (shc == 2 ? Lx : 0.0);
+          const float half = sqrtf((float)(rh * rh - dyz2));
+          const float c0 = (float)((P.x - sh) - (double)x0);  // centre's image, in lanes
+          const float l = ceilf(c0 - half - 1e-3f), u = floorf(c0 + half + 1e-3f);
+          lo = l < 0.0f ? 0 : (int)l;
+          hi = u > (float)xlim ? xlim : (int)u;
         }
         chord = hi >= lo ? hi - lo + 1 : 0;
       }
     }
     const int incl = wave_scan_incl(chord);
     const int off = incl - chord;
-    const int total = __shfl(incl, 63, 64);
+    const int total = __builtin_amdgcn_readlane(incl, 63);
     const unsigned long long cmask = __ballot(chord > 0);
+    // lo (6 bits), wrap, shc (2 bits) and off in one word for the broadcast
+    const int pk = lo | (wrap << 6) | (shc << 7) | (off << 9);
     // phase 2: one (entry, cell) pair per lane
     for (int jb = 0; jb < total; jb += 64) {
       const int j = jb + lane;
@@ -143,13 +150,12 @@ __device__ inline void collect_slots(const Geom& g, int x0, int x, int y, int z,
         const int c = __ffsll(m) - 1;
         if (j >= __builtin_amdgcn_readlane(off, c)) b = c;
       }
-      const int lob = __shfl(lo, b, 64);
-      const int offb = __shfl(off, b, 64);
-      const int wrapb = __shfl(wrap, b, 64);
+      const int pkb = __shfl(pk, b, 64);
       const double dyz2b = __shfl(dyz2, b, 64);
-      const double shb = __shfl(sh, b, 64);
-      const bool valid = j < total;
+      const int lob = pkb & 63, wrapb = (pkb >> 6) & 1, offb = pkb >> 9;
+      const double shb = ((pkb >> 7) & 3) == 1 ? -Lx : (((pkb >> 7) & 3) == 2 ? Lx : 0.0);
       const int cl = lob + (j - offb);  // cell lane of the pair
+      const bool valid = j < total && (unsigned)cl < 64u;
       const int e = base + b;
       const LdsEntry& P = lds[valid ? e : 0];
       double dx = (double)(x0 + cl) - P.x;
@@ -214,25 +220,21 @@ __device__ inline void collect_slots(const Geom& g, int x0, int x, int y, int z,
 }
 
 
-// Loads the tile's particle list into LDS in ascending particle id (a rank
-// sort; ids in a list are distinct) and clears its force accumulators.
-// Returns the list length (uniform over the block).  Must be called by the
-// whole block.
+// Loads the tile's particle list into LDS (in list order: the slot search
+// orders each cell's slots by particle id) and clears its force accumulators.
+// Returns the list length (uniform over the block); when it is positive the
+// block has passed a barrier after the fill.  Must be called by the whole
+// block.
 __device__ inline int load_tile_list(const int* tile_count, const int* tile_list, int cap,
                                      const PSnap* snap, int tile, LdsEntry* lds, double* acc,
                                      int np) {
   int cnt = np > 0 ? tile_count[tile] : 0;
   if (cnt > cap) cnt = cap;
   if (cnt == 0) return 0;
-  int* ids = reinterpret_cast<int*>(acc ? acc : reinterpret_cast<double*>(lds + cap));
-  for (int e = threadIdx.x; e < cnt; e += BLOCK) ids[e] = tile_list[(size_t)tile * cap + e];
-  __syncthreads();
   for (int e = threadIdx.x; e < cnt; e += BLOCK) {
-    const int id = ids[e];
-    int rank = 0;
-    for (int j = 0; j < cnt; ++j) rank += ids[j] < id;
+    const int id = tile_list[(size_t)tile * cap + e];
     const PSnap& P = snap[id];
-    LdsEntry& L = lds[rank];
+    LdsEntry& L = lds[e];
     L.x = P.x[0];
     L.y = P.x[1];
     L.z = P.x[2];
@@ -245,9 +247,9 @@ __device__ inline int load_tile_list(const int* tile_count, const int* tile_list
     }
     L.id = id;
   }
-  __syncthreads();
   if (acc)
     for (int k = threadIdx.x; k < 6 * cnt; k += BLOCK) acc[k] = 0.0;
+  __syncthreads();
   return cnt;
 }
 
