@@ -64,7 +64,7 @@ int validate(const psclbm_config* c) {
 
 struct Layout {
   size_t f, err, scalar, tile_count, tile_list, snap, facc0, facc1, mass_part, outlet_u, outlet_g;
-  size_t bin_count, bin_rec, cn0, cn1, cid0, cid1, total;
+  size_t bin_count, bin_rec, cn0, cn1, cid0, cid1, fcont, total;
   int ntx, nty, ntz, ntiles;
   long long face_stride;
   int nbin[3];
@@ -128,6 +128,7 @@ Layout plan(const psclbm_config* c) {
   l.cn1 = take(sizeof(int) * (size_t)(np > 0 ? np : 1));
   l.cid0 = take(sizeof(int) * (size_t)(np > 0 ? np : 1) * mc);
   l.cid1 = take(sizeof(int) * (size_t)(np > 0 ? np : 1) * mc);
+  l.fcont = take(sizeof(double) * 3 * (size_t)(np > 0 ? np : 1));
   l.total = off;
   return l;
 }
@@ -228,6 +229,7 @@ int lbm_init(const psclbm_config* cfg, void* d_workspace, size_t bytes, void* hi
   c->contact_n[1] = reinterpret_cast<int*>(base + l.cn1);
   c->contact_id[0] = reinterpret_cast<int*>(base + l.cid0);
   c->contact_id[1] = reinterpret_cast<int*>(base + l.cid1);
+  c->fcontact = reinterpret_cast<double*>(base + l.fcont);
   // clear everything but the distributions, then set f = f^eq(rho0, 0)
   rc = launch_zero(c, base + l.err, l.total - l.err);
   if (!rc) rc = launch_init_equilibrium(c, nullptr, nullptr);

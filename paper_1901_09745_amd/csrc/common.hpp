@@ -113,6 +113,28 @@ struct Geom {
   double rho0;
 };
 
+// Contact-pass arguments: the binning it reads and the contact lists.
+struct DemArgs {
+  int n;
+  int three_d;
+  int L[3];
+  int periodic[3];
+  int nbin[3];
+  double bin_size[3];
+  int bin_cap;
+  const int* bin_count;  // counts of the current binning
+  const double* bin_rec; // its records: x, u, r, id at the start of the sub-step
+  const int* prev_n;
+  const int* prev_id;
+  int* next_n;
+  int* next_id;
+  int max_contacts;
+  double E;       // effective modulus of two bodies of the material (Eq. 25)
+  double gamma;
+  double eta_n;
+  unsigned* err;
+};
+
 struct StepArgs {
   Geom g;
   void* f;
@@ -138,6 +160,15 @@ struct StepArgs {
   unsigned outlet_wave;    // outlet faces served from the neighbour's lane
   int original;            // original weighting (Eqs. 7-9, 11) instead of Eqs. 12-14
   const void* src;         // ring step: canonical FP64 state read (f is written)
+  // coupled step: the leading dem_blocks workgroups gather the DEM contacts
+  // of four particles each (positions px, velocities pu, radii pr at the
+  // start of the step) into fc [n][3]; the tiles follow
+  int dem_blocks;
+  DemArgs dem;
+  const double* px;
+  const double* pu;
+  const double* pr;
+  double* fc;
 };
 
 // Outlet faces whose cells share a wave with their interior neighbour, so that
@@ -182,6 +213,7 @@ struct psclbm_ctx {
   int* contact_n[2];
   int* contact_id[2];
   int contact_cur;
+  double* fcontact;  // [max_particles][3] contact forces of the coupled step
   double* scalar;  // one FP64 device scalar for reductions
   // host-side state
   long long steps;
@@ -335,6 +367,10 @@ int launch_set_f(psclbm_ctx* c, const double* f);
 int launch_get_f(psclbm_ctx* c, double* f);
 int launch_get_macros(psclbm_ctx* c, double* rho, double* u);
 int launch_rasterize(psclbm_ctx* c, const psclbm_particles* p, bool dem_bins);
+// The step with the contact workgroups of dem (the DEM contact forces of the
+// step's start into fcontact); dem null: the plain step.
+int launch_step_contacts(psclbm_ctx* c, const DemArgs* dem, const double* x, const double* u,
+                         const double* r);
 int launch_coupled(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, double* u, double* w,
                    const double* r, int n, int nsteps);
 int launch_solid_fraction(psclbm_ctx* c, double* eps, int* ids, double* seps, int k);

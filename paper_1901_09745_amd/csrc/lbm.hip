@@ -24,8 +24,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstring>
 
 #include "common.hpp"
+#include "dem.hpp"
 #include "tiles.hpp"
 
 namespace psclbm {
@@ -192,11 +194,17 @@ __device__ inline Cell cell_of(const Geom& g, long long n) {
 // ---------------------------------------------------------------------------
 // The fused collide-stream step.
 // ---------------------------------------------------------------------------
-// The 3D FP32 and FP16 forms sit at 96 VGPRs, the last count that fits five
-// waves per SIMD; the hint keeps them there.
+// Waves per SIMD of each form (2D FP32 / FP16 7, 3D FP32 / FP16 and 2D FP64
+// 5, 3D FP64 4): the register budget of the tiles, which the contact
+// workgroups' code must fit as well.
+template <int Q, int PREC>
+constexpr int step_waves() {
+  return PREC == PSCLBM_FP64 ? (Q == 9 ? 5 : 4) : (Q == 9 ? 7 : 5);
+}
+
 template <int Q, int PREC, int PAR, bool WALLS>
 __global__ void __launch_bounds__(BLOCK)
-    __attribute__((amdgpu_waves_per_eu(Q == 19 && PREC != PSCLBM_FP64 ? 5 : 1)))
+    __attribute__((amdgpu_waves_per_eu(step_waves<Q, PREC>())))
     k_step(const StepArgs a) {
   using L = Lattice<Q>;
   using C = typename Form<PREC>::C;
@@ -205,9 +213,31 @@ __global__ void __launch_bounds__(BLOCK)
   constexpr int D = L::D;
   extern __shared__ double smem_d[];
   __shared__ SlotLds slot_lds;
+  if ((int)blockIdx.x < a.dem_blocks) {
+    // contact workgroup of the coupled step: one wave per particle gathers
+    // its DEM contact force from the binning of the step's start
+    const int i = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (BLOCK / 64) + threadIdx.x / 64));
+    if (i < a.dem.n) {
+      const int lane = (int)(threadIdx.x & 63);
+      double xs[3], us[3], fs[3];
+#pragma unroll
+      for (int k = 0; k < 3; ++k) {
+        xs[k] = a.px[3 * i + k];
+        us[k] = a.pu[3 * i + k];
+      }
+      dem_contact_wave(a.dem, i, lane, xs, us, a.pr[i], fs);
+      if (lane == 0)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) a.fc[3 * i + k] = fs[k];
+    }
+    return;
+  }
   S* __restrict__ A = static_cast<S*>(a.f);
-  const int nb = gridDim.x;
-  const int tile = xcd_tile(blockIdx.x, nb);
+  // the tiles: workgroups dem_blocks.. (a multiple of 8, so that the XCD
+  // round robin of the tile workgroups is that of their own index)
+  const int nb = (int)gridDim.x - a.dem_blocks;
+  const int bid = (int)blockIdx.x - a.dem_blocks;
+  const int tile = xcd_tile(bid, nb);
 
   // particle list of the tile (LDS) and its force accumulators
   LdsEntry* lds = reinterpret_cast<LdsEntry*>(smem_d);
@@ -558,7 +588,7 @@ __global__ void __launch_bounds__(BLOCK)
   if (a.mass_part && threadIdx.x == 0) {
     double t = 0.0;
     for (int k = 0; k < BLOCK / 64; ++k) t += wsum[k];
-    a.mass_part[blockIdx.x] = t;
+    a.mass_part[bid] = t;
   }
 
   // ---- flush the tile's force / torque partials (FP64); the barrier of the
@@ -575,7 +605,7 @@ __global__ void __launch_bounds__(BLOCK)
   // ---- clear the other force buffer for the next step ----
   if (a.np > 0 && a.fzero) {
     const unsigned tot = 6u * (unsigned)a.np;
-    for (unsigned k = blockIdx.x * BLOCK + threadIdx.x; k < tot; k += (unsigned)nb * BLOCK)
+    for (unsigned k = (unsigned)bid * BLOCK + threadIdx.x; k < tot; k += (unsigned)nb * BLOCK)
       a.fzero[k] = 0.0;
   }
 }
@@ -806,7 +836,7 @@ static int grid_for(long long n, int block = 256) {
 
 template <int Q, int PREC>
 static int dispatch_step(psclbm_ctx* c, const StepArgs& a, int par, size_t lds_bytes) {
-  const int nb = c->ntiles;
+  const int nb = c->ntiles + a.dem_blocks;
   const bool walls = !(c->geom.periodic[0] && c->geom.periodic[1] && c->geom.periodic[2]);
   if (par == 2) {  // ring step: canonical FP64 in and out
     if constexpr (PREC == PSCLBM_FP64) {
@@ -953,6 +983,10 @@ static StepArgs step_args(psclbm_ctx* c) {
   a.open_mask = a.inlet_mask | a.outlet_mask;
   a.outlet_wave = outlet_wave_mask(c->geom, a.outlet_mask);
   a.original = c->cfg.weighting == PSCLBM_WEIGHT_ORIGINAL;
+  a.dem_blocks = 0;
+  std::memset(&a.dem, 0, sizeof(a.dem));
+  a.px = a.pu = a.pr = nullptr;
+  a.fc = nullptr;
   return a;
 }
 
@@ -961,9 +995,20 @@ static size_t step_lds(const psclbm_ctx* c) {
                    : 0;
 }
 
-int launch_step(psclbm_ctx* c) {
+int launch_step(psclbm_ctx* c) { return launch_step_contacts(c, nullptr, nullptr, nullptr, nullptr); }
+
+int launch_step_contacts(psclbm_ctx* c, const DemArgs* dem, const double* x, const double* u,
+                         const double* r) {
   const int par = (int)(c->steps & 1);
   StepArgs a = step_args(c);
+  if (dem && dem->n > 0) {
+    a.dem_blocks = ((dem->n + BLOCK / 64 - 1) / (BLOCK / 64) + 7) / 8 * 8;
+    a.dem = *dem;
+    a.px = x;
+    a.pu = u;
+    a.pr = r;
+    a.fc = c->fcontact;
+  }
   // outlets whose neighbour is in another wave: velocities before the step
   const unsigned separate = a.outlet_mask & ~a.outlet_wave;
   if (separate) {
