@@ -58,32 +58,25 @@ __device__ inline int bin_coord(double x, int a, const DemArgs& d) {
   return dem_bin_coord(x, d.L[a], d.periodic[a], d.nbin[a], d.bin_size[a]);
 }
 
-// Distinct neighbour-bin offsets along one axis.
-__device__ inline int axis_offsets(int b, int a, const DemArgs& d, int* out) {
-  const int nb = d.nbin[a];
-  int k = 0;
-  if (d.periodic[a]) {
-    if (nb == 1) {
-      out[k++] = 0;
-    } else if (nb == 2) {
-      out[k++] = b;
-      out[k++] = 1 - b;
-    } else {
-      out[k++] = (b + nb - 1) % nb;
-      out[k++] = b;
-      out[k++] = (b + 1) % nb;
-    }
-  } else {
-    for (int o = -1; o <= 1; ++o)
-      if (b + o >= 0 && b + o < nb) out[k++] = b + o;
-  }
-  return k;
-}
+// Neighbour bins along one axis of bin b: cnt distinct coordinates
+// first, first + 1, .. (modulo nb on a periodic axis).
+struct AxisNb {
+  int first, cnt, nb, periodic;
+  __device__ int at(int k) const { return periodic ? (first + k) % nb : first + k; }
+};
 
-__device__ inline bool was_in_contact(const int* ids, int n, int id) {
-  for (int k = 0; k < n; ++k)
-    if (ids[k] == id) return true;
-  return false;
+__device__ inline AxisNb axis_nb(int b, int a, const DemArgs& d) {
+  AxisNb r;
+  r.nb = d.nbin[a];
+  r.periodic = d.periodic[a];
+  if (r.periodic) {
+    r.cnt = r.nb < 3 ? r.nb : 3;
+    r.first = r.nb < 3 ? b : b - 1 + r.nb;
+  } else {
+    r.first = b > 0 ? b - 1 : 0;
+    r.cnt = (b + 1 < r.nb ? b + 1 : r.nb - 1) - r.first + 1;
+  }
+  return r;
 }
 
 // Contact force on particle i (position xs, velocity us, radius ri at the
@@ -94,13 +87,37 @@ __device__ inline bool was_in_contact(const int* ids, int n, int id) {
 // new contact list (d.next_id / d.next_n) with a ballot, and every lane
 // returns the force summed over the wave in fsum.  Every lane of the wave
 // must be active.
+__device__ __forceinline__ double wave_uniform(double v) {
+  const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
+  const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+
+__device__ inline AxisNb wave_uniform(AxisNb a) {
+  a.first = __builtin_amdgcn_readfirstlane(a.first);
+  a.cnt = __builtin_amdgcn_readfirstlane(a.cnt);
+  a.nb = __builtin_amdgcn_readfirstlane(a.nb);
+  a.periodic = __builtin_amdgcn_readfirstlane(a.periodic);
+  return a;
+}
+
 __device__ inline void dem_contact_wave(const DemArgs& d, int i, int lane, const double* xs,
-                                        const double* us, double ri, double* fsum) {
+                                        const double* us, double r_i, double* fsum) {
   const int D = d.three_d ? 3 : 2;
-  const double xi0 = xs[0], xi1 = xs[1], xi2 = d.three_d ? xs[2] : 0.0;
-  const double ui0 = us[0], ui1 = us[1], ui2 = d.three_d ? us[2] : 0.0;
-  const int pn = d.prev_n[i];
-  const int* prev = d.prev_id + (size_t)i * d.max_contacts;
+  // the particle's own values are the same in every lane (scalar registers)
+  const double ri = wave_uniform(r_i);
+  const double xi0 = wave_uniform(xs[0]), xi1 = wave_uniform(xs[1]);
+  const double xi2 = d.three_d ? wave_uniform(xs[2]) : 0.0;
+  const double ui0 = wave_uniform(us[0]), ui1 = wave_uniform(us[1]);
+  const double ui2 = d.three_d ? wave_uniform(us[2]) : 0.0;
+  // the previous contact list, one entry per lane (max_contacts <= 64)
+  const int pn = __builtin_amdgcn_readfirstlane(d.prev_n[i]);
+  const int pid = lane < d.max_contacts ? d.prev_id[(size_t)i * d.max_contacts + lane] : 0;
+  auto was_in_contact = [&](int id) {
+    bool hit = false;
+    for (int k = 0; k < pn; ++k) hit |= __builtin_amdgcn_readlane(pid, k) == id;
+    return hit;
+  };
   int* next = d.next_id + (size_t)i * d.max_contacts;
   double fs0 = 0.0, fs1 = 0.0, fs2 = 0.0;
   int cnt = 0;  // uniform over the wave
@@ -117,12 +134,13 @@ __device__ inline void dem_contact_wave(const DemArgs& d, int i, int lane, const
         const double dist = (face % 2 == 0) ? xa + 0.5 : (d.L[a] - 0.5) - xa;
         const double delta = ri - dist;
         id = -1 - face;
-        if (delta >= 0.0 || was_in_contact(prev, pn, id)) {
+        if (delta >= 0.0 || was_in_contact(id)) {
+          const double sgn = (face % 2 == 0) ? -1.0 : 1.0;  // normal towards the wall
+          const double damp = d.eta_n * (-ua * sgn);
           double dC;
           const double F = jkr_force(ri, d.E, d.gamma, delta, &dC);
           if (delta >= 0.0 || delta > -dC) {
-            const double sgn = (face % 2 == 0) ? -1.0 : 1.0;  // normal towards the wall
-            const double fm = (-F + d.eta_n * (-ua * sgn)) * sgn;
+            const double fm = (-F + damp) * sgn;
             if (a == 0) fs0 += fm;
             else if (a == 1) fs1 += fm;
             else fs2 += fm;
@@ -139,21 +157,22 @@ __device__ inline void dem_contact_wave(const DemArgs& d, int i, int lane, const
     cnt += __popcll(m);
   }
 
-  // particle pairs from the neighbouring bins
-  int ox[3], oy[3], oz[3];
-  const int bx = bin_coord(xi0, 0, d), by = bin_coord(xi1, 1, d);
-  const int bz = d.three_d ? bin_coord(xi2, 2, d) : 0;
-  const int nxo = axis_offsets(bx, 0, d, ox);
-  const int nyo = axis_offsets(by, 1, d, oy);
-  int nzo = 1;
-  oz[0] = 0;
-  if (d.three_d) nzo = axis_offsets(bz, 2, d, oz);
-  const int nb = nxo * nyo * nzo;
+  // particle pairs from the neighbouring bins: the lanes take the
+  // (neighbour bin, slot) candidates 64 at a time
+  const AxisNb ax = wave_uniform(axis_nb(bin_coord(xi0, 0, d), 0, d));
+  const AxisNb ay = wave_uniform(axis_nb(bin_coord(xi1, 1, d), 1, d));
+  AxisNb az;
+  az.first = 0;
+  az.cnt = 1;
+  az.nb = 1;
+  az.periodic = 0;
+  if (d.three_d) az = wave_uniform(axis_nb(bin_coord(xi2, 2, d), 2, d));
+  const int nb = ax.cnt * ay.cnt * az.cnt;
   for (int base = 0;; base += 64) {
     const int c = base + lane;
     const int k = c % nb, slot = c / nb;
-    const int kx = k % nxo, ky = (k / nxo) % nyo, kz = k / (nxo * nyo);
-    const int b = ox[kx] + d.nbin[0] * (oy[ky] + d.nbin[1] * oz[kz]);
+    const int kx = k % ax.cnt, ky = (k / ax.cnt) % ay.cnt, kz = k / (ax.cnt * ay.cnt);
+    const int b = ax.at(kx) + d.nbin[0] * (ay.at(ky) + d.nbin[1] * az.at(kz));
     int mcount = d.bin_count[b];
     if (mcount > d.bin_cap) mcount = d.bin_cap;
     const bool valid = slot < mcount;
@@ -170,15 +189,19 @@ __device__ inline void dem_contact_wave(const DemArgs& d, int i, int lane, const
         const double dist = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
         const double rj = rc[6];
         const double delta = ri + rj - dist;
-        if (delta >= 0.0 || was_in_contact(prev, pn, j)) {
+        if (delta >= 0.0 || was_in_contact(j)) {
+          // normal and normal relative velocity first: only they (and the
+          // force sums) stay live across the JKR solve
+          const double inv = 1.0 / dist;
+          const double n0 = dv0 * inv, n1 = dv1 * inv, n2 = dv2 * inv;
+          double vrn = (rc[3] - ui0) * n0 + (rc[4] - ui1) * n1;
+          if (d.three_d) vrn += (rc[5] - ui2) * n2;
+          const double damp = d.eta_n * vrn;
           const double Reff = 1.0 / (1.0 / ri + 1.0 / rj);
           double dC;
           const double F = jkr_force(Reff, d.E, d.gamma, delta, &dC);
           if (delta >= 0.0 || delta > -dC) {
-            const double n0 = dv0 / dist, n1 = dv1 / dist, n2 = dv2 / dist;
-            double vrn = (rc[3] - ui0) * n0 + (rc[4] - ui1) * n1;
-            if (d.three_d) vrn += (rc[5] - ui2) * n2;
-            const double fm = -F + d.eta_n * vrn;
+            const double fm = -F + damp;
             fs0 += fm * n0;
             fs1 += fm * n1;
             fs2 += fm * n2;
