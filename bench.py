@@ -228,14 +228,26 @@ def cpu_baseline(w, budget_s=15.0):
                       f"{dt:.1f} s, OpenMP cell loop, brute-force contact search"}
 
 
+# the sources the step kernel is compiled from
+KERNEL_SOURCES = ("lbm.hip", "common.hpp", "tiles.hpp", "dem.hpp")
+
+
+def kernel_digest():
+    """sha256 prefix over the step kernel's sources (the staleness key of the
+    committed counter summary)."""
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1901_09745_amd", "csrc", name), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def _traffic(kernel_key):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it
     was taken on the current kernel source; else None."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    src = os.path.join(ROOT, "paper_1901_09745_amd", "csrc", "lbm.hip")
-    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    digest = kernel_digest()
     data = json.load(open(path))
     ent = data.get(kernel_key)
     if not ent or ent.get("source_sha256_16") != digest:
