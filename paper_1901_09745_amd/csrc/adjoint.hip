@@ -111,23 +111,53 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
     const double rho0 = G.rho0;
     const double F0 = a.force[0], F1 = a.force[1], F2 = a.force[2];
     const int lane = (int)(threadIdx.x & 63);
-    double f[Q];
-#pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = a.f[(size_t)i * N + n];
 
-    // moments of the state as loaded; an x-face outlet whose interior
-    // neighbour is in this wave takes that neighbour's velocity from its lane
-    double rho_in = 0.0, uin0 = 0.0, uin1 = 0.0, uin2 = 0.0;
+    // sensitivity of each post-collision population: where it streams to;
+    // kappa is the moving-wall term -6 w_i rho (e_i . u_w): d/df_j = -6 w_i (e_i . u_w)
+    double ls[Q];
+    double kappa = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      unsigned m = n;
+      const unsigned out = i == 0 ? 0u : link<WALLS>(d, x, y, z, L::ex(i), L::ey(i), L::ez(i), n, m);
+      if (!out) {
+        ls[i] = a.lam_in[(size_t)i * N + m];
+      } else {
+        ls[i] = a.lam_in[(size_t)L::opp(i) * N + n];
+        const unsigned mw = out & a.moving_mask;
+        if (mw) {
+          double uw0 = 0.0, uw1 = 0.0, uw2 = 0.0;
+#pragma unroll
+          for (int fc = 0; fc < 6; ++fc)
+            if ((mw >> fc) & 1u) {
+              uw0 += G.face_u[fc][0];
+              uw1 += G.face_u[fc][1];
+              uw2 += G.face_u[fc][2];
+            }
+          kappa -= 6.0 * L::w(i) * edot(L::ex(i), L::ey(i), L::ez(i), uw0, uw1, uw2) * ls[i];
+        }
+      }
+    }
+
+    // the state entering the step, consumed as it loads: its moments and
+    // the two sums through which it enters the adjoint, Sf = sum_i lam*_i f_i
+    // and So = sum_i lam*_{-i} f_i (= sum_i lam*_i f_{-i}); an x-face outlet
+    // whose interior neighbour is in this wave takes that neighbour's
+    // velocity from its lane
+    double rho_in = 0.0, j0 = 0.0, j1 = 0.0, j2 = 0.0, Sf = 0.0, So = 0.0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double fi = a.f[(size_t)i * N + n];
+      rho_in += fi;
+      eacc(L::ex(i), j0, fi);
+      eacc(L::ey(i), j1, fi);
+      eacc(L::ez(i), j2, fi);
+      Sf += ls[i] * fi;
+      So += ls[L::opp(i)] * fi;
+    }
+    double uin0 = 0.0, uin1 = 0.0, uin2 = 0.0;
     double wu0 = 0.0, wu1 = 0.0, wu2 = 0.0;
     if (a.outlet_wave) {
-      double j0 = 0.0, j1 = 0.0, j2 = 0.0;
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        rho_in += f[i];
-        j0 += L::ex(i) * f[i];
-        j1 += L::ey(i) * f[i];
-        j2 += L::ez(i) * f[i];
-      }
       uin0 = (j0 + 0.5 * F0) / rho_in;
       uin1 = (j1 + 0.5 * F1) / rho_in;
       uin2 = (j2 + 0.5 * F2) / rho_in;
@@ -142,6 +172,7 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
     // inlet / outlet reset (as in the forward: outlets first, an inlet wins)
     int reset = 0, rface = 0;
     double ub0 = 0.0, ub1 = 0.0, ub2 = 0.0;
+    double rho = rho_in, jx = j0, jy = j1, jz = j2;
     if (a.inlet_mask | a.outlet_mask) {
 #pragma unroll
       for (int fc = 0; fc < 6; ++fc) {
@@ -171,55 +202,38 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
           rface = fc;
         }
       }
-      if (reset) {
+      if (reset) {  // the state is f^eq(rho0, u_b)
         const double uq = ub0 * ub0 + ub1 * ub1 + ub2 * ub2;
+        rho = jx = jy = jz = Sf = So = 0.0;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) f[i] = feq_i<Q>(i, rho0, ub0, ub1, ub2, uq);
+        for (int i = 0; i < Q; ++i) {
+          const double fi = feq_i<Q>(i, rho0, ub0, ub1, ub2, uq);
+          rho += fi;
+          eacc(L::ex(i), jx, fi);
+          eacc(L::ey(i), jy, fi);
+          eacc(L::ez(i), jz, fi);
+          Sf += ls[i] * fi;
+          So += ls[L::opp(i)] * fi;
+        }
       }
     }
 
-    // sensitivity of each post-collision population: where it streams to
-    double ls[Q];
-    double rho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
+    // moving walls: d/du_w of -6 w_i rho (e_i . u_w)
+    if (a.gface && a.moving_mask) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      rho += f[i];
-      jx += L::ex(i) * f[i];
-      jy += L::ey(i) * f[i];
-      jz += L::ez(i) * f[i];
-    }
-    double kappa = 0.0;  // moving-wall term -6 w_i rho (e_i . u_w): d/df_j = -6 w_i (e_i . u_w)
+      for (int i = 1; i < Q; ++i) {
+        unsigned m = n;
+        const unsigned mw =
+            link<WALLS>(d, x, y, z, L::ex(i), L::ey(i), L::ez(i), n, m) & a.moving_mask;
+        if (!mw) continue;
+        const double cw = -6.0 * L::w(i) * rho * ls[i];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      unsigned m = n;
-      const unsigned out = i == 0 ? 0u : link<WALLS>(d, x, y, z, L::ex(i), L::ey(i), L::ez(i), n, m);
-      if (!out) {
-        ls[i] = a.lam_in[(size_t)i * N + m];
-      } else {
-        ls[i] = a.lam_in[(size_t)L::opp(i) * N + n];
-        const unsigned mw = out & a.moving_mask;
-        if (mw) {
-          double uw0 = 0.0, uw1 = 0.0, uw2 = 0.0;
-#pragma unroll
-          for (int fc = 0; fc < 6; ++fc)
-            if ((mw >> fc) & 1u) {
-              uw0 += G.face_u[fc][0];
-              uw1 += G.face_u[fc][1];
-              uw2 += G.face_u[fc][2];
-            }
-          kappa -= 6.0 * L::w(i) * (L::ex(i) * uw0 + L::ey(i) * uw1 + L::ez(i) * uw2) * ls[i];
-          // wall velocity: d/du_w of -6 w_i rho (e_i . u_w)
-          if (a.gface) {
-            const double cw = -6.0 * L::w(i) * rho * ls[i];
-#pragma unroll
-            for (int fc = 0; fc < 6; ++fc)
-              if ((mw >> fc) & 1u) {
-                if (L::ex(i)) atomicAdd(a.gface + 3 * fc, cw * L::ex(i));
-                if (L::ey(i)) atomicAdd(a.gface + 3 * fc + 1, cw * L::ey(i));
-                if (L::ez(i)) atomicAdd(a.gface + 3 * fc + 2, cw * L::ez(i));
-              }
+        for (int fc = 0; fc < 6; ++fc)
+          if ((mw >> fc) & 1u) {
+            if (L::ex(i)) atomicAdd(a.gface + 3 * fc, cw * L::ex(i));
+            if (L::ey(i)) atomicAdd(a.gface + 3 * fc + 1, cw * L::ey(i));
+            if (L::ez(i)) atomicAdd(a.gface + 3 * fc + 2, cw * L::ez(i));
           }
-        }
       }
     }
 
@@ -241,10 +255,12 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
     const double cp = S <= 1.0 ? tm / (den * den) : -1.0 / (S * S);
     const double Bnp = S < 1.0 ? tm * (1.0 + tm) / (den * den) : 0.0;
 
-    // base adjoint terms; L0 = sum_i lam*_i (f_{-i} - f^eq_{-i} - f_i), the part
-    // of lam* . Omega^s common to every particle; and the moments of w_i lam*_i
-    // (orders 0, 1, 2 in e_i), through which the particle terms close
-    double ar = 0.0, aux = 0.0, auy = 0.0, auz = 0.0, LP = 0.0, L0 = 0.0;
+    // base adjoint terms; LP = sum_i lam*_i (w (f_i - f^eq_i) - F_i) and
+    // L0 = sum_i lam*_i (f_{-i} - f^eq_{-i} - f_i), the part of lam* . Omega^s
+    // common to every particle, start from the state sums Sf, So; and the
+    // moments of w_i lam*_i (orders 0, 1, 2 in e_i), through which the
+    // particle terms close
+    double ar = 0.0, aux = 0.0, auy = 0.0, auz = 0.0, LP = w * Sf, L0 = So - Sf;
     double m0 = 0.0, m1x = 0.0, m1y = 0.0, m1z = 0.0;
     double mxx = 0.0, myy = 0.0, mzz = 0.0, mxy = 0.0, mxz = 0.0, myz = 0.0;
 #pragma unroll
@@ -258,8 +274,8 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
       const double fe_o = rw * (sq - 3.0 * eu);
       const double eF = ex * F0 + ey * F1 + ez * F2;
       const double Fi = kg * L::w(i) * (3.0 * (eF - (ux * F0 + uy * F1 + uz * F2)) + 9.0 * eu * eF);
-      LP += ls[i] * (w * (f[i] - fe) - Fi);
-      L0 += ls[i] * (f[o] - fe_o - f[i]);
+      LP -= ls[i] * (w * fe + Fi);
+      L0 -= ls[i] * fe_o;
       // coefficient of f^eq_i: (1-B_n) w lam*_i - B_n lam*_{-i}
       const double cf = (1.0 - Bn) * w * ls[i] - Bn * ls[o];
       ar += cf * fe / rho;
