@@ -260,46 +260,56 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
     // common to every particle, start from the state sums Sf, So; and the
     // moments of w_i lam*_i (orders 0, 1, 2 in e_i), through which the
     // particle terms close
-    double ar = 0.0, aux = 0.0, auy = 0.0, auz = 0.0, LP = w * Sf, L0 = So - Sf;
+    // The velocity gradient sums
+    //   sum_i cf_i df^eq_i/du = sum_i cf_i rho w_i (3 e_i + 9 (e_i.u) e_i - 3 u) and
+    //   sum_i cF_i dF_i/du / (k w_i) = sum_i cF_i (9 (e_i.F) e_i - 3 F)
+    // are collected as sum_i t_i e_i (only the nonzero components of e_i are
+    // added) minus 3 u sum_i cf_i rho w_i and 3 F sum_i cF_i.
+    double ar = 0.0, LP = w * Sf, L0 = So - Sf;
+    double vx = 0.0, vy = 0.0, vz = 0.0, scw = 0.0, scF = 0.0;
     double m0 = 0.0, m1x = 0.0, m1y = 0.0, m1z = 0.0;
     double mxx = 0.0, myy = 0.0, mzz = 0.0, mxy = 0.0, mxz = 0.0, myz = 0.0;
+    const double irho = 1.0 / rho;
+    const double uF = ux * F0 + uy * F1 + uz * F2;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int o = L::opp(i);
-      const double ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
-      const double eu = ex * ux + ey * uy + ez * uz;
+      const int ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
+      const double eu = edot(ex, ey, ez, ux, uy, uz);
       const double rw = rho * L::w(i);
       const double sq = 1.0 + 4.5 * eu * eu - 1.5 * uu;
       const double fe = rw * (sq + 3.0 * eu);
       const double fe_o = rw * (sq - 3.0 * eu);
-      const double eF = ex * F0 + ey * F1 + ez * F2;
-      const double Fi = kg * L::w(i) * (3.0 * (eF - (ux * F0 + uy * F1 + uz * F2)) + 9.0 * eu * eF);
+      const double eF = edot(ex, ey, ez, F0, F1, F2);
+      const double Fi = kg * L::w(i) * (3.0 * (eF - uF) + 9.0 * eu * eF);
       LP -= ls[i] * (w * fe + Fi);
       L0 -= ls[i] * fe_o;
       // coefficient of f^eq_i: (1-B_n) w lam*_i - B_n lam*_{-i}
       const double cf = (1.0 - Bn) * w * ls[i] - Bn * ls[o];
-      ar += cf * fe / rho;
-      // df^eq_i/du = rho w_i (3 e + 9 (e.u) e - 3 u)
-      aux += cf * rw * (3.0 * ex + 9.0 * eu * ex - 3.0 * ux);
-      auy += cf * rw * (3.0 * ey + 9.0 * eu * ey - 3.0 * uy);
-      auz += cf * rw * (3.0 * ez + 9.0 * eu * ez - 3.0 * uz);
-      // dF_i/du = k w_i (-3 F + 9 (e.F) e)
+      ar += cf * fe * irho;
+      const double crw = cf * rw;
       const double cF = (1.0 - Bn) * ls[i] * kg * L::w(i);
-      aux += cF * (-3.0 * F0 + 9.0 * eF * ex);
-      auy += cF * (-3.0 * F1 + 9.0 * eF * ey);
-      auz += cF * (-3.0 * F2 + 9.0 * eF * ez);
+      scw += crw;
+      scF += cF;
+      const double t = crw * (3.0 + 9.0 * eu) + 9.0 * cF * eF;
+      eacc(ex, vx, t);
+      eacc(ey, vy, t);
+      eacc(ez, vz, t);
       const double wl = L::w(i) * ls[i];
       m0 += wl;
-      m1x += ex * wl;
-      m1y += ey * wl;
-      m1z += ez * wl;
-      mxx += ex * ex * wl;
-      myy += ey * ey * wl;
-      mzz += ez * ez * wl;
-      mxy += ex * ey * wl;
-      mxz += ex * ez * wl;
-      myz += ey * ez * wl;
+      eacc(ex, m1x, wl);
+      eacc(ey, m1y, wl);
+      eacc(ez, m1z, wl);
+      if (ex != 0) mxx += wl;
+      if (ey != 0) myy += wl;
+      if (ez != 0) mzz += wl;
+      eacc(ex * ey, mxy, wl);
+      eacc(ex * ez, mxz, wl);
+      eacc(ey * ez, myz, wl);
     }
+    double aux = vx - 3.0 * (ux * scw + F0 * scF);
+    double auy = vy - 3.0 * (uy * scw + F1 * scF);
+    double auz = vz - 3.0 * (uz * scw + F2 * scF);
 
     // covering particles, first pass: G_s = lam* . Omega^s + q_s . M_s with
     //   lam* . f^eq(rho, u_s) = rho [m0 (1 - 1.5 u_s^2) + 3 u_s . m1 + 4.5 u_s.M2.u_s]
@@ -406,7 +416,6 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
     //   dJ/du_b = sum_j lam_j rho0 w_j (3 e_j + 9 (e_j.u_b) e_j - 3 u_b)
     // and keeps none of its own
     const double alpha = 1.0 - (1.0 - Bn) * w - Bn;
-    const double irho = 1.0 / rho;
     double g0 = 0.0, g1 = 0.0, g2 = 0.0;
     if (reset) {
 #pragma unroll
@@ -457,13 +466,17 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
       }
     }
     const double sb = -(s0 * uin0 + s1 * uin1 + s2 * uin2);
+    // lam_j = alpha lam*_j + B_n lam*_{-j} + kappa + ar + au.(e_j - u)/rho:
+    // the part common to every j, and au/rho dotted with e_j's nonzero
+    // components
+    const double qx = aux * irho, qy = auy * irho, qz = auz * irho;
+    const double base = kappa + ar - (qx * ux + qy * uy + qz * uz);
 #pragma unroll
     for (int j = 0; j < Q; ++j) {
-      const double ex = L::ex(j), ey = L::ey(j), ez = L::ez(j);
-      double lj = alpha * ls[j] + Bn * ls[L::opp(j)] + kappa + ar +
-                  (aux * (ex - ux) + auy * (ey - uy) + auz * (ez - uz)) * irho;
+      const int ex = L::ex(j), ey = L::ey(j), ez = L::ez(j);
+      double lj = alpha * ls[j] + Bn * ls[L::opp(j)] + base + edot(ex, ey, ez, qx, qy, qz);
       if (reset) lj = 0.0;
-      lj += s0 * ex + s1 * ey + s2 * ez + sb;
+      lj += edot(ex, ey, ez, s0, s1, s2) + sb;
       a.lam_out[(size_t)j * N + n] = lj;
     }
   }
