@@ -25,6 +25,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <type_traits>
 
 #include "common.hpp"
 #include "dem.hpp"
@@ -194,12 +195,14 @@ __device__ inline Cell cell_of(const Geom& g, long long n) {
 // ---------------------------------------------------------------------------
 // The fused collide-stream step.
 // ---------------------------------------------------------------------------
-// Waves per SIMD of each form (2D FP32 / FP16 7, 3D FP32 / FP16 and 2D FP64
+// Waves per SIMD of each form (2D FP32 / FP16 8, 3D FP32 / FP16 and 2D FP64
 // 5, 3D FP64 4): the register budget of the tiles, which the contact
-// workgroups' code must fit as well.
+// workgroups' code must fit as well.  At 8 waves the 2D FP32 / FP16 forms
+// spill a few registers and hold their slot fractions in FP32 (the LDS of
+// eight workgroups per CU); measured faster than 7 waves without spills.
 template <int Q, int PREC>
 constexpr int step_waves() {
-  return PREC == PSCLBM_FP64 ? (Q == 9 ? 5 : 4) : (Q == 9 ? 7 : 5);
+  return PREC == PSCLBM_FP64 ? (Q == 9 ? 5 : 4) : (Q == 9 ? 8 : 5);
 }
 
 template <int Q, int PREC, int PAR, bool WALLS>
@@ -211,8 +214,10 @@ __global__ void __launch_bounds__(BLOCK)
   using S = typename Form<PREC>::S;
   using ST = Store<PREC, Q>;
   constexpr int D = L::D;
+  // slot fractions held in FP32 by the FP32 arithmetic forms
+  using E = typename std::conditional<PREC == PSCLBM_FP64, double, float>::type;
   extern __shared__ double smem_d[];
-  __shared__ SlotLds slot_lds;
+  __shared__ SlotLdsT<E> slot_lds;
   if ((int)blockIdx.x < a.dem_blocks) {
     // contact workgroup of the coupled step: one wave per particle gathers
     // its DEM contact force from the binning of the step's start
@@ -260,7 +265,7 @@ __global__ void __launch_bounds__(BLOCK)
   // ---- solid fractions of the covering particles (Table 1), whole wave; in
   // 3D after the loads of f are issued, so that their latency overlaps the
   // slot search (in 2D the registers this holds cost more than it saves) ----
-  Slots s;
+  SlotsT<E> s;
   s.n = 0;
   if constexpr (Q == 9) {
     if (cnt > 0) collect_slots<D>(a.g, x0, x, y, z, active, lds, cnt, a.h, s, a.err, slot_lds);

@@ -42,20 +42,26 @@ struct LdsEntry {
   int pad;
 };
 
-// Slots of one cell: up to KSLOTS particles with eps > 0, ascending id.
-struct Slots {
+// Slots of one cell: up to KSLOTS particles with eps > 0, ascending id.  The
+// fractions are evaluated in FP64 and held as E (FP64, or FP32 for the FP32
+// arithmetic forms, whose weights are formed in FP32 anyway).
+template <typename E>
+struct SlotsT {
   int n;
   int id[KSLOTS];
   int e[KSLOTS];  // index in the tile list
-  double eps[KSLOTS];
+  E eps[KSLOTS];
 };
+using Slots = SlotsT<double>;
 
 // Workgroup LDS of the slot search: per cell, the slots found so far.
-struct SlotLds {
+template <typename E>
+struct SlotLdsT {
   int n[BLOCK];
   int e[KSLOTS][BLOCK];
-  double eps[KSLOTS][BLOCK];
+  E eps[KSLOTS][BLOCK];
 };
+using SlotLds = SlotLdsT<double>;
 
 // Inclusive prefix sum of an int over the 64 lanes of a wave, in DPP steps:
 // shifts by 1, 2, 4 and 8 within each row of 16 lanes, then the row totals
@@ -84,10 +90,10 @@ __device__ __forceinline__ int wave_scan_incl(int v) {
 // cell (more set ERR_SLOTS).  All 64 lanes must call this.
 static_assert(TX == 64, "one wave per tile row");
 
-template <int D>
+template <int D, typename E>
 __device__ inline void collect_slots(const Geom& g, int x0, int x, int y, int z, bool active,
-                                     const LdsEntry* lds, int cnt, double h, Slots& s,
-                                     unsigned* err, SlotLds& sl) {
+                                     const LdsEntry* lds, int cnt, double h, SlotsT<E>& s,
+                                     unsigned* err, SlotLdsT<E>& sl) {
   const int px = g.periodic[0], py = g.periodic[1], pz = g.periodic[2];
   const int nx = g.nx, ny = g.ny, nz = g.nz;
   const int tid = (int)threadIdx.x;
@@ -176,7 +182,7 @@ __device__ inline void collect_slots(const Geom& g, int x0, int x, int y, int z,
         const int k = atomicAdd(&sl.n[c], 1);
         if (k < KSLOTS) {
           sl.e[k][c] = e;
-          sl.eps[k][c] = eps;
+          sl.eps[k][c] = (E)eps;
         } else if (err) {
           atomicOr(err, ERR_SLOTS);
         }
@@ -194,7 +200,7 @@ __device__ inline void collect_slots(const Geom& g, int x0, int x, int y, int z,
   for (int k = 0; k < KSLOTS; ++k) {
     const bool has = k < n;
     s.e[k] = has ? sl.e[k][tid] : 0;
-    s.eps[k] = has ? sl.eps[k][tid] : 0.0;
+    s.eps[k] = has ? sl.eps[k][tid] : (E)0;
     s.id[k] = has ? lds[s.e[k]].id : 0x7fffffff;
   }
   if (__any(n > 1)) {
@@ -202,7 +208,7 @@ __device__ inline void collect_slots(const Geom& g, int x0, int x, int y, int z,
     auto cx = [&](int i, int k) {
       const bool sw = s.id[k] < s.id[i];
       const int ti = s.id[i], te = s.e[i];
-      const double tp = s.eps[i];
+      const E tp = s.eps[i];
       s.id[i] = sw ? s.id[k] : ti;
       s.e[i] = sw ? s.e[k] : te;
       s.eps[i] = sw ? s.eps[k] : tp;
