@@ -202,6 +202,63 @@ def settle_packing(w, nsteps):
     return f0, ps, info
 
 
+def run_ergun(dps, res, weightings, chunk=500, tol=1e-6, max_steps=200_000):
+    """Sec. 3.4 packed bed (8 fixed spheres in simple-cubic contact, periodic
+    2 d_p cube, body force): each case run to steady state in the FP64 form
+    (relative change of the superficial velocity below `tol` per `chunk`
+    steps), then Eq. 36's Re_p* and dP* against Eq. 35."""
+    import time
+    import torch
+    import paper_1901_09745_amd.psclbm as P
+    import workloads as W
+
+    out = []
+    for dp in dps:
+        for re in res:
+            w = W.ergun(dp, re)
+            lat = w.lattice
+            for wt in weightings:
+                G = P.Lattice(lat, "fp64", max_particles=8, max_radius=dp / 2.0,
+                              max_tile_particles=64, weighting=wt)
+                G.rasterize(P.DeviceParticles.from_host(w.particles))
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                steps, U_prev, U = 0, None, 0.0
+                while steps < max_steps:
+                    G.step(chunk)
+                    steps += chunk
+                    rho, u = G.macros()
+                    # superficial velocity: flux through the plane x = 0 over its area
+                    U = float((rho[:, :, 0] * u[:, :, 0, 0]).mean()) / lat.rho0
+                    if not np.isfinite(U):   # unstable (lattice too coarse for the velocity)
+                        break
+                    if U_prev is not None and abs(U - U_prev) < tol * abs(U):
+                        break
+                    U_prev = U
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                stable = bool(np.isfinite(U))
+                rec = {"d_p": dp, "Re_target": re, "weighting": wt, "cells": lat.ncells,
+                       "steps": steps, "stable": stable,
+                       "converged": stable and steps < max_steps,
+                       "seconds": dt, "mlups": lat.ncells * steps / dt / 1e6,
+                       "U": None, "Re_p*": None, "dP*": None, "dP*_Eq35": None,
+                       "rel_err": None}
+                if stable:
+                    re_m, dps_m = W.ergun_numbers(lat.force[0], U, dp, lat.tau)
+                    ref = W.ergun_dp_star(re_m)
+                    rec.update({"U": U, "Re_p*": re_m, "dP*": dps_m, "dP*_Eq35": ref,
+                                "rel_err": dps_m / ref - 1.0})
+                    _log(f"bench: ergun d_p={dp} Re*={re_m:.3f} {wt}: dP*={dps_m:.2f} vs "
+                         f"{ref:.2f} ({dps_m / ref - 1.0:+.4f}), {steps} steps")
+                else:
+                    _log(f"bench: ergun d_p={dp} target Re*={re} {wt}: unstable after "
+                         f"{steps} steps")
+                out.append(rec)
+                del G
+    return out
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The FP64 oracle on the host: coupled steps of the same workload for
     about budget_s seconds."""
@@ -270,6 +327,8 @@ def main():
                     help="steps of the differentiable 3D packing window (0: skip)")
     ap.add_argument("--settle-steps", type=int, default=19500,
                     help="coupled steps that settle the 3D packing before its window")
+    ap.add_argument("--ergun-dps", default="10,20,40,80",
+                    help="sphere diameters of the packed-bed (Sec. 3.4) runs ('' to skip)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (the reference kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -394,6 +453,13 @@ def main():
             del f0
         adj["ratio"] = adj["channel_2d"]["ratio"]
         out["adjoint"] = adj
+    dps = [int(v) for v in args.ergun_dps.split(",") if v.strip()]
+    if dps:
+        out["ergun"] = {
+            "workload": "Sec. 3.4 packed bed: 8 fixed spheres of diameter d_p in simple-cubic "
+                        "contact, periodic 2d_p cube, D3Q19 tau=0.65, body force from Eq. 35 "
+                        "at the target Re_p*, FP64, run to steady state",
+            "runs": run_ergun(dps, (1.0, 10.0), ("modified", "original"))}
     if not args.no_cpu:
         _log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(w2, args.cpu_budget)

@@ -340,6 +340,51 @@ def c5(scale: float = 1.0, seed: int = 5) -> Workload:
                     f"{n} adhesive spheres r~U(3,5) seed {seed}, gravity 1e-6 along -x")
 
 
+# --------------------------------------------------------------------------
+# Packed bed of Sec. 3.4 (Ergun, Eqs. 34-36)
+# --------------------------------------------------------------------------
+
+# porosity of the simple-cubic lattice packing of touching spheres
+ERGUN_POROSITY = 1.0 - np.pi / 6.0
+
+
+def ergun_dp_star(re: float) -> float:
+    """Eq. 35: dimensionless pressure loss 150 / Re_p* + 1.75."""
+    return 150.0 / re + 1.75
+
+
+def ergun_numbers(force: float, U: float, dp: float, tau: float, rho: float = 1.0,
+                  porosity: float = ERGUN_POROSITY) -> Tuple[float, float]:
+    """Eq. 36 for a bed driven by a body force (pressure gradient dP/h = force)
+    with superficial velocity U: (Re_p*, dP*), lattice units, nu = (tau - 1/2)/3.
+    dP* carries eps^3 / (1 - eps): with that factor Eq. 35 is Eq. 34 divided
+    through; the printed (1 - eps)^2 would leave a stray factor 1 - eps."""
+    nu = (tau - 0.5) / 3.0
+    re = dp * U / (nu * (1.0 - porosity))
+    dps = force * dp / (rho * U * U) * porosity ** 3 / (1.0 - porosity)
+    return re, dps
+
+
+def ergun(dp: int, re: float = 1.0, tau: float = 0.65) -> Workload:
+    """Sec. 3.4: the lattice packing of 8 fixed spheres of diameter dp in a
+    periodic 2dp cube (neighbouring spheres touch, so the cells at the
+    contacts are shared), D3Q19, driven along x by the body force for which
+    Eq. 35 gives the modified Reynolds number `re`.  Centres at
+    ((i + 1/2) dp, ...): every contact point is a cell centre, a cell the
+    two touching spheres share (the paper leaves the alignment open)."""
+    L = 2 * dp
+    c = [(i + 0.5) * dp for i in range(2)]
+    x = np.array([[cx, cy, cz] for cz in c for cy in c for cx in c])
+    eps = ERGUN_POROSITY
+    nu = (tau - 0.5) / 3.0
+    U = re * nu * (1.0 - eps) / dp
+    force = ergun_dp_star(re) * U * U * (1.0 - eps) / (dp * eps ** 3)
+    lat = LatticeSpec(q=19, nx=L, ny=L, nz=L, tau=tau, force=(force, 0.0, 0.0))
+    return Workload(f"ergun{dp}", lat, _particles(x, r=np.full(8, dp / 2.0)), steps=0,
+                    description=f"D3Q19 tau={tau} {L}^3 periodic, 8 fixed spheres d_p={dp} in "
+                    f"simple-cubic contact, body force {force:.3e} (Eq. 35 at Re_p*={re})")
+
+
 WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
 
 
