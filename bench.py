@@ -259,6 +259,54 @@ def run_ergun(dps, res, weightings, chunk=500, tol=1e-6, max_steps=200_000):
     return out
 
 
+def run_drag(cases, precision="fp32", chunk=1000, tol=1e-5, max_steps=150_000):
+    """Sec. 3.2 fixed sphere in a 20d x 10d x 10d box (equilibrium inlet u0,
+    constant-pressure outlet and open sides): each case (d_p, Re_p, u0) run
+    until, after five flow-through times, the drag changes by less than `tol`
+    per `chunk` steps; the drag coefficient (Eq. 32) against Eq. 33."""
+    import time
+    import torch
+    import paper_1901_09745_amd.psclbm as P
+    import workloads as W
+
+    out = []
+    for dp, re, u0 in cases:
+        w = W.sphere_drag(dp, re, u0)
+        lat = w.lattice
+        G = P.Lattice(lat, precision, max_particles=1, max_radius=dp / 2.0,
+                      max_tile_particles=64)
+        G.rasterize(P.DeviceParticles.from_host(w.particles))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps, prev, fx = 0, None, float("nan")
+        min_steps = int(5 * lat.nx / u0)
+        while steps < max_steps:
+            G.step(chunk)
+            steps += chunk
+            F, _ = G.forces()
+            fx = float(F[0, 0])
+            if not np.isfinite(fx):
+                break
+            if steps >= min_steps and prev is not None and abs(fx - prev) < tol * abs(fx):
+                break
+            prev = fx
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        stable = bool(np.isfinite(fx))
+        cd = W.drag_coefficient(fx, u0, dp) if stable else None
+        ref = W.schiller_naumann(re)
+        out.append({"d_p": dp, "Re_p": re, "u0": u0, "tau": lat.tau, "cells": lat.ncells,
+                    "precision": precision, "steps": steps, "stable": stable,
+                    "converged": stable and steps < max_steps, "seconds": dt,
+                    "mlups": lat.ncells * steps / dt / 1e6, "C_d": cd, "C_d_Eq33": ref,
+                    "rel_err": (cd / ref - 1.0) if stable else None})
+        _log(f"bench: drag d_p={dp} Re_p={re} u0={u0}: C_d="
+             + (f"{cd:.4f} vs {ref:.4f} ({cd / ref - 1.0:+.4f})" if stable else "unstable")
+             + f", {steps} steps")
+        del G
+    return out
+
+
 def cpu_baseline(w, budget_s=15.0):
     """The FP64 oracle on the host: coupled steps of the same workload for
     about budget_s seconds."""
@@ -329,6 +377,8 @@ def main():
                     help="coupled steps that settle the 3D packing before its window")
     ap.add_argument("--ergun-dps", default="10,20,40,80",
                     help="sphere diameters of the packed-bed (Sec. 3.4) runs ('' to skip)")
+    ap.add_argument("--no-drag", action="store_true",
+                    help="skip the fixed-sphere drag runs (Sec. 3.2)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run a plain 1 GiB device copy (the reference kernel that "
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
@@ -460,6 +510,14 @@ def main():
                         "contact, periodic 2d_p cube, D3Q19 tau=0.65, body force from Eq. 35 "
                         "at the target Re_p*, FP64, run to steady state",
             "runs": run_ergun(dps, (1.0, 10.0), ("modified", "original"))}
+    if not args.no_drag:
+        out["drag"] = {
+            "workload": "Sec. 3.2 fixed sphere at the centre of a 20d x 10d x 10d box, D3Q19, "
+                        "equilibrium inlet u0 on x, constant-pressure outlets on the other "
+                        "five faces, tau from Re_p = u0 d_p / nu, FP32 form, run to steady drag",
+            "runs": run_drag([(10, 10.0, 0.05), (10, 50.0, 0.05), (10, 100.0, 0.05),
+                              (20, 10.0, 0.05), (20, 100.0, 0.05),
+                              (10, 10.0, 0.02), (10, 1.0, 0.05)])}
     if not args.no_cpu:
         _log("bench: CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(w2, args.cpu_budget)

@@ -385,6 +385,37 @@ def ergun(dp: int, re: float = 1.0, tau: float = 0.65) -> Workload:
                     f"simple-cubic contact, body force {force:.3e} (Eq. 35 at Re_p*={re})")
 
 
+# --------------------------------------------------------------------------
+# Drag on a fixed sphere, Sec. 3.2 (Eqs. 32-33)
+# --------------------------------------------------------------------------
+
+def drag_coefficient(force: float, u0: float, dp: float, rho: float = 1.0) -> float:
+    """Eq. 32: C_d = 8 F_d / (rho U0^2 pi d_p^2)."""
+    return 8.0 * force / (rho * u0 * u0 * np.pi * dp * dp)
+
+
+def schiller_naumann(re: float) -> float:
+    """Eq. 33: C_d = 24 / Re_p (1 + 0.15 Re_p^0.687)."""
+    return 24.0 / re * (1.0 + 0.15 * re ** 0.687)
+
+
+def sphere_drag(dp: int, re: float, u0: float = 0.05) -> Workload:
+    """Sec. 3.2: a fixed sphere of diameter dp at the centre of a
+    20dp x 10dp x 10dp box, D3Q19; equilibrium inlet u0 along x on x = 0, a
+    constant-pressure outlet on x = nx - 1, and the four side faces open
+    (constant-pressure outlets: zero normal gradient of the velocity, rho0);
+    tau from Re_p = u0 dp / nu."""
+    nx, ny, nz = 20 * dp, 10 * dp, 10 * dp
+    nu = u0 * dp / re
+    lat = LatticeSpec(q=19, nx=nx, ny=ny, nz=nz, tau=3.0 * nu + 0.5,
+                      faces=(INLET_EQ, OUTLET_EQ, OUTLET_EQ, OUTLET_EQ, OUTLET_EQ, OUTLET_EQ),
+                      face_u=((u0, 0.0, 0.0),) + ((0.0, 0.0, 0.0),) * 5)
+    x = np.array([[(nx - 1) / 2.0, (ny - 1) / 2.0, (nz - 1) / 2.0]])
+    return Workload(f"drag{dp}_re{re:g}", lat, _particles(x, r=np.array([dp / 2.0])), steps=0,
+                    description=f"D3Q19 {nx}x{ny}x{nz}, tau={3.0 * nu + 0.5:.4f}, inlet u0={u0} "
+                    f"on x, outlets elsewhere, fixed sphere d_p={dp} at the centre (Re_p={re:g})")
+
+
 WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
 
 
