@@ -297,6 +297,14 @@ __global__ void __launch_bounds__(BLOCK)
   if constexpr (Q == 19) {
     if (cnt > 0) collect_slots<D>(a.g, x0, x, y, z, active, lds, cnt, a.h, s, a.err, slot_lds);
   }
+  // the slots' list entries, two to a register (entries < 2^16; the list
+  // capacity is at most 512): registers held through the collision
+  const unsigned e01 = (unsigned)s.e[0] | ((unsigned)s.e[1] << 16);
+  const unsigned e23 = (unsigned)s.e[2] | ((unsigned)s.e[3] << 16);
+  auto slot_e = [&](int k) {
+    return (int)(((k < 2 ? e01 : e23) >> (16 * (k & 1))) & 0xffffu);
+  };
+  static_assert(KSLOTS == 4, "entries packed for four slots");
 
   if (active) {
     // ---- inlet / outlet layers: reset to an equilibrium before collision ----
@@ -452,6 +460,13 @@ __global__ void __launch_bounds__(BLOCK)
     double bscale = tm * inv_den;
     if (S_ > 1.0) bscale = 1.0 / S_;
     constexpr int NV = D == 3 ? 6 : 3;
+    // the row's y and z as FP64, converted from their scalar registers at each
+    // use: an empty asm makes each use opaque, so the compiler does not hold
+    // (or spill) one converted copy across the slots
+    auto row_coord = [](int v) {
+      asm volatile("" : "+s"(v));
+      return (double)v;
+    };
     // slot k of this cell: the equilibrium difference into g and, unless the
     // step accumulates no force (the ring step), the negated exchange into mv
     auto slot_update = [&](int k, C (&mv)[NV]) {
@@ -459,10 +474,10 @@ __global__ void __launch_bounds__(BLOCK)
                               : (C)(s.eps[k] * bscale);
       // Eq. 14 weighs the momentum exchange by B_s; Eq. 11 by the cell's B_n
       const C Bm = a.original ? Bn_cell : Bs;
-      const LdsEntry& P = lds[s.e[k]];
+      const LdsEntry& P = lds[slot_e(k)];
       const double rx = min_image((double)x - P.x, d.px, d.nx);
-      const double ry = min_image((double)y - P.y, d.py, d.ny);
-      const double rz = D == 3 ? min_image((double)z - P.z, d.pz, d.nz) : 0.0;
+      const double ry = min_image(row_coord(y) - P.y, d.py, d.ny);
+      const double rz = D == 3 ? min_image(row_coord(z) - P.z, d.pz, d.nz) : 0.0;
       // rigid-body velocity of particle s at the cell centre
       const C usx = (C)(P.u[0] + P.w[1] * rz - P.w[2] * ry);
       const C usy = (C)(P.u[1] + P.w[2] * rx - P.w[0] * rz);
@@ -524,7 +539,7 @@ __global__ void __launch_bounds__(BLOCK)
           if (k >= s.n) continue;
           C mv[NV];
           slot_update(k, mv);
-          if (a.facc) accumulate(s.e[k], mv);
+          if (a.facc) accumulate(slot_e(k), mv);
         }
       }
     } else {
@@ -542,10 +557,10 @@ __global__ void __launch_bounds__(BLOCK)
         if (has) slot_update(k, mv);
         if (a.facc) {
           bool lead;
-          const unsigned mf = merge_flags(has ? s.e[k] : -1, lane, lead);
+          const unsigned mf = merge_flags(has ? slot_e(k) : -1, lane, lead);
 #pragma unroll
           for (int j = 0; j < NV; ++j) mv[j] = merge_sum(mv[j], mf);
-          if (lead) accumulate(s.e[k], mv);
+          if (lead) accumulate(slot_e(k), mv);
         }
       }
     }
