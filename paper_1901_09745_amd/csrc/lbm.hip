@@ -195,19 +195,21 @@ __device__ inline Cell cell_of(const Geom& g, long long n) {
 // ---------------------------------------------------------------------------
 // The fused collide-stream step.
 // ---------------------------------------------------------------------------
-// Waves per SIMD of each form (2D FP32 / FP16 8, 3D FP32 / FP16 and 2D FP64
-// 5, 3D FP64 4): the register budget of the tiles, which the contact
-// workgroups' code must fit as well.  At 8 waves the 2D FP32 / FP16 forms
-// spill a few registers and hold their slot fractions in FP32 (the LDS of
-// eight workgroups per CU); measured faster than 7 waves without spills.
-template <int Q, int PREC>
+// Waves per SIMD of each form, the register budget of the tiles (which the
+// contact workgroups' code must fit as well), each as measured fastest: 2D
+// FP32 / FP16 8 (their slot fractions held in FP32, so that eight
+// workgroups' LDS fits a CU), 3D FP16 and walled 3D FP32 6, periodic 3D FP32
+// and 2D FP64 5, 3D FP64 4.
+template <int Q, int PREC, bool WALLS>
 constexpr int step_waves() {
-  return PREC == PSCLBM_FP64 ? (Q == 9 ? 5 : 4) : (Q == 9 ? 8 : 5);
+  if (PREC == PSCLBM_FP64) return Q == 9 ? 5 : 4;
+  if (Q == 9) return 8;
+  return (PREC == PSCLBM_FP32_FP16STORE || WALLS) ? 6 : 5;
 }
 
 template <int Q, int PREC, int PAR, bool WALLS>
 __global__ void __launch_bounds__(BLOCK)
-    __attribute__((amdgpu_waves_per_eu(step_waves<Q, PREC>())))
+    __attribute__((amdgpu_waves_per_eu(step_waves<Q, PREC, WALLS>())))
     k_step(const StepArgs a) {
   using L = Lattice<Q>;
   using C = typename Form<PREC>::C;
