@@ -100,7 +100,7 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
   const unsigned n = (unsigned)x + (unsigned)G.nx * ((unsigned)y + (unsigned)G.ny * (unsigned)z);
   Slots s;
   s.n = 0;
-  if (cnt > 0) collect_slots<D>(G, x0, x, y, z, active, lds, cnt, a.h, s, nullptr, slot_lds);
+  if (cnt > 0) collect_slots<D>(G, x0, y, z, active, lds, cnt, a.h, s, nullptr, slot_lds);
 
   if (active) {
     Dims d;
@@ -584,7 +584,7 @@ __global__ void __launch_bounds__(BLOCK) k_rasterize_adjoint(Geom g, double h, i
   const bool active = x < g.nx && y < g.ny && z < g.nz;
   Slots s;
   s.n = 0;
-  if (cnt > 0) collect_slots<D>(g, x0, x, y, z, active, lds, cnt, h, s, nullptr, slot_lds);
+  if (cnt > 0) collect_slots<D>(g, x0, y, z, active, lds, cnt, h, s, nullptr, slot_lds);
   if (!active) return;
   const long long n = x + (long long)g.nx * (y + (long long)g.ny * z);
 #pragma unroll

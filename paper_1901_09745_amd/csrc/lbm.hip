@@ -270,7 +270,7 @@ __global__ void __launch_bounds__(BLOCK)
   SlotsT<E> s;
   s.n = 0;
   if constexpr (Q == 9) {
-    if (cnt > 0) collect_slots<D>(a.g, x0, x, y, z, active, lds, cnt, a.h, s, a.err, slot_lds);
+    if (cnt > 0) collect_slots<D>(a.g, x0, y, z, active, lds, cnt, a.h, s, a.err, slot_lds);
   }
 
   C g[Q];
@@ -297,7 +297,7 @@ __global__ void __launch_bounds__(BLOCK)
     }
   }
   if constexpr (Q == 19) {
-    if (cnt > 0) collect_slots<D>(a.g, x0, x, y, z, active, lds, cnt, a.h, s, a.err, slot_lds);
+    if (cnt > 0) collect_slots<D>(a.g, x0, y, z, active, lds, cnt, a.h, s, a.err, slot_lds);
   }
   // the slots' list entries, two to a register (entries < 2^16; the list
   // capacity is at most 512): registers held through the collision
@@ -762,7 +762,7 @@ __global__ void k_reduce(const double* part, int n, double* out) {
   s[threadIdx.x] = t;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
-    if (threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
+    if ((int)threadIdx.x < w) s[threadIdx.x] += s[threadIdx.x + w];
     __syncthreads();
   }
   if (threadIdx.x == 0) out[0] = s[0];
@@ -826,7 +826,7 @@ __global__ void __launch_bounds__(BLOCK) k_solid_fraction(Geom g, double h, int 
   c.n = c.x + (long long)g.nx * (c.y + (long long)g.ny * c.z);
   Slots s;
   s.n = 0;
-  if (cnt > 0) collect_slots<D>(g, x0, c.x, c.y, c.z, active, lds, cnt, h, s, err, slot_lds);
+  if (cnt > 0) collect_slots<D>(g, x0, c.y, c.z, active, lds, cnt, h, s, err, slot_lds);
   if (!active) return;
   double S_ = 0.0;
 #pragma unroll

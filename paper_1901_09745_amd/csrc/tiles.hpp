@@ -81,17 +81,18 @@ __device__ __forceinline__ int wave_scan_incl(int v) {
 // entry's y and z separations are the same for the whole wave.  Phase 1: each
 // lane takes one list entry and, when its shell r + h reaches the row, the
 // chord of the row the shell can cover (the lanes whose cell centres lie
-// within sqrt((r + h)^2 - dy^2 - dz^2) of the centre's nearest image, widened
-// by 1e-6; on periodic x narrower than 64 + 2 (r + h) + 2 the whole row).
-// Phase 2: the (entry, cell) pairs of all chords, laid out entry by entry, are
-// taken 64 at a time, one per lane: Table 1 for the pair, and a slot of its
-// cell in LDS when the fraction is positive.  Phase 3: each cell reads its
+// within sqrt((r + h)^2 - dy^2 - dz^2) of the centre's nearest image, bounded
+// in FP32 and widened by 1e-3 lanes, since it only limits the cells examined;
+// on periodic x narrower than 64 + 2 (r + h) + 2 the whole row).  Phase 2: the
+// (entry, cell) pairs of all chords, laid out entry by entry by a prefix scan,
+// are taken 64 at a time, one per lane: Table 1 for the pair in FP64, and a
+// slot of its cell in LDS when the fraction is positive.  Phase 3: each cell reads its
 // slots and orders them by particle id.  At most KSLOTS slots are kept per
 // cell (more set ERR_SLOTS).  All 64 lanes must call this.
 static_assert(TX == 64, "one wave per tile row");
 
 template <int D, typename E>
-__device__ inline void collect_slots(const Geom& g, int x0, int x, int y, int z, bool active,
+__device__ inline void collect_slots(const Geom& g, int x0, int y, int z, bool active,
                                      const LdsEntry* lds, int cnt, double h, SlotsT<E>& s,
                                      unsigned* err, SlotLdsT<E>& sl) {
   const int px = g.periodic[0], py = g.periodic[1], pz = g.periodic[2];
