@@ -570,12 +570,17 @@ __global__ void __launch_bounds__(BLOCK)
 
   if (active) {
     // ---- stream (Eq. 1) with halfway bounce-back (Eq. 6) ----
+    // the cell index formed again from x (an empty asm keeps the compiler from
+    // reusing, and so holding or spilling, the one the loads used)
+    unsigned xo = (unsigned)x;
+    asm volatile("" : "+v"(xo));
+    const unsigned no = xo + d.sy * (unsigned)y + d.sz * (unsigned)z;
     C cell_dev = 0;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      unsigned m = n;
+      unsigned m = no;
       const unsigned out =
-          i == 0 ? 0u : link<WALLS>(d, x, y, z, L::ex(i), L::ey(i), L::ez(i), n, m);
+          i == 0 ? 0u : link<WALLS>(d, x, y, z, L::ex(i), L::ey(i), L::ez(i), no, m);
       C v = g[i];
       if (out) {
         const unsigned mw = out & a.moving_mask;
@@ -593,7 +598,7 @@ __global__ void __launch_bounds__(BLOCK)
         }
       }
       if (PAR == 0 || out)  // own cell, opposite slot
-        cell_dev += ST::st(A + (size_t)L::opp(i) * N, n, i, v, rho0);
+        cell_dev += ST::st(A + (size_t)L::opp(i) * N, no, i, v, rho0);
       else                  // neighbour cell, same slot
         cell_dev += ST::st(A + (size_t)i * N, m, i, v, rho0);
     }
