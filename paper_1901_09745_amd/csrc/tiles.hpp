@@ -235,11 +235,16 @@ __device__ inline void collect_slots(const Geom& g, int x0, int y, int z, bool a
 __device__ inline int load_tile_list(const int* tile_count, const int* tile_list, int cap,
                                      const PSnap* snap, int tile, LdsEntry* lds, double* acc,
                                      int np) {
+  // each thread's first list entry is read alongside the count (entries past
+  // the count are stale ids or zeros inside the list buffer, never used)
+  const int* lst = tile_list + (size_t)tile * cap;
+  const int e0 = (int)threadIdx.x;
+  const int pre = np > 0 && e0 < cap ? lst[e0] : 0;
   int cnt = np > 0 ? tile_count[tile] : 0;
   if (cnt > cap) cnt = cap;
   if (cnt == 0) return 0;
-  for (int e = threadIdx.x; e < cnt; e += BLOCK) {
-    const int id = tile_list[(size_t)tile * cap + e];
+  for (int e = e0; e < cnt; e += BLOCK) {
+    const int id = e == e0 ? pre : lst[e];
     const PSnap& P = snap[id];
     LdsEntry& L = lds[e];
     L.x = P.x[0];
