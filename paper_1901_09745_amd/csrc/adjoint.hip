@@ -260,41 +260,18 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
     // common to every particle, start from the state sums Sf, So; and the
     // moments of w_i lam*_i (orders 0, 1, 2 in e_i), through which the
     // particle terms close
-    // The velocity gradient sums
-    //   sum_i cf_i df^eq_i/du = sum_i cf_i rho w_i (3 e_i + 9 (e_i.u) e_i - 3 u) and
-    //   sum_i cF_i dF_i/du / (k w_i) = sum_i cF_i (9 (e_i.F) e_i - 3 F)
-    // are collected as sum_i t_i e_i (only the nonzero components of e_i are
-    // added) minus 3 u sum_i cf_i rho w_i and 3 F sum_i cF_i.
-    double ar = 0.0, LP = w * Sf, L0 = So - Sf;
-    double vx = 0.0, vy = 0.0, vz = 0.0, scw = 0.0, scF = 0.0;
+    // Moments of w_i lam*_i (orders 0, 1, 2 in e_i; only the nonzero
+    // components of e_i are added).  Every sum over directions of the base
+    // adjoint closes on them, since f^eq_i and F_i are polynomials of degree
+    // two in e_i with the weight w_i, and e_{-i} = -e_i, w_{-i} = w_i:
+    //   sum_i lam*_i    f^eq_i / rho = m0 (1 - 1.5 u^2) + 3 u.m1 + 4.5 u.M2.u  (Qp)
+    //   sum_i lam*_{-i} f^eq_i / rho = m0 (1 - 1.5 u^2) - 3 u.m1 + 4.5 u.M2.u  (Qm)
+    //   sum_i lam*_i F_i / k = 3 (F.m1 - (u.F) m0) + 9 u.M2.F
     double m0 = 0.0, m1x = 0.0, m1y = 0.0, m1z = 0.0;
     double mxx = 0.0, myy = 0.0, mzz = 0.0, mxy = 0.0, mxz = 0.0, myz = 0.0;
-    const double irho = 1.0 / rho;
-    const double uF = ux * F0 + uy * F1 + uz * F2;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const int o = L::opp(i);
       const int ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
-      const double eu = edot(ex, ey, ez, ux, uy, uz);
-      const double rw = rho * L::w(i);
-      const double sq = 1.0 + 4.5 * eu * eu - 1.5 * uu;
-      const double fe = rw * (sq + 3.0 * eu);
-      const double fe_o = rw * (sq - 3.0 * eu);
-      const double eF = edot(ex, ey, ez, F0, F1, F2);
-      const double Fi = kg * L::w(i) * (3.0 * (eF - uF) + 9.0 * eu * eF);
-      LP -= ls[i] * (w * fe + Fi);
-      L0 -= ls[i] * fe_o;
-      // coefficient of f^eq_i: (1-B_n) w lam*_i - B_n lam*_{-i}
-      const double cf = (1.0 - Bn) * w * ls[i] - Bn * ls[o];
-      ar += cf * fe * irho;
-      const double crw = cf * rw;
-      const double cF = (1.0 - Bn) * ls[i] * kg * L::w(i);
-      scw += crw;
-      scF += cF;
-      const double t = crw * (3.0 + 9.0 * eu) + 9.0 * cF * eF;
-      eacc(ex, vx, t);
-      eacc(ey, vy, t);
-      eacc(ez, vz, t);
       const double wl = L::w(i) * ls[i];
       m0 += wl;
       eacc(ex, m1x, wl);
@@ -307,9 +284,36 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
       eacc(ex * ez, mxz, wl);
       eacc(ey * ez, myz, wl);
     }
-    double aux = vx - 3.0 * (ux * scw + F0 * scF);
-    double auy = vy - 3.0 * (uy * scw + F1 * scF);
-    double auz = vz - 3.0 * (uz * scw + F2 * scF);
+    const double irho = 1.0 / rho;
+    const double uF = ux * F0 + uy * F1 + uz * F2;
+    const double Mux = mxx * ux + mxy * uy + mxz * uz;  // M2 u
+    const double Muy = mxy * ux + myy * uy + myz * uz;
+    const double Muz = mxz * ux + myz * uy + mzz * uz;
+    const double MFx = mxx * F0 + mxy * F1 + mxz * F2;  // M2 F
+    const double MFy = mxy * F0 + myy * F1 + myz * F2;
+    const double MFz = mxz * F0 + myz * F1 + mzz * F2;
+    const double um1 = ux * m1x + uy * m1y + uz * m1z;
+    const double uMu = ux * Mux + uy * Muy + uz * Muz;
+    const double even = m0 * (1.0 - 1.5 * uu) + 4.5 * uMu;
+    const double Qp = even + 3.0 * um1, Qm = even - 3.0 * um1;
+    const double lF = kg * (3.0 * ((F0 * m1x + F1 * m1y + F2 * m1z) - uF * m0) +
+                            9.0 * (ux * MFx + uy * MFy + uz * MFz));
+    // LP = sum_i lam*_i (w (f_i - f^eq_i) - F_i) and L0 = sum_i lam*_i
+    // (f_{-i} - f^eq_{-i} - f_i), the part of lam* . Omega^s common to every
+    // particle, from the state sums Sf, So
+    const double LP = w * (Sf - rho * Qp) - lF;
+    const double L0 = So - Sf - rho * Qm;
+    // the coefficient of f^eq_i is cf_i = (1-B_n) w lam*_i - B_n lam*_{-i}:
+    // sum_i cf_i f^eq_i / rho, and the velocity gradient
+    //   sum_i cf_i df^eq_i/du + (1-B_n) lam*_i dF_i/du
+    //   = rho (3 c1 m1 + 9 c2 M2 u - 3 c2 m0 u) + (1-B_n) k (9 M2 F - 3 m0 F)
+    // with c1 = (1-B_n) w + B_n, c2 = (1-B_n) w - B_n
+    double ar = (1.0 - Bn) * w * Qp - Bn * Qm;
+    const double c1 = (1.0 - Bn) * w + Bn, c2 = (1.0 - Bn) * w - Bn;
+    const double kF = (1.0 - Bn) * kg;
+    double aux = rho * (3.0 * c1 * m1x + 9.0 * c2 * Mux - 3.0 * c2 * m0 * ux) + kF * (9.0 * MFx - 3.0 * m0 * F0);
+    double auy = rho * (3.0 * c1 * m1y + 9.0 * c2 * Muy - 3.0 * c2 * m0 * uy) + kF * (9.0 * MFy - 3.0 * m0 * F1);
+    double auz = rho * (3.0 * c1 * m1z + 9.0 * c2 * Muz - 3.0 * c2 * m0 * uz) + kF * (9.0 * MFz - 3.0 * m0 * F2);
 
     // covering particles, first pass: G_s = lam* . Omega^s + q_s . M_s with
     //   lam* . f^eq(rho, u_s) = rho [m0 (1 - 1.5 u_s^2) + 3 u_s . m1 + 4.5 u_s.M2.u_s]
