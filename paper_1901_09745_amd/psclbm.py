@@ -304,7 +304,8 @@ class Lattice:
     def __init__(self, spec, precision: str = "fp64", max_particles: int = 0,
                  max_radius: float = 0.0, max_tile_particles: int = 128, max_contacts: int = 16,
                  device: str = "cuda", weighting: str = "modified"):
-        load()
+        # held for __del__, which may run after the module's globals are gone
+        self._lib = load()
         self.spec = spec
         self.cfg = make_config(spec, precision, max_particles, max_radius, max_tile_particles,
                                max_contacts, weighting)
@@ -319,8 +320,9 @@ class Lattice:
 
     def __del__(self):
         ctx = getattr(self, "ctx", None)
-        if ctx:
-            lbm_free(ctx)
+        lib = getattr(self, "_lib", None)
+        if ctx and lib is not None:
+            lib.lbm_free(ctx)
             self.ctx = None
 
     # state I/O -------------------------------------------------------------
