@@ -52,7 +52,9 @@ class _Dem(ctypes.Structure):
                 ("E_p", ctypes.c_double), ("poisson", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("eta_n", ctypes.c_double),
                 ("g", ctypes.c_double * 3), ("dt", ctypes.c_double),
-                ("n_sub", ctypes.c_int), ("kinematic", ctypes.c_int)]
+                ("n_sub", ctypes.c_int), ("kinematic", ctypes.c_int),
+                ("k_t", ctypes.c_double), ("eta_t", ctypes.c_double),
+                ("mu_f", ctypes.c_double)]
 
 
 _lib_handle = None
@@ -88,7 +90,7 @@ def _lib():
         L.or_jkr_force.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                    ctypes.c_double, _D, _D]
         L.or_dem_step.argtypes = [ctypes.POINTER(_Config), ctypes.POINTER(_Dem), ctypes.c_int,
-                                  _D, _D, _D, _D, _D, _D, ctypes.c_int, _I, _I]
+                                  _D, _D, _D, _D, _D, _D, ctypes.c_int, _I, _I, _D]
         L.or_num_threads.restype = ctypes.c_int
         _lib_handle = L
     return _lib_handle
@@ -288,6 +290,7 @@ def make_dem(d) -> _Dem:
     for a in range(3):
         p.g[a] = d.g[a]
     p.dt, p.n_sub, p.kinematic = d.dt, d.n_sub, int(d.kinematic)
+    p.k_t, p.eta_t, p.mu_f = d.k_t, d.eta_t, d.mu_f
     return p
 
 
@@ -300,6 +303,8 @@ class Dem:
         self.cap = dem.max_contacts
         self.ncontact = np.zeros(max(n, 1), dtype=np.int32)
         self.ids = np.zeros(max(n, 1) * self.cap, dtype=np.int32)
+        # each contact's springs (tangential displacement xi[3], twist angle)
+        self.hist = np.zeros(max(n, 1) * self.cap * 4)
 
     def step(self, p, F: np.ndarray, T: np.ndarray) -> None:
         """Advance p in place by one coupling step with fluid force F, torque T."""
@@ -307,10 +312,18 @@ class Dem:
         Tc = np.ascontiguousarray(T, dtype=np.float64)
         rc = _lib().or_dem_step(ctypes.byref(self.cfg), ctypes.byref(self.params), p.n,
                                 _dp(p.x), _dp(p.u), _dp(p.omega), _dp(p.r), _dp(Fc), _dp(Tc),
-                                self.cap, _ip(self.ncontact), _ip(self.ids))
+                                self.cap, _ip(self.ncontact), _ip(self.ids), _dp(self.hist))
         if rc:
             raise RuntimeError(f"oracle DEM step failed: {rc}")
 
     def contacts(self):
         return [sorted(self.ids[i * self.cap: i * self.cap + self.ncontact[i]].tolist())
                 for i in range(self.ncontact.size)]
+
+    def springs(self, i: int) -> dict:
+        """{contact id: (xi[3], theta)} of particle i's contacts."""
+        out = {}
+        for k in range(self.ncontact[i]):
+            h = self.hist[(i * self.cap + k) * 4:(i * self.cap + k + 1) * 4]
+            out[int(self.ids[i * self.cap + k])] = (h[:3].copy(), float(h[3]))
+        return out

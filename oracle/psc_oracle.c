@@ -25,7 +25,8 @@
  *   Sec. 2.1 Eqs. 1-5 (BGK + Guo forcing), Sec. 2.2 Eq. 6 (bounce-back),
  *   Sec. 2.3 Eqs. 10, 12-14 (modified PSC collision and per-particle forces),
  *   Sec. 2.4 Eqs. 15-19 and Table 1 (linear solid fraction),
- *   Sec. 2.5 Eqs. 21, 25-27 (Newton-Euler motion with the JKR normal force).
+ *   Sec. 2.5 Eqs. 21, 25-27 (Newton-Euler motion with the JKR normal force)
+ *   and Eqs. 22, 28, 29 (sliding and twisting friction, optional).
  * Readings of points the paper leaves open are marked "Reading:".
  */
 #include <math.h>
@@ -82,6 +83,9 @@ typedef struct {
   double dt;           /* coupling time step (one LBM step) */
   int n_sub;           /* DEM sub-cycles per coupling step (ratio lambda) */
   int kinematic;       /* 1: X += dt*U only (prescribed motion) */
+  double k_t;          /* tangential stiffness k_T (Eq. 28) */
+  double eta_t;        /* tangential dissipation coefficient eta_T (Eq. 28) */
+  double mu_f;         /* friction coefficient (Eq. 29); 0: no sliding or twisting friction */
 } or_dem_params;
 
 int or_version(void) { return 1; }
@@ -594,9 +598,99 @@ void or_jkr_force(double R, double E, double gamma, double delta,
   *dC = k.dC;
 }
 
-static int in_list(const int* ids, int n, int id) {
-  for (int k = 0; k < n; ++k) if (ids[k] == id) return 1;
-  return 0;
+/* Position of id in a contact list of n entries, or -1. */
+static int list_index(const int* ids, int n, int id) {
+  for (int k = 0; k < n; ++k) if (ids[k] == id) return k;
+  return -1;
+}
+
+static int in_list(const int* ids, int n, int id) { return list_index(ids, n, id) >= 0; }
+
+/* The springs (xi[3], theta) that contact id carried in the previous list
+ * (ids[n], springs hs[4n]), or zero for a new contact. */
+static void prev_springs(const int* ids, int n, const double* hs, int id, double h[4]) {
+  int k = list_index(ids, n, id);
+  for (int b = 0; b < 4; ++b) h[b] = (k >= 0 && hs) ? hs[4 * k + b] : 0.0;
+}
+
+static void cross(const double a[3], const double b[3], double out[3]) {
+  out[0] = a[1] * b[2] - a[2] * b[1];
+  out[1] = a[2] * b[0] - a[0] * b[2];
+  out[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+static double dot3(const double a[3], const double b[3]) {
+  return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
+}
+
+/* Sliding and twisting friction of one contact (Eqs. 22, 28, 29), each a
+ * linear spring-dashpot-slider.  Body i (radius ri, velocity ui, spin wi)
+ * touches body j (rj, uj, wj; a wall has zero velocity and spin) along the
+ * unit normal n from i towards j.  Fne is the JKR elastic normal force
+ * (repulsive positive, no damping), FC = 3 pi gamma R and a the contact
+ * radius.  h holds the contact's springs from the previous sub-step (the
+ * tangential displacement xi[3] and the twist angle theta) and receives the
+ * new ones; the force on i is added to fc and its torque about i's centre to
+ * tc.
+ * Readings: v_R is the velocity of j's surface point relative to i's at the
+ *   contact (points at distance ri and rj from the centres along n), and a
+ *   positive displacement of j drags i along with it, which is the paper's
+ *   minus sign with the roles of i and j exchanged; the integral of Eq. 28
+ *   runs from the first sub-step of contact and includes the current one,
+ *   and the stored displacement is projected onto the current tangent plane
+ *   before the step's increment is added; min[.] caps the magnitude of the
+ *   spring-plus-dashpot force (moment), and while it is capped the spring is
+ *   reset to the stretch that gives the capped value (the slider takes the
+ *   rest); F_ne of Eq. 29 is the elastic JKR force, so the cap
+ *   mu_f (F_ne + 2 F_C) is positive on the whole stable branch. */
+static void contact_friction(const or_dem_params* p, const double n[3], double ri,
+                             const double ui[3], const double wi[3], double rj,
+                             const double uj[3], const double wj[3], double Fne, double FC,
+                             double a, double dts, double h[4], double fc[3], double tc[3]) {
+  double rin[3], rjn[3], si[3], sj[3], vR[3], vt[3];
+  for (int b = 0; b < 3; ++b) {
+    rin[b] = ri * n[b];
+    rjn[b] = -rj * n[b];
+  }
+  cross(wi, rin, si);
+  cross(wj, rjn, sj);
+  for (int b = 0; b < 3; ++b) vR[b] = (uj[b] + sj[b]) - (ui[b] + si[b]);
+  const double vn = dot3(vR, n);
+  for (int b = 0; b < 3; ++b) vt[b] = vR[b] - vn * n[b];
+  /* sliding (Eq. 28 first line, cap Eq. 29 first line) */
+  const double Fcrit = p->mu_f * fabs(Fne + 2.0 * FC);
+  const double hn = dot3(h, n);
+  double xi[3], Ft[3];
+  for (int b = 0; b < 3; ++b) {
+    xi[b] = h[b] - hn * n[b] + dts * vt[b];
+    Ft[b] = p->k_t * xi[b] + p->eta_t * vt[b];
+  }
+  const double Fmag = sqrt(dot3(Ft, Ft));
+  if (Fmag > Fcrit) {
+    for (int b = 0; b < 3; ++b) {
+      Ft[b] *= Fcrit / Fmag;
+      xi[b] = (Ft[b] - p->eta_t * vt[b]) / p->k_t;
+    }
+  }
+  double tq[3];
+  cross(rin, Ft, tq);
+  for (int b = 0; b < 3; ++b) {
+    fc[b] += Ft[b];
+    tc[b] += tq[b];
+    h[b] = xi[b];
+  }
+  /* twisting (Eq. 28 second line, cap Eq. 29 second line) */
+  const double Om = dot3(wj, n) - dot3(wi, n);
+  const double kr = 0.5 * p->k_t * a * a, er = 0.5 * p->eta_t * a * a;
+  double theta = h[3] + dts * Om;
+  double Mt = kr * theta + er * Om;
+  const double Mcrit = 3.0 * M_PI * a * Fcrit / 16.0;
+  if (fabs(Mt) > Mcrit) {
+    Mt = Mt > 0.0 ? Mcrit : -Mcrit;
+    theta = (Mt - er * Om) / kr;
+  }
+  for (int b = 0; b < 3; ++b) tc[b] += Mt * n[b];
+  h[3] = theta;
 }
 
 /* One coupling step of the DEM (Eq. 21): n_sub semi-implicit Euler sub-steps
@@ -607,15 +701,21 @@ static int in_list(const int* ids, int n, int id) {
  * of the previous sub-step.  Reading: non-periodic axes have flat walls at
  * -1/2 and L-1/2 acting as JKR bodies of infinite radius and the particle's
  * material; the walls are contact partners -1-face.
- * Contact state: ncontact[np], contact_ids[np*cap] (sorted ascending), in/out.
+ * With mu_f > 0 every contact also carries the sliding and twisting friction
+ * of Eqs. 22, 28, 29 (contact_friction); a wall is at rest.
+ * Contact state: ncontact[np], contact_ids[np*cap] (sorted ascending), in/out;
+ * hist[np*cap*4] (may be NULL without friction) holds each contact's springs
+ * (xi[3], theta) beside its id; without friction the springs are written as
+ * zero, so friction switched on later starts every persisting contact unloaded.
  * Gravity G = (rho_p - rho_f) V g.  2D: disks of unit depth, V = pi r^2,
- * I = m r^2 / 2; 3D: V = 4/3 pi r^3, I = 2 m r^2 / 5.
+ * I = m r^2 / 2, spin about z only; 3D: V = 4/3 pi r^3, I = 2 m r^2 / 5.
  * Returns 0, or -1 when a particle has more than cap contacts. */
 int or_dem_step(const or_config* c, const or_dem_params* p, int np, double* X,
                 double* U, double* W, const double* R, const double* Ff,
-                const double* Tf, int cap, int* ncontact, int* contact_ids) {
+                const double* Tf, int cap, int* ncontact, int* contact_ids, double* hist) {
   const int two_d = (c->q == 9);
   const double dts = p->dt / (double)p->n_sub;
+  const int fric = p->mu_f > 0.0;
   if (p->kinematic) {
     for (int sub = 0; sub < p->n_sub; ++sub)
       for (int s = 0; s < np; ++s)
@@ -623,14 +723,19 @@ int or_dem_step(const or_config* c, const or_dem_params* p, int np, double* X,
   } else {
     const double E = eff_modulus(p);
     double* Fc = (double*)calloc((size_t)3 * np, sizeof(double));
+    double* Tc = (double*)calloc((size_t)3 * np, sizeof(double));
     int* nn = (int*)calloc((size_t)np, sizeof(int));
     int* nid = (int*)calloc((size_t)np * cap, sizeof(int));
+    double* nh = (double*)calloc((size_t)np * cap * 4, sizeof(double));
+    const double zero[3] = {0, 0, 0};
     int rc = 0;
     for (int sub = 0; sub < p->n_sub && rc == 0; ++sub) {
       for (int i = 0; i < np; ++i) {
-        double fc[3] = {0, 0, 0};
+        double fc[3] = {0, 0, 0}, tc[3] = {0, 0, 0};
+        double hl[512][4];
         int cnt = 0, list[512];
         const int* prev = &contact_ids[(size_t)i * cap];
+        const double* prev_h = hist ? &hist[(size_t)i * cap * 4] : NULL;
         /* particle-wall contacts first (ids -1-face are the smallest) */
         for (int face = 5; face >= 0; --face) {
           int a = face / 2;
@@ -641,11 +746,21 @@ int or_dem_step(const or_config* c, const or_dem_params* p, int np, double* X,
           or_jkr_force(R[i], E, p->gamma, delta, &force, &dC);
           int id = -1 - face;
           if (delta >= 0.0 || (delta > -dC && in_list(prev, ncontact[i], id))) {
-            double nrm[3] = {0, 0, 0};
+            double nrm[3] = {0, 0, 0}, h[4] = {0, 0, 0, 0};
             nrm[a] = (face % 2 == 0) ? -1.0 : 1.0;
             double vrn = -(U[3 * i + 0] * nrm[0] + U[3 * i + 1] * nrm[1] + U[3 * i + 2] * nrm[2]);
             for (int b = 0; b < 3; ++b) fc[b] += (-force + p->eta_n * vrn) * nrm[b];
-            if (cnt < 512) list[cnt] = id;
+            if (fric) {
+              jkr_consts k = jkr_make(R[i], E, p->gamma);
+              double acon = or_jkr_x(delta / k.dC) * k.a0;
+              prev_springs(prev, ncontact[i], prev_h, id, h);
+              contact_friction(p, nrm, R[i], &U[3 * i], &W[3 * i], 0.0, zero, zero, force,
+                               k.FC, acon, dts, h, fc, tc);
+            }
+            if (cnt < 512) {
+              list[cnt] = id;
+              for (int b = 0; b < 4; ++b) hl[cnt][b] = h[b];
+            }
             ++cnt;
           }
         }
@@ -664,18 +779,34 @@ int or_dem_step(const or_config* c, const or_dem_params* p, int np, double* X,
           double force, dC;
           or_jkr_force(Reff, E, p->gamma, delta, &force, &dC);
           if (delta >= 0.0 || delta > -dC) {
-            double nrm[3], vrn = 0.0;
+            double nrm[3], vrn = 0.0, h[4] = {0, 0, 0, 0};
             for (int a = 0; a < 3; ++a) nrm[a] = dv[a] / dist;
             for (int a = 0; a < 3; ++a) vrn += (U[3 * j + a] - U[3 * i + a]) * nrm[a];
             for (int a = 0; a < 3; ++a) fc[a] += (-force + p->eta_n * vrn) * nrm[a];
-            if (cnt < 512) list[cnt] = j;
+            if (fric) {
+              jkr_consts k = jkr_make(Reff, E, p->gamma);
+              double acon = or_jkr_x(delta / k.dC) * k.a0;
+              prev_springs(prev, ncontact[i], prev_h, j, h);
+              contact_friction(p, nrm, R[i], &U[3 * i], &W[3 * i], R[j], &U[3 * j], &W[3 * j],
+                               force, k.FC, acon, dts, h, fc, tc);
+            }
+            if (cnt < 512) {
+              list[cnt] = j;
+              for (int b = 0; b < 4; ++b) hl[cnt][b] = h[b];
+            }
             ++cnt;
           }
         }
         if (cnt > cap) { rc = -1; break; }
         nn[i] = cnt;
-        for (int k = 0; k < cnt; ++k) nid[(size_t)i * cap + k] = list[k];
-        for (int a = 0; a < 3; ++a) Fc[3 * i + a] = fc[a];
+        for (int k = 0; k < cnt; ++k) {
+          nid[(size_t)i * cap + k] = list[k];
+          for (int b = 0; b < 4; ++b) nh[((size_t)i * cap + k) * 4 + b] = hl[k][b];
+        }
+        for (int a = 0; a < 3; ++a) {
+          Fc[3 * i + a] = fc[a];
+          Tc[3 * i + a] = tc[a];
+        }
       }
       if (rc) break;
       for (int i = 0; i < np; ++i) {
@@ -690,15 +821,20 @@ int or_dem_step(const or_config* c, const or_dem_params* p, int np, double* X,
           X[3 * i + a] += dts * U[3 * i + a];
         }
         if (two_d) {
-          W[3 * i + 2] += dts * Tf[3 * i + 2] / I;
+          W[3 * i + 2] += dts * (Tf[3 * i + 2] + Tc[3 * i + 2]) / I;
         } else {
-          for (int a = 0; a < 3; ++a) W[3 * i + a] += dts * Tf[3 * i + a] / I;
+          for (int a = 0; a < 3; ++a) W[3 * i + a] += dts * (Tf[3 * i + a] + Tc[3 * i + a]) / I;
         }
         ncontact[i] = nn[i];
-        for (int k = 0; k < nn[i]; ++k) contact_ids[(size_t)i * cap + k] = nid[(size_t)i * cap + k];
+        for (int k = 0; k < nn[i]; ++k) {
+          contact_ids[(size_t)i * cap + k] = nid[(size_t)i * cap + k];
+          if (hist)
+            for (int b = 0; b < 4; ++b)
+              hist[((size_t)i * cap + k) * 4 + b] = nh[((size_t)i * cap + k) * 4 + b];
+        }
       }
     }
-    free(Fc); free(nn); free(nid);
+    free(Fc); free(Tc); free(nn); free(nid); free(nh);
     if (rc) return rc;
   }
   /* wrap positions into [0, L) on periodic axes */

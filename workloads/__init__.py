@@ -110,6 +110,9 @@ class DemSpec:
     n_sub: int = 1
     kinematic: bool = False
     max_contacts: int = 16
+    k_t: float = 0.0       # tangential stiffness k_T (Eq. 28)
+    eta_t: float = 0.0     # tangential dissipation coefficient eta_T (Eq. 28)
+    mu_f: float = 0.0      # friction coefficient (Eq. 29); 0: no friction
 
 
 @dataclass
