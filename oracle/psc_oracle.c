@@ -613,6 +613,19 @@ static void prev_springs(const int* ids, int n, const double* hs, int id, double
   for (int b = 0; b < 4; ++b) h[b] = (k >= 0 && hs) ? hs[4 * k + b] : 0.0;
 }
 
+/* Velocity and spin of a body as friction sees them: a 2D disk moves in
+ * its plane and spins about z only. */
+static void planar(int two_d, const double* u, const double* w, double uo[3], double wo[3]) {
+  for (int b = 0; b < 3; ++b) {
+    uo[b] = u[b];
+    wo[b] = w[b];
+  }
+  if (two_d) {
+    uo[2] = 0.0;
+    wo[0] = wo[1] = 0.0;
+  }
+}
+
 static void cross(const double a[3], const double b[3], double out[3]) {
   out[0] = a[1] * b[2] - a[2] * b[1];
   out[1] = a[2] * b[0] - a[0] * b[2];
@@ -753,9 +766,11 @@ int or_dem_step(const or_config* c, const or_dem_params* p, int np, double* X,
             if (fric) {
               jkr_consts k = jkr_make(R[i], E, p->gamma);
               double acon = or_jkr_x(delta / k.dC) * k.a0;
+              double ui[3], wi[3];
+              planar(two_d, &U[3 * i], &W[3 * i], ui, wi);
               prev_springs(prev, ncontact[i], prev_h, id, h);
-              contact_friction(p, nrm, R[i], &U[3 * i], &W[3 * i], 0.0, zero, zero, force,
-                               k.FC, acon, dts, h, fc, tc);
+              contact_friction(p, nrm, R[i], ui, wi, 0.0, zero, zero, force, k.FC, acon, dts, h,
+                               fc, tc);
             }
             if (cnt < 512) {
               list[cnt] = id;
@@ -786,9 +801,12 @@ int or_dem_step(const or_config* c, const or_dem_params* p, int np, double* X,
             if (fric) {
               jkr_consts k = jkr_make(Reff, E, p->gamma);
               double acon = or_jkr_x(delta / k.dC) * k.a0;
+              double ui[3], wi[3], uj[3], wj[3];
+              planar(two_d, &U[3 * i], &W[3 * i], ui, wi);
+              planar(two_d, &U[3 * j], &W[3 * j], uj, wj);
               prev_springs(prev, ncontact[i], prev_h, j, h);
-              contact_friction(p, nrm, R[i], &U[3 * i], &W[3 * i], R[j], &U[3 * j], &W[3 * j],
-                               force, k.FC, acon, dts, h, fc, tc);
+              contact_friction(p, nrm, R[i], ui, wi, R[j], uj, wj, force, k.FC, acon, dts, h, fc,
+                               tc);
             }
             if (cnt < 512) {
               list[cnt] = j;
