@@ -115,6 +115,10 @@ typedef struct {
   double dt;                  /* coupling step (one LBM step) */
   int n_sub;                  /* DEM sub-cycles per coupling step (lambda), >= 1 */
   int kinematic;              /* nonzero: prescribed motion, x += dt u only */
+  double k_t;                 /* tangential stiffness k_T (Eq. 28), > 0 when mu_f > 0 */
+  double eta_t;               /* tangential dissipation coefficient eta_T (Eq. 28), >= 0 */
+  double mu_f;                /* friction coefficient (Eq. 29), >= 0; 0: no sliding or
+                                 twisting friction (zero-initialised callers get none) */
 } psclbm_dem_params;
 
 typedef struct psclbm_ctx psclbm_ctx;
@@ -191,15 +195,26 @@ int particle_forces(psclbm_ctx* ctx, double* d_force, double* d_torque);
  * hydrodynamic force d_force[3n] and torque d_torque[3n] held fixed (Sec. 2.5),
  * gravity (rho_p - rho_f) V g, and JKR normal contacts (Eqs. 25-27, with the
  * jump-on / pull-off hysteresis) between particles and with the walls of
- * non-periodic axes (flat walls at -1/2 and L-1/2).  Positions wrap into
- * [0, L) on periodic axes.  2D: disks of unit depth.  Contact history lives in
- * the workspace (dem_reset_contacts clears it).  d_force and d_torque may
+ * non-periodic axes (flat walls at -1/2 and L-1/2).  With mu_f > 0 every
+ * contact also carries sliding and twisting friction (Eqs. 22, 28, 29), each a
+ * linear spring-dashpot-slider: the tangential force k_T xi + eta_T v_t capped
+ * at mu_f |F_ne + 2 F_C| (F_ne the JKR elastic force), its torque r_i n x F
+ * about the centre, and the twisting moment (a^2/2)(k_T theta + eta_T Omega_t)
+ * capped at 3 pi a F_crit / 16 (a the JKR contact radius); v_t is the slip of
+ * the partner's surface point relative to the particle's, xi and theta the
+ * slip and twist integrated since the contact began, reset to the capped
+ * value while capped; walls are at rest, and a 2D disk moves in its plane
+ * and spins about z.  Positions wrap into [0, L) on periodic axes.  2D: disks
+ * of unit depth.  Contact history (ids, and with friction each contact's
+ * springs; a step without friction leaves every spring unloaded) lives in the
+ * workspace (dem_reset_contacts clears it).  d_force and d_torque may
  * both be NULL: the force and torque of the most recent lbm_step are then
  * read from the workspace (n must equal the rasterised count; ESTATE
  * otherwise).  The contact forces of a particle are summed in neighbour-bin
- * order.  Errors: EINVAL (bad params, n > max_particles, only one of the two
- * force pointers NULL, a contact reach delta_C of 1 or more), EHIP; sticky
- * ECONTACTS on contact or bin overflow. */
+ * order.  Errors: EINVAL (bad params, among them a negative or non-finite
+ * k_t, eta_t or mu_f, or k_t == 0 with mu_f > 0; n > max_particles, only one
+ * of the two force pointers NULL, a contact reach delta_C of 1 or more), EHIP;
+ * sticky ECONTACTS on contact or bin overflow. */
 int dem_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double* d_u,
              double* d_omega, const double* d_radius, int n, const double* d_force,
              const double* d_torque);
@@ -212,7 +227,8 @@ int dem_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double*
  * sums of contact forces.  With n_sub == 1 the work of consecutive steps is
  * fused: the DEM wave of a particle, having integrated it, writes its
  * snapshot and enters it in the tile lists and DEM bins of the next step, so
- * a step is two kernels (plus one at the start of the call).  Afterwards the
+ * a step is two kernels (plus one at the start of the call); with friction
+ * (mu_f > 0) the three calls are made in turn.  Afterwards the
  * context holds the last step's rasterisation and force / torque
  * accumulators, as after the three calls.  Errors: those of psc_rasterize,
  * lbm_step and dem_step (EINVAL, EHIP; sticky ESLOTS, ECONTACTS). */

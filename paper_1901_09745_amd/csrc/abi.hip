@@ -64,7 +64,7 @@ int validate(const psclbm_config* c) {
 
 struct Layout {
   size_t f, err, scalar, tile_count, tile_list, snap, facc0, facc1, mass_part, outlet_u, outlet_g;
-  size_t bin_count, bin_rec, cn0, cn1, cid0, cid1, fcont, total;
+  size_t bin_count, bin_rec, cn0, cn1, cid0, cid1, fcont, spr0, spr1, wsnap, total;
   int ntx, nty, ntz, ntiles;
   long long face_stride;
   int nbin[3];
@@ -129,6 +129,9 @@ Layout plan(const psclbm_config* c) {
   l.cid0 = take(sizeof(int) * (size_t)(np > 0 ? np : 1) * mc);
   l.cid1 = take(sizeof(int) * (size_t)(np > 0 ? np : 1) * mc);
   l.fcont = take(sizeof(double) * 3 * (size_t)(np > 0 ? np : 1));
+  l.spr0 = take(sizeof(double) * 4 * (size_t)(np > 0 ? np : 1) * mc);
+  l.spr1 = take(sizeof(double) * 4 * (size_t)(np > 0 ? np : 1) * mc);
+  l.wsnap = take(sizeof(double) * 3 * (size_t)(np > 0 ? np : 1));
   l.total = off;
   return l;
 }
@@ -230,6 +233,9 @@ int lbm_init(const psclbm_config* cfg, void* d_workspace, size_t bytes, void* hi
   c->contact_id[0] = reinterpret_cast<int*>(base + l.cid0);
   c->contact_id[1] = reinterpret_cast<int*>(base + l.cid1);
   c->fcontact = reinterpret_cast<double*>(base + l.fcont);
+  c->contact_springs[0] = reinterpret_cast<double*>(base + l.spr0);
+  c->contact_springs[1] = reinterpret_cast<double*>(base + l.spr1);
+  c->wsnap = reinterpret_cast<double*>(base + l.wsnap);
   // clear everything but the distributions, then set f = f^eq(rho0, 0)
   rc = launch_zero(c, base + l.err, l.total - l.err);
   if (!rc) rc = launch_init_equilibrium(c, nullptr, nullptr);
@@ -324,6 +330,17 @@ int particle_forces(psclbm_ctx* ctx, double* d_force, double* d_torque) {
   return rc;
 }
 
+// Material and friction parameters of a dynamic DEM step.
+static bool dem_material_ok(const psclbm_dem_params* p) {
+  if (!(p->rho_p > 0.0) || !(p->E_p > 0.0) || !(p->gamma >= 0.0) ||
+      !(p->poisson > -1.0 && p->poisson < 0.5) || !(p->eta_n >= 0.0))
+    return false;
+  if (!(p->k_t >= 0.0) || !(p->eta_t >= 0.0) || !(p->mu_f >= 0.0) || !std::isfinite(p->k_t) ||
+      !std::isfinite(p->eta_t) || !std::isfinite(p->mu_f))
+    return false;
+  return p->mu_f == 0.0 || p->k_t > 0.0;  // the slider divides by k_T
+}
+
 int dem_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double* d_u,
              double* d_omega, const double* d_radius, int n, const double* d_force,
              const double* d_torque) {
@@ -337,11 +354,7 @@ int dem_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double*
     if (!ctx->rasterized || n != ctx->np) return PSCLBM_ESTATE;
   }
   if (prm->n_sub < 1 || !(prm->dt > 0.0) || !std::isfinite(prm->dt)) return PSCLBM_EINVAL;
-  if (!prm->kinematic) {
-    if (!(prm->rho_p > 0.0) || !(prm->E_p > 0.0) || !(prm->gamma >= 0.0) ||
-        !(prm->poisson > -1.0 && prm->poisson < 0.5) || !(prm->eta_n >= 0.0))
-      return PSCLBM_EINVAL;
-  }
+  if (!prm->kinematic && !dem_material_ok(prm)) return PSCLBM_EINVAL;
   return launch_dem_step(ctx, prm, d_x, d_u, d_omega, d_radius, n, d_force, d_torque);
 }
 
@@ -351,11 +364,7 @@ int coupled_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, dou
   if (n < 0 || n > ctx->cfg.max_particles) return PSCLBM_EINVAL;
   if (n > 0 && (!d_x || !d_u || !d_omega || !d_radius)) return PSCLBM_EINVAL;
   if (prm->n_sub < 1 || !(prm->dt > 0.0) || !std::isfinite(prm->dt)) return PSCLBM_EINVAL;
-  if (!prm->kinematic) {
-    if (!(prm->rho_p > 0.0) || !(prm->E_p > 0.0) || !(prm->gamma >= 0.0) ||
-        !(prm->poisson > -1.0 && prm->poisson < 0.5) || !(prm->eta_n >= 0.0))
-      return PSCLBM_EINVAL;
-  }
+  if (!prm->kinematic && !dem_material_ok(prm)) return PSCLBM_EINVAL;
   const int rc = launch_coupled(ctx, prm, d_x, d_u, d_omega, d_radius, n, nsteps);
   if (rc) return rc;
   ctx->np = n;

@@ -214,6 +214,9 @@ struct psclbm_ctx {
   int* contact_id[2];
   int contact_cur;
   double* fcontact;  // [max_particles][3] contact forces of the coupled step
+  double* contact_springs[2];  // per contact list: [max_particles][max_contacts][4] friction springs
+  int springs_valid;           // the current list's springs were written (friction was on)
+  double* wsnap;               // [max_particles][3] spins at the start of a friction sub-step
   double* scalar;  // one FP64 device scalar for reductions
   // host-side state
   long long steps;

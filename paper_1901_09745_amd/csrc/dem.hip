@@ -1,6 +1,7 @@
 // Adhesive DEM step of the gfx950 PSC-LBM library (FP64), Sec. 2.5:
 // Newton-Euler motion (Eq. 21) with the JKR normal contact force (Eqs. 25-27)
-// including the jump-on / pull-off hysteresis, sub-cycled n_sub times per
+// including the jump-on / pull-off hysteresis and, optionally, the sliding
+// and twisting friction of Eqs. 22, 28, 29, sub-cycled n_sub times per
 // coupling step with the hydrodynamic force and torque held fixed.
 //
 // Per sub-step, two kernels: (1) bin the particles into a uniform grid whose
@@ -10,7 +11,9 @@
 // walls (so that no particle sees another's update), records the new contact
 // list, sums the forces over the wave and integrates the particle with
 // semi-implicit Euler.  The bin counts and records are triple buffered: each
-// binning fills one set and clears the set the binning after it fills.
+// binning fills one set and clears the set the binning after it fills.  With
+// friction the binning also copies the spins, which the contacts read, and
+// each contact's springs travel with the contact lists.
 //
 // The coupled step (n_sub = 1) gathers the contacts in leading workgroups of
 // the step kernel instead, which run beside the tiles (contacts need only
@@ -29,13 +32,17 @@ namespace psclbm {
 
 
 // One thread per particle: its bin in the target set and its image; the
-// grid also clears the set the binning after next fills.
+// grid also clears the set the binning after next fills.  wsnap (friction
+// only): a copy of the spins at the start of the sub-step.
 __global__ void k_dem_bin(DemBinOut b, Geom g, int n, int three_d, const double* x,
-                          const double* u, const double* r, unsigned* err) {
+                          const double* u, const double* r, unsigned* err, const double* w,
+                          double* wsnap) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   for (long long k = i; k < b.nbins; k += (long long)gridDim.x * blockDim.x) b.stale[k] = 0;
   if (i >= n) return;
   dem_bin_insert(b, three_d, g, i, x + 3 * i, u + 3 * i, r[i], err);
+  if (wsnap)
+    for (int a = 0; a < 3; ++a) wsnap[3 * i + a] = w[3 * i + a];
 }
 
 struct IntArgs {
@@ -49,12 +56,13 @@ struct IntArgs {
   int fstride, tstride;  // element strides of the force / torque rows
 };
 
-// Semi-implicit Euler (Eq. 21) with hydrodynamic force F, torque T and
-// contact force fc: u += dt (F + fc + G)/m, x += dt u, omega += dt T/I, then
-// the wrap into [0, L) on periodic axes (kinematic: x += dt u only).
+// Semi-implicit Euler (Eq. 21) with hydrodynamic force F, torque T, contact
+// force fc and contact torque tc (null: none): u += dt (F + fc + G)/m,
+// x += dt u, omega += dt (T + tc)/I, then the wrap into [0, L) on periodic
+// axes (kinematic: x += dt u only).
 __device__ inline void integrate_state(const IntArgs& p, double ri, const double* F,
-                                       const double* T, const double* fc, double* x, double* u,
-                                       double* w) {
+                                       const double* T, const double* fc, const double* tc,
+                                       double* x, double* u, double* w) {
   const int D = p.three_d ? 3 : 2;
   if (!p.kinematic) {
     const double V = p.three_d ? (4.0 / 3.0) * M_PI * ri * ri * ri : M_PI * ri * ri;
@@ -66,9 +74,9 @@ __device__ inline void integrate_state(const IntArgs& p, double ri, const double
       x[a] += p.dt * u[a];
     }
     if (p.three_d) {
-      for (int a = 0; a < 3; ++a) w[a] += p.dt * T[a] / I;
+      for (int a = 0; a < 3; ++a) w[a] += p.dt * (tc ? T[a] + tc[a] : T[a]) / I;
     } else {
-      w[2] += p.dt * T[2] / I;
+      w[2] += p.dt * (tc ? T[2] + tc[2] : T[2]) / I;
     }
   } else {
     for (int a = 0; a < D; ++a) x[a] += p.dt * u[a];
@@ -102,13 +110,16 @@ struct NextOut {
 
 // One wave per particle.  Unless fc_in holds them (the contact forces the
 // coupled step kernel gathered), the contacts are gathered here
-// (dem_contact_wave).  Every lane then integrates the particle (the same
-// values), lane 0 stores it, and with nx.build the wave rasterises it for
-// the next coupled step.  Kinematic particles skip the contacts.
-__global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, IntArgs ia, NextOut nx,
-                                                      double* x, double* u, double* w,
-                                                      const double* r, const double* Ff,
-                                                      const double* Tf, const double* fc_in) {
+// (dem_contact_wave, with friction when FRIC).  Every lane then integrates
+// the particle (the same values), lane 0 stores it, and with nx.build the
+// wave rasterises it for the next coupled step.  Kinematic particles skip
+// the contacts.
+template <bool FRIC>
+__global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, FricArgs fr, IntArgs ia,
+                                                      NextOut nx, double* x, double* u,
+                                                      double* w, const double* r,
+                                                      const double* Ff, const double* Tf,
+                                                      const double* fc_in) {
   const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (nx.build) {
     for (long long k = gid; k < nx.ntiles; k += (long long)gridDim.x * blockDim.x)
@@ -136,14 +147,17 @@ __global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, IntArgs ia, Nex
     ws[a] = w[3 * i + a];
   }
   double fsum[3] = {0.0, 0.0, 0.0};
-  if (fc_in) {  // contacts gathered by the step kernel's contact workgroups
+  double tsum[3] = {0.0, 0.0, 0.0};
+  if constexpr (FRIC) {
+    dem_contact_wave<true>(d, i, lane, xs, us, ri, fsum, &fr, ws, tsum);
+  } else if (fc_in) {  // contacts gathered by the step kernel's contact workgroups
 #pragma unroll
     for (int a = 0; a < 3; ++a) fsum[a] = fc_in[3 * i + a];
   } else if (!ia.kinematic) {
     dem_contact_wave(d, i, lane, xs, us, ri, fsum);
   }
-  integrate_state(ia, ri, Ff + (size_t)ia.fstride * i, Tf + (size_t)ia.tstride * i, fsum, xs, us,
-                  ws);
+  integrate_state(ia, ri, Ff + (size_t)ia.fstride * i, Tf + (size_t)ia.tstride * i, fsum,
+                  FRIC ? tsum : nullptr, xs, us, ws);
   if (lane == 0) {
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -169,8 +183,8 @@ __global__ void k_dem_advect(IntArgs p, double* x, double* u, double* w, const d
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= p.n) return;
   const double z[3] = {0.0, 0.0, 0.0};
-  integrate_state(p, r[i], Ff + (size_t)p.fstride * i, Tf + (size_t)p.tstride * i, z, x + 3 * i,
-                  u + 3 * i, w + 3 * i);
+  integrate_state(p, r[i], Ff + (size_t)p.fstride * i, Tf + (size_t)p.tstride * i, z, nullptr,
+                  x + 3 * i, u + 3 * i, w + 3 * i);
 }
 
 int launch_dem_reset(psclbm_ctx* c) {
@@ -262,19 +276,36 @@ int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doub
   if (!(E > 0.0)) return PSCLBM_EINVAL;
   NextOut nx;
   std::memset(&nx, 0, sizeof(nx));
+  const bool fric = prm->mu_f > 0.0;
+  FricArgs fr;
+  std::memset(&fr, 0, sizeof(fr));
+  fr.w = c->wsnap;
+  fr.k_t = prm->k_t;
+  fr.eta_t = prm->eta_t;
+  fr.mu_f = prm->mu_f;
+  fr.dts = prm->dt / prm->n_sub;
   for (int s = 0; s < prm->n_sub; ++s) {
     ia.wrap = s == prm->n_sub - 1;  // positions wrap once, after the last sub-step
     const DemBinOut b = dem_bin_out(c, true);
     const long long bth = b.nbins > n ? b.nbins : n;
-    k_dem_bin<<<(unsigned)((bth + 127) / 128), 128, 0, c->stream>>>(b, c->geom, n,
-                                                                   c->geom.q == 19, x, u, r,
-                                                                   c->err);
+    k_dem_bin<<<(unsigned)((bth + 127) / 128), 128, 0, c->stream>>>(
+        b, c->geom, n, c->geom.q == 19, x, u, r, c->err, w, fric ? c->wsnap : nullptr);
     dem_bins_advance(c);
     const DemArgs d = dem_args(c, prm, n, E);
-    k_dem_contacts<<<(n + 3) / 4, 256, 0, c->stream>>>(d, ia, nx, x, u, w, r, F, T, nullptr);
+    if (fric) {
+      // springs of the previous lists only if they were kept (friction on)
+      fr.prev_h = c->springs_valid ? c->contact_springs[c->contact_cur] : nullptr;
+      fr.next_h = c->contact_springs[c->contact_cur ^ 1];
+      k_dem_contacts<true><<<(n + 3) / 4, 256, 0, c->stream>>>(d, fr, ia, nx, x, u, w, r, F, T,
+                                                              nullptr);
+    } else {
+      k_dem_contacts<false><<<(n + 3) / 4, 256, 0, c->stream>>>(d, fr, ia, nx, x, u, w, r, F,
+                                                               T, nullptr);
+    }
     int rc = hip_ok(hipGetLastError());
     if (rc) return rc;
     c->contact_cur ^= 1;
+    c->springs_valid = fric ? 1 : 0;
   }
   return PSCLBM_OK;
 }
@@ -293,8 +324,8 @@ int launch_coupled(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doubl
     E = dem_modulus(c, prm);
     if (!(E > 0.0)) return PSCLBM_EINVAL;
   }
-  if (prm->n_sub != 1 || n == 0) {
-    // sub-cycled DEM: the three calls in turn
+  if (prm->n_sub != 1 || n == 0 || (!prm->kinematic && prm->mu_f > 0.0)) {
+    // sub-cycled DEM or friction: the three calls in turn
     for (int t = 0; t < nsteps; ++t) {
       int rc = launch_rasterize(c, p, false);
       if (!rc) c->np = n;
@@ -332,11 +363,16 @@ int launch_coupled(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doubl
     nx.cap = c->cfg.max_tile_particles;
     nx.db = dem_bin_out(c, build && !prm->kinematic);
     nx.err = c->err;
-    k_dem_contacts<<<(n + 3) / 4, 256, 0, c->stream>>>(d, ia, nx, x, u, w, r, F, T,
-                                                      prm->kinematic ? nullptr : c->fcontact);
+    FricArgs fr;
+    std::memset(&fr, 0, sizeof(fr));
+    k_dem_contacts<false><<<(n + 3) / 4, 256, 0, c->stream>>>(
+        d, fr, ia, nx, x, u, w, r, F, T, prm->kinematic ? nullptr : c->fcontact);
     rc = hip_ok(hipGetLastError());
     if (rc) return rc;
-    if (!prm->kinematic) c->contact_cur ^= 1;
+    if (!prm->kinematic) {
+      c->contact_cur ^= 1;
+      c->springs_valid = 0;
+    }
     if (build) {
       c->tile_cur ^= 1;
       c->tile_count = c->tile_count_buf[c->tile_cur];

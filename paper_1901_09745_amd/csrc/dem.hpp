@@ -1,7 +1,8 @@
 // DEM contact gather of the gfx950 PSC-LBM library (FP64), Sec. 2.5: the
-// JKR normal force (Eqs. 25-27) with the jump-on / pull-off hysteresis,
-// gathered by one wave per particle from the DEM bins.  Used by the DEM
-// kernel and by the contact workgroups of the coupled step kernel.
+// JKR normal force (Eqs. 25-27) with the jump-on / pull-off hysteresis, and
+// optionally the sliding and twisting friction of Eqs. 22, 28, 29, gathered
+// by one wave per particle from the DEM bins.  Used by the DEM kernel and
+// (without friction) by the contact workgroups of the coupled step kernel.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -26,8 +27,10 @@ __device__ inline double min_img(double d, int periodic, int L) {
 // F_C = 3 pi gamma R, a0^3 = 9 pi gamma R^2 / E, delta_C = a0^2/(2 6^{1/3} R).
 // Solved for s = x^{1/2} by Newton from above (g(s) = 2 s^4 - 4/3 s is convex
 // and increasing on the branch s >= 6^{-1/3}, so the iterates decrease
-// monotonically to the root).  Returns the repulsive-positive force.
-__device__ inline double jkr_force(double R, double E, double gamma, double delta, double* dC) {
+// monotonically to the root).  Returns the repulsive-positive force, and the
+// contact radius a = x a0 in *a_out when that is given.
+__device__ inline double jkr_force(double R, double E, double gamma, double delta, double* dC,
+                                   double* a_out = nullptr) {
   const double c6 = 1.8171205928321397;  // 6^{1/3}
   const double FC = 3.0 * M_PI * gamma * R;
   const double a0 = cbrt(9.0 * M_PI * gamma * R * R / E);
@@ -51,7 +54,77 @@ __device__ inline double jkr_force(double R, double E, double gamma, double delt
     }
   }
   const double x = s * s;
+  if (a_out) *a_out = x * a0;
   return 4.0 * FC * (x * x * x - x * s);
+}
+
+// Friction arguments of the standalone DEM kernel: each contact's springs
+// (tangential displacement xi[3], twist angle theta) sit beside its id in the
+// contact lists, [particle][max_contacts][4].
+struct FricArgs {
+  const double* w;       // [n][3] spins at the start of the sub-step
+  const double* prev_h;  // springs of the previous lists; null: every contact starts unloaded
+  double* next_h;        // springs of the lists being built
+  double k_t, eta_t, mu_f;
+  double dts;            // sub-step
+};
+
+// Sliding and twisting friction on body i from one contact (Eqs. 22, 28, 29),
+// each a linear spring-dashpot-slider.  n: unit normal from i to its partner;
+// vr: velocity of the partner's surface point relative to i's at the contact;
+// om: the partner's spin minus i's, along n; Fne: the JKR elastic force
+// (repulsive positive); FC = 3 pi gamma R; a: the contact radius.  h holds
+// the springs of the previous sub-step and receives the new ones; the force
+// on i is added to f and its torque about i's centre to t.  The stored
+// displacement is first turned into the current tangent plane, then the
+// sub-step's slip is added; a force beyond F_crit = mu_f |F_ne + 2 F_C| (a
+// moment beyond 3 pi a F_crit / 16) is capped, the spring reset to the
+// stretch that gives the capped value.
+__device__ inline void contact_friction(const FricArgs& fr, double n0, double n1, double n2,
+                                        double ri, double vr0, double vr1, double vr2, double om,
+                                        double Fne, double FC, double a, double h[4], double f[3],
+                                        double t[3]) {
+  const double vn = vr0 * n0 + vr1 * n1 + vr2 * n2;
+  const double vt0 = vr0 - vn * n0, vt1 = vr1 - vn * n1, vt2 = vr2 - vn * n2;
+  const double hn = h[0] * n0 + h[1] * n1 + h[2] * n2;
+  double x0 = h[0] - hn * n0 + fr.dts * vt0;
+  double x1 = h[1] - hn * n1 + fr.dts * vt1;
+  double x2 = h[2] - hn * n2 + fr.dts * vt2;
+  double F0 = fr.k_t * x0 + fr.eta_t * vt0;
+  double F1 = fr.k_t * x1 + fr.eta_t * vt1;
+  double F2 = fr.k_t * x2 + fr.eta_t * vt2;
+  const double Fcrit = fr.mu_f * fabs(Fne + 2.0 * FC);
+  const double Fm = sqrt(F0 * F0 + F1 * F1 + F2 * F2);
+  if (Fm > Fcrit) {
+    const double sc = Fcrit / Fm;
+    F0 *= sc;
+    F1 *= sc;
+    F2 *= sc;
+    x0 = (F0 - fr.eta_t * vt0) / fr.k_t;
+    x1 = (F1 - fr.eta_t * vt1) / fr.k_t;
+    x2 = (F2 - fr.eta_t * vt2) / fr.k_t;
+  }
+  f[0] += F0;
+  f[1] += F1;
+  f[2] += F2;
+  t[0] += ri * (n1 * F2 - n2 * F1);  // (r_i n) x F
+  t[1] += ri * (n2 * F0 - n0 * F2);
+  t[2] += ri * (n0 * F1 - n1 * F0);
+  const double kr = 0.5 * fr.k_t * a * a, er = 0.5 * fr.eta_t * a * a;
+  double th = h[3] + fr.dts * om;
+  double M = kr * th + er * om;
+  const double Mcrit = 3.0 * M_PI * a * Fcrit / 16.0;
+  if (fabs(M) > Mcrit) {
+    M = copysign(Mcrit, M);
+    th = (M - er * om) / kr;
+  }
+  t[0] += M * n0;
+  t[1] += M * n1;
+  t[2] += M * n2;
+  h[0] = x0;
+  h[1] = x1;
+  h[2] = x2;
+  h[3] = th;
 }
 
 __device__ inline int bin_coord(double x, int a, const DemArgs& d) {
@@ -79,14 +152,6 @@ __device__ inline AxisNb axis_nb(int b, int a, const DemArgs& d) {
   return r;
 }
 
-// Contact force on particle i (position xs, velocity us, radius ri at the
-// start of the sub-step), gathered by the 64 lanes of one wave: the lanes
-// stride over the walls of the non-periodic axes and the (neighbour bin,
-// slot) candidates, whose positions and velocities are the binning's records
-// (so no particle sees another's update).  Contacts are compacted into the
-// new contact list (d.next_id / d.next_n) with a ballot, and every lane
-// returns the force summed over the wave in fsum.  Every lane of the wave
-// must be active.
 __device__ __forceinline__ double wave_uniform(double v) {
   const int lo = __builtin_amdgcn_readfirstlane(__double2loint(v));
   const int hi = __builtin_amdgcn_readfirstlane(__double2hiint(v));
@@ -101,8 +166,22 @@ __device__ inline AxisNb wave_uniform(AxisNb a) {
   return a;
 }
 
+// Contact force on particle i (position xs, velocity us, radius ri at the
+// start of the sub-step), gathered by the 64 lanes of one wave: the lanes
+// stride over the walls of the non-periodic axes and the (neighbour bin,
+// slot) candidates, whose positions and velocities are the binning's records
+// (so no particle sees another's update).  Contacts are compacted into the
+// new contact list (d.next_id / d.next_n) with a ballot, and every lane
+// returns the force summed over the wave in fsum.  With FRIC, each contact
+// also carries the friction of contact_friction (walls at rest; the spins
+// are ws for i and fr->w for the partners, a 2D disk spinning about z only):
+// its springs go beside its id into fr->next_h and the torque summed over the
+// wave is returned in tsum.  Every lane of the wave must be active.
+template <bool FRIC = false>
 __device__ inline void dem_contact_wave(const DemArgs& d, int i, int lane, const double* xs,
-                                        const double* us, double r_i, double* fsum) {
+                                        const double* us, double r_i, double* fsum,
+                                        const FricArgs* fr = nullptr, const double* ws = nullptr,
+                                        double* tsum = nullptr) {
   const int D = d.three_d ? 3 : 2;
   // the particle's own values are the same in every lane (scalar registers)
   const double ri = wave_uniform(r_i);
@@ -110,6 +189,14 @@ __device__ inline void dem_contact_wave(const DemArgs& d, int i, int lane, const
   const double xi2 = d.three_d ? wave_uniform(xs[2]) : 0.0;
   const double ui0 = wave_uniform(us[0]), ui1 = wave_uniform(us[1]);
   const double ui2 = d.three_d ? wave_uniform(us[2]) : 0.0;
+  double wi0 = 0.0, wi1 = 0.0, wi2 = 0.0;
+  if constexpr (FRIC) {
+    wi2 = wave_uniform(ws[2]);
+    if (d.three_d) {
+      wi0 = wave_uniform(ws[0]);
+      wi1 = wave_uniform(ws[1]);
+    }
+  }
   // the previous contact list, one entry per lane (max_contacts <= 64)
   const int pn = __builtin_amdgcn_readfirstlane(d.prev_n[i]);
   const int pid = lane < d.max_contacts ? d.prev_id[(size_t)i * d.max_contacts + lane] : 0;
@@ -118,8 +205,38 @@ __device__ inline void dem_contact_wave(const DemArgs& d, int i, int lane, const
     for (int k = 0; k < pn; ++k) hit |= __builtin_amdgcn_readlane(pid, k) == id;
     return hit;
   };
+  // with friction: the position of id in the previous list, or -1
+  auto prev_slot = [&](int id) {
+    int at = -1;
+    for (int k = 0; k < pn; ++k)
+      if (__builtin_amdgcn_readlane(pid, k) == id) at = k;
+    return at;
+  };
+  // the springs of previous-list entry k (zero for a new contact)
+  auto load_springs = [&](int k, double h[4]) {
+    if (k >= 0 && fr->prev_h) {
+      const double* hp = fr->prev_h + ((size_t)i * d.max_contacts + k) * 4;
+      for (int b = 0; b < 4; ++b) h[b] = hp[b];
+    } else {
+      for (int b = 0; b < 4; ++b) h[b] = 0.0;
+    }
+  };
   int* next = d.next_id + (size_t)i * d.max_contacts;
   double fs0 = 0.0, fs1 = 0.0, fs2 = 0.0;
+  double tq[3] = {0.0, 0.0, 0.0};
+  double h[4] = {0.0, 0.0, 0.0, 0.0};
+  auto store = [&](bool have, int id, unsigned long long m, int cnt) {
+    if (have) {
+      const int pos = cnt + lanes_below(m);
+      if (pos < d.max_contacts) {
+        next[pos] = id;
+        if constexpr (FRIC) {
+          double* hn = fr->next_h + ((size_t)i * d.max_contacts + pos) * 4;
+          for (int b = 0; b < 4; ++b) hn[b] = h[b];
+        }
+      }
+    }
+  };
   int cnt = 0;  // uniform over the wave
 
   // walls of non-periodic axes: flat bodies at -1/2 and L-1/2 (1/R = 1/r)
@@ -134,26 +251,47 @@ __device__ inline void dem_contact_wave(const DemArgs& d, int i, int lane, const
         const double dist = (face % 2 == 0) ? xa + 0.5 : (d.L[a] - 0.5) - xa;
         const double delta = ri - dist;
         id = -1 - face;
-        if (delta >= 0.0 || was_in_contact(id)) {
+        int kp = -1;
+        bool touch;
+        if constexpr (FRIC) {
+          kp = prev_slot(id);
+          touch = delta >= 0.0 || kp >= 0;
+        } else {
+          touch = delta >= 0.0 || was_in_contact(id);
+        }
+        if (touch) {
           const double sgn = (face % 2 == 0) ? -1.0 : 1.0;  // normal towards the wall
           const double damp = d.eta_n * (-ua * sgn);
-          double dC;
-          const double F = jkr_force(ri, d.E, d.gamma, delta, &dC);
+          double dC, acon;
+          const double F = jkr_force(ri, d.E, d.gamma, delta, &dC, FRIC ? &acon : nullptr);
           if (delta >= 0.0 || delta > -dC) {
             const double fm = (-F + damp) * sgn;
             if (a == 0) fs0 += fm;
             else if (a == 1) fs1 += fm;
             else fs2 += fm;
             have = true;
+            if constexpr (FRIC) {
+              const double n0 = a == 0 ? sgn : 0.0, n1 = a == 1 ? sgn : 0.0,
+                           n2 = a == 2 ? sgn : 0.0;
+              // the wall is at rest: vr = -(u_i + omega_i x (r_i n))
+              const double vr0 = -(ui0 + ri * (wi1 * n2 - wi2 * n1));
+              const double vr1 = -(ui1 + ri * (wi2 * n0 - wi0 * n2));
+              const double vr2 = -(ui2 + ri * (wi0 * n1 - wi1 * n0));
+              const double om = -(wi0 * n0 + wi1 * n1 + wi2 * n2);
+              double f[3] = {0.0, 0.0, 0.0};
+              load_springs(kp, h);
+              contact_friction(*fr, n0, n1, n2, ri, vr0, vr1, vr2, om, F,
+                               3.0 * M_PI * d.gamma * ri, acon, h, f, tq);
+              fs0 += f[0];
+              fs1 += f[1];
+              fs2 += f[2];
+            }
           }
         }
       }
     }
     const unsigned long long m = __ballot(have);
-    if (have) {
-      const int pos = cnt + lanes_below(m);
-      if (pos < d.max_contacts) next[pos] = id;
-    }
+    store(have, id, m, cnt);
     cnt += __popcll(m);
   }
 
@@ -189,7 +327,15 @@ __device__ inline void dem_contact_wave(const DemArgs& d, int i, int lane, const
         const double dist = sqrt(dv0 * dv0 + dv1 * dv1 + dv2 * dv2);
         const double rj = rc[6];
         const double delta = ri + rj - dist;
-        if (delta >= 0.0 || was_in_contact(j)) {
+        int kp = -1;
+        bool touch;
+        if constexpr (FRIC) {
+          kp = prev_slot(j);
+          touch = delta >= 0.0 || kp >= 0;
+        } else {
+          touch = delta >= 0.0 || was_in_contact(j);
+        }
+        if (touch) {
           // normal and normal relative velocity first: only they (and the
           // force sums) stay live across the JKR solve
           const double inv = 1.0 / dist;
@@ -198,8 +344,8 @@ __device__ inline void dem_contact_wave(const DemArgs& d, int i, int lane, const
           if (d.three_d) vrn += (rc[5] - ui2) * n2;
           const double damp = d.eta_n * vrn;
           const double Reff = 1.0 / (1.0 / ri + 1.0 / rj);
-          double dC;
-          const double F = jkr_force(Reff, d.E, d.gamma, delta, &dC);
+          double dC, acon;
+          const double F = jkr_force(Reff, d.E, d.gamma, delta, &dC, FRIC ? &acon : nullptr);
           if (delta >= 0.0 || delta > -dC) {
             const double fm = -F + damp;
             fs0 += fm * n0;
@@ -207,20 +353,43 @@ __device__ inline void dem_contact_wave(const DemArgs& d, int i, int lane, const
             fs2 += fm * n2;
             have = true;
             id = j;
+            if constexpr (FRIC) {
+              const double uj2 = d.three_d ? rc[5] : 0.0;
+              const double wj2 = fr->w[3 * j + 2];
+              const double wj0 = d.three_d ? fr->w[3 * j] : 0.0;
+              const double wj1 = d.three_d ? fr->w[3 * j + 1] : 0.0;
+              // (u_j + omega_j x (-r_j n)) - (u_i + omega_i x (r_i n))
+              const double vr0 = (rc[3] - ui0) - rj * (wj1 * n2 - wj2 * n1) -
+                                 ri * (wi1 * n2 - wi2 * n1);
+              const double vr1 = (rc[4] - ui1) - rj * (wj2 * n0 - wj0 * n2) -
+                                 ri * (wi2 * n0 - wi0 * n2);
+              const double vr2 = (uj2 - ui2) - rj * (wj0 * n1 - wj1 * n0) -
+                                 ri * (wi0 * n1 - wi1 * n0);
+              const double om = (wj0 - wi0) * n0 + (wj1 - wi1) * n1 + (wj2 - wi2) * n2;
+              double f[3] = {0.0, 0.0, 0.0};
+              load_springs(kp, h);
+              contact_friction(*fr, n0, n1, n2, ri, vr0, vr1, vr2, om, F,
+                               3.0 * M_PI * d.gamma * Reff, acon, h, f, tq);
+              fs0 += f[0];
+              fs1 += f[1];
+              fs2 += f[2];
+            }
           }
         }
       }
     }
     const unsigned long long m = __ballot(have);
-    if (have) {
-      const int pos = cnt + lanes_below(m);
-      if (pos < d.max_contacts) next[pos] = id;
-    }
+    store(have, id, m, cnt);
     cnt += __popcll(m);
   }
   fsum[0] = wave_sum(fs0);
   fsum[1] = wave_sum(fs1);
   fsum[2] = wave_sum(fs2);
+  if constexpr (FRIC) {
+    tsum[0] = wave_sum(tq[0]);
+    tsum[1] = wave_sum(tq[1]);
+    tsum[2] = wave_sum(tq[2]);
+  }
   if (lane == 0) {
     if (cnt > d.max_contacts) {
       atomicOr(d.err, ERR_CONTACTS);

@@ -55,7 +55,9 @@ class DemParams(ctypes.Structure):
                 ("E_p", ctypes.c_double), ("poisson", ctypes.c_double),
                 ("gamma", ctypes.c_double), ("eta_n", ctypes.c_double),
                 ("g", ctypes.c_double * 3), ("dt", ctypes.c_double),
-                ("n_sub", ctypes.c_int), ("kinematic", ctypes.c_int)]
+                ("n_sub", ctypes.c_int), ("kinematic", ctypes.c_int),
+                ("k_t", ctypes.c_double), ("eta_t", ctypes.c_double),
+                ("mu_f", ctypes.c_double)]
 
 
 # Every symbol the header declares, with its ctypes signature.
@@ -274,6 +276,7 @@ def make_dem_params(d) -> DemParams:
     for a in range(3):
         p.g[a] = d.g[a]
     p.dt, p.n_sub, p.kinematic = d.dt, d.n_sub, int(d.kinematic)
+    p.k_t, p.eta_t, p.mu_f = d.k_t, d.eta_t, d.mu_f
     return p
 
 
