@@ -54,7 +54,7 @@ class _Dem(ctypes.Structure):
                 ("g", ctypes.c_double * 3), ("dt", ctypes.c_double),
                 ("n_sub", ctypes.c_int), ("kinematic", ctypes.c_int),
                 ("k_t", ctypes.c_double), ("eta_t", ctypes.c_double),
-                ("mu_f", ctypes.c_double)]
+                ("mu_f", ctypes.c_double), ("theta_r", ctypes.c_double)]
 
 
 _lib_handle = None
@@ -290,7 +290,7 @@ def make_dem(d) -> _Dem:
     for a in range(3):
         p.g[a] = d.g[a]
     p.dt, p.n_sub, p.kinematic = d.dt, d.n_sub, int(d.kinematic)
-    p.k_t, p.eta_t, p.mu_f = d.k_t, d.eta_t, d.mu_f
+    p.k_t, p.eta_t, p.mu_f, p.theta_r = d.k_t, d.eta_t, d.mu_f, d.theta_r
     return p
 
 
@@ -303,8 +303,9 @@ class Dem:
         self.cap = dem.max_contacts
         self.ncontact = np.zeros(max(n, 1), dtype=np.int32)
         self.ids = np.zeros(max(n, 1) * self.cap, dtype=np.int32)
-        # each contact's springs (tangential displacement xi[3], twist angle)
-        self.hist = np.zeros(max(n, 1) * self.cap * 4)
+        # each contact's springs (tangential displacement xi[3], twist angle,
+        # rolling displacement xr[3], unused)
+        self.hist = np.zeros(max(n, 1) * self.cap * 8)
 
     def step(self, p, F: np.ndarray, T: np.ndarray) -> None:
         """Advance p in place by one coupling step with fluid force F, torque T."""
@@ -321,9 +322,9 @@ class Dem:
                 for i in range(self.ncontact.size)]
 
     def springs(self, i: int) -> dict:
-        """{contact id: (xi[3], theta)} of particle i's contacts."""
+        """{contact id: (xi[3], theta, xr[3])} of particle i's contacts."""
         out = {}
         for k in range(self.ncontact[i]):
-            h = self.hist[(i * self.cap + k) * 4:(i * self.cap + k + 1) * 4]
-            out[int(self.ids[i * self.cap + k])] = (h[:3].copy(), float(h[3]))
+            h = self.hist[(i * self.cap + k) * 8:(i * self.cap + k + 1) * 8]
+            out[int(self.ids[i * self.cap + k])] = (h[:3].copy(), float(h[3]), h[4:7].copy())
         return out

@@ -25,8 +25,9 @@
  *   Sec. 2.1 Eqs. 1-5 (BGK + Guo forcing), Sec. 2.2 Eq. 6 (bounce-back),
  *   Sec. 2.3 Eqs. 10, 12-14 (modified PSC collision and per-particle forces),
  *   Sec. 2.4 Eqs. 15-19 and Table 1 (linear solid fraction),
- *   Sec. 2.5 Eqs. 21, 25-27 (Newton-Euler motion with the JKR normal force)
- *   and Eqs. 22, 28, 29 (sliding and twisting friction, optional).
+ *   Sec. 2.5 Eqs. 21, 25-27 (Newton-Euler motion with the JKR normal force,
+ *   or Hertz's without adhesion) and Eqs. 22, 28, 29 (sliding, twisting and
+ *   rolling friction, optional).
  * Readings of points the paper leaves open are marked "Reading:".
  */
 #include <math.h>
@@ -86,6 +87,7 @@ typedef struct {
   double k_t;          /* tangential stiffness k_T (Eq. 28) */
   double eta_t;        /* tangential dissipation coefficient eta_T (Eq. 28) */
   double mu_f;         /* friction coefficient (Eq. 29); 0: no sliding or twisting friction */
+  double theta_r;      /* critical rolling angle theta_crit (Eq. 29); 0: no rolling resistance */
 } or_dem_params;
 
 int or_version(void) { return 1; }
@@ -588,14 +590,34 @@ static double eff_modulus(const or_dem_params* p) {
   return 1.0 / (2.0 * (1.0 - p->poisson * p->poisson) / p->E_p);
 }
 
-/* JKR normal force magnitude (repulsive positive, Eq. 26 without damping)
- * and delta_C for a contact of effective radius R at overlap delta. */
+/* Elastic normal contact of effective radius R at overlap delta: the force
+ * (repulsive positive, Eq. 26 without damping), delta_C, and the contact
+ * radius a with x = a / a0.  Without adhesion (gamma == 0) JKR reduces to
+ * Hertz: F = (4/3) E sqrt(R) delta^{3/2} and a = sqrt(R delta) for
+ * delta >= 0, nothing below, delta_C = 0 and x = 0. */
+static void normal_contact(double R, double E, double gamma, double delta, double* force,
+                           double* dC, double* a, double* x) {
+  if (gamma == 0.0) {
+    double d = delta > 0.0 ? delta : 0.0;
+    *force = 4.0 / 3.0 * E * sqrt(R) * d * sqrt(d);
+    *dC = 0.0;
+    *a = sqrt(R * d);
+    *x = 0.0;
+    return;
+  }
+  jkr_consts k = jkr_make(R, E, gamma);
+  double xx = or_jkr_x(delta / k.dC);
+  *force = 4.0 * k.FC * (xx * xx * xx - pow(xx, 1.5));
+  *dC = k.dC;
+  *a = xx * k.a0;
+  *x = xx;
+}
+
+/* Elastic normal force and delta_C of a contact (normal_contact). */
 void or_jkr_force(double R, double E, double gamma, double delta,
                   double* force, double* dC) {
-  jkr_consts k = jkr_make(R, E, gamma);
-  double x = or_jkr_x(delta / k.dC);
-  *force = 4.0 * k.FC * (x * x * x - pow(x, 1.5));
-  *dC = k.dC;
+  double a, x;
+  normal_contact(R, E, gamma, delta, force, dC, &a, &x);
 }
 
 /* Position of id in a contact list of n entries, or -1. */
@@ -606,11 +628,11 @@ static int list_index(const int* ids, int n, int id) {
 
 static int in_list(const int* ids, int n, int id) { return list_index(ids, n, id) >= 0; }
 
-/* The springs (xi[3], theta) that contact id carried in the previous list
- * (ids[n], springs hs[4n]), or zero for a new contact. */
-static void prev_springs(const int* ids, int n, const double* hs, int id, double h[4]) {
+/* The springs (xi[3], theta, xr[3], unused) that contact id carried in the
+ * previous list (ids[n], springs hs[8n]), or zero for a new contact. */
+static void prev_springs(const int* ids, int n, const double* hs, int id, double h[8]) {
   int k = list_index(ids, n, id);
-  for (int b = 0; b < 4; ++b) h[b] = (k >= 0 && hs) ? hs[4 * k + b] : 0.0;
+  for (int b = 0; b < 8; ++b) h[b] = (k >= 0 && hs) ? hs[8 * k + b] : 0.0;
 }
 
 /* Velocity and spin of a body as friction sees them: a 2D disk moves in
@@ -636,27 +658,9 @@ static double dot3(const double a[3], const double b[3]) {
   return a[0] * b[0] + a[1] * b[1] + a[2] * b[2];
 }
 
-/* Sliding and twisting friction of one contact (Eqs. 22, 28, 29), each a
- * linear spring-dashpot-slider.  Body i (radius ri, velocity ui, spin wi)
- * touches body j (rj, uj, wj; a wall has zero velocity and spin) along the
- * unit normal n from i towards j.  Fne is the JKR elastic normal force
- * (repulsive positive, no damping), FC = 3 pi gamma R and a the contact
- * radius.  h holds the contact's springs from the previous sub-step (the
- * tangential displacement xi[3] and the twist angle theta) and receives the
- * new ones; the force on i is added to fc and its torque about i's centre to
- * tc.
- * Readings: v_R is the velocity of j's surface point relative to i's at the
- *   contact (points at distance ri and rj from the centres along n), and a
- *   positive displacement of j drags i along with it, which is the paper's
- *   minus sign with the roles of i and j exchanged; the integral of Eq. 28
- *   runs from the first sub-step of contact and includes the current one,
- *   and the stored displacement is projected onto the current tangent plane
- *   before the step's increment is added; min[.] caps the magnitude of the
- *   spring-plus-dashpot force (moment), and while it is capped the spring is
- *   reset to the stretch that gives the capped value (the slider takes the
- *   rest); F_ne of Eq. 29 is the elastic JKR force, so the cap
- *   mu_f (F_ne + 2 F_C) is positive on the whole stable branch. */
-static void contact_friction(const or_dem_params* p, const double n[3], double ri,
+/* Sliding (Eq. 28 first line, cap Eq. 29 first line) and twisting (second
+ * lines) of one contact; arguments as contact_friction, h[0..3]. */
+static void sliding_twisting(const or_dem_params* p, const double n[3], double ri,
                              const double ui[3], const double wi[3], double rj,
                              const double uj[3], const double wj[3], double Fne, double FC,
                              double a, double dts, double h[4], double fc[3], double tc[3]) {
@@ -706,6 +710,60 @@ static void contact_friction(const or_dem_params* p, const double n[3], double r
   h[3] = theta;
 }
 
+/* Rolling resistance (Eq. 28 third line, cap Eq. 29 third line) of one
+ * contact: the rolling displacement xr = integral of v_L with
+ * v_L = R (w_i - w_j) x n, turned into the current tangent plane before the
+ * sub-step's increment, resisted by the moment k_r |xr| with
+ * k_r = 4 F_C x^{3/2}, which acts on i as k_r (xr x n).  Reading: Eq. 29's
+ * M_r,crit is k_r theta_crit R in magnitude (its minus sign only restates
+ * that the moment opposes the rolling), so the spring holds at most
+ * |xr| = theta_crit R and is clamped there while the contact rolls on. */
+static void rolling(const or_dem_params* p, const double n[3], double R, const double wi[3],
+                    const double wj[3], double FC, double x, double dts, double xr[3],
+                    double tc[3]) {
+  double dw[3], dwn[3], m[3];
+  for (int b = 0; b < 3; ++b) dw[b] = wi[b] - wj[b];
+  cross(dw, n, dwn);                              /* v_L = R dwn */
+  const double hn = dot3(xr, n);
+  for (int b = 0; b < 3; ++b) xr[b] = xr[b] - hn * n[b] + dts * R * dwn[b];
+  const double mag = sqrt(dot3(xr, xr)), cap = p->theta_r * R;
+  if (mag > cap)
+    for (int b = 0; b < 3; ++b) xr[b] *= cap / mag;
+  const double kr = 4.0 * FC * pow(x, 1.5);
+  cross(xr, n, m);
+  for (int b = 0; b < 3; ++b) tc[b] += kr * m[b];
+}
+
+/* Sliding, twisting and rolling friction of one contact (Eqs. 22, 28, 29),
+ * each a linear spring-dashpot-slider.  Body i (radius ri, velocity ui, spin
+ * wi) touches body j (rj, uj, wj; a wall has zero velocity and spin) along
+ * the unit normal n from i towards j; R is the effective radius.  Fne is the
+ * elastic normal force (repulsive positive, no damping), FC = 3 pi gamma R,
+ * a the contact radius and x = a / a0.  h holds the contact's springs from
+ * the previous sub-step (the tangential displacement xi[3], the twist angle
+ * theta and the rolling displacement xr[3]) and receives the new ones; the
+ * force on i is added to fc and its torque about i's centre to tc.  Sliding
+ * and twisting act with mu_f > 0, rolling with theta_r > 0 and adhesion.
+ * Readings: v_R is the velocity of j's surface point relative to i's at the
+ *   contact (points at distance ri and rj from the centres along n), and a
+ *   positive displacement of j drags i along with it, which is the paper's
+ *   minus sign with the roles of i and j exchanged; the integral of Eq. 28
+ *   runs from the first sub-step of contact and includes the current one,
+ *   and the stored displacement is projected onto the current tangent plane
+ *   before the step's increment is added; min[.] caps the magnitude of the
+ *   spring-plus-dashpot force (moment), and while it is capped the spring is
+ *   reset to the stretch that gives the capped value (the slider takes the
+ *   rest); F_ne of Eq. 29 is the elastic JKR force, so the cap
+ *   mu_f (F_ne + 2 F_C) is positive on the whole stable branch. */
+static void contact_friction(const or_dem_params* p, const double n[3], double ri,
+                             const double ui[3], const double wi[3], double rj,
+                             const double uj[3], const double wj[3], double R, double Fne,
+                             double FC, double a, double x, double dts, double h[8],
+                             double fc[3], double tc[3]) {
+  if (p->mu_f > 0.0) sliding_twisting(p, n, ri, ui, wi, rj, uj, wj, Fne, FC, a, dts, h, fc, tc);
+  if (p->theta_r > 0.0 && FC > 0.0) rolling(p, n, R, wi, wj, FC, x, dts, &h[4], tc);
+}
+
 /* One coupling step of the DEM (Eq. 21): n_sub semi-implicit Euler sub-steps
  * of dt / n_sub, with the hydrodynamic force Ff and torque Tf frozen (Sec.
  * 2.5).  Contacts (all pairs, nearest image) carry the JKR normal force with
@@ -714,12 +772,14 @@ static void contact_friction(const or_dem_params* p, const double n[3], double r
  * of the previous sub-step.  Reading: non-periodic axes have flat walls at
  * -1/2 and L-1/2 acting as JKR bodies of infinite radius and the particle's
  * material; the walls are contact partners -1-face.
- * With mu_f > 0 every contact also carries the sliding and twisting friction
- * of Eqs. 22, 28, 29 (contact_friction); a wall is at rest.
+ * gamma == 0 is Hertz's contact without adhesion (normal_contact).  With
+ * mu_f > 0 or theta_r > 0 every contact also carries the friction of Eqs. 22,
+ * 28, 29 (contact_friction); a wall is at rest.
  * Contact state: ncontact[np], contact_ids[np*cap] (sorted ascending), in/out;
- * hist[np*cap*4] (may be NULL without friction) holds each contact's springs
- * (xi[3], theta) beside its id; without friction the springs are written as
- * zero, so friction switched on later starts every persisting contact unloaded.
+ * hist[np*cap*8] (may be NULL without friction) holds each contact's springs
+ * (xi[3], theta, xr[3], unused) beside its id; without friction the springs
+ * are written as zero, so friction switched on later starts every persisting
+ * contact unloaded.
  * Gravity G = (rho_p - rho_f) V g.  2D: disks of unit depth, V = pi r^2,
  * I = m r^2 / 2, spin about z only; 3D: V = 4/3 pi r^3, I = 2 m r^2 / 5.
  * Returns 0, or -1 when a particle has more than cap contacts. */
@@ -728,7 +788,7 @@ int or_dem_step(const or_config* c, const or_dem_params* p, int np, double* X,
                 const double* Tf, int cap, int* ncontact, int* contact_ids, double* hist) {
   const int two_d = (c->q == 9);
   const double dts = p->dt / (double)p->n_sub;
-  const int fric = p->mu_f > 0.0;
+  const int fric = p->mu_f > 0.0 || p->theta_r > 0.0;
   if (p->kinematic) {
     for (int sub = 0; sub < p->n_sub; ++sub)
       for (int s = 0; s < np; ++s)
@@ -739,42 +799,40 @@ int or_dem_step(const or_config* c, const or_dem_params* p, int np, double* X,
     double* Tc = (double*)calloc((size_t)3 * np, sizeof(double));
     int* nn = (int*)calloc((size_t)np, sizeof(int));
     int* nid = (int*)calloc((size_t)np * cap, sizeof(int));
-    double* nh = (double*)calloc((size_t)np * cap * 4, sizeof(double));
+    double* nh = (double*)calloc((size_t)np * cap * 8, sizeof(double));
     const double zero[3] = {0, 0, 0};
     int rc = 0;
     for (int sub = 0; sub < p->n_sub && rc == 0; ++sub) {
       for (int i = 0; i < np; ++i) {
         double fc[3] = {0, 0, 0}, tc[3] = {0, 0, 0};
-        double hl[512][4];
+        double hl[512][8];
         int cnt = 0, list[512];
         const int* prev = &contact_ids[(size_t)i * cap];
-        const double* prev_h = hist ? &hist[(size_t)i * cap * 4] : NULL;
+        const double* prev_h = hist ? &hist[(size_t)i * cap * 8] : NULL;
         /* particle-wall contacts first (ids -1-face are the smallest) */
         for (int face = 5; face >= 0; --face) {
           int a = face / 2;
           if (axis_periodic(c, a)) continue;
           double L = (double)dims(c, a);
           double dist = (face % 2 == 0) ? X[3 * i + a] + 0.5 : (L - 0.5) - X[3 * i + a];
-          double delta = R[i] - dist, force, dC;
-          or_jkr_force(R[i], E, p->gamma, delta, &force, &dC);
+          double delta = R[i] - dist, force, dC, acon, xcon;
+          normal_contact(R[i], E, p->gamma, delta, &force, &dC, &acon, &xcon);
           int id = -1 - face;
           if (delta >= 0.0 || (delta > -dC && in_list(prev, ncontact[i], id))) {
-            double nrm[3] = {0, 0, 0}, h[4] = {0, 0, 0, 0};
+            double nrm[3] = {0, 0, 0}, h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             nrm[a] = (face % 2 == 0) ? -1.0 : 1.0;
             double vrn = -(U[3 * i + 0] * nrm[0] + U[3 * i + 1] * nrm[1] + U[3 * i + 2] * nrm[2]);
             for (int b = 0; b < 3; ++b) fc[b] += (-force + p->eta_n * vrn) * nrm[b];
             if (fric) {
-              jkr_consts k = jkr_make(R[i], E, p->gamma);
-              double acon = or_jkr_x(delta / k.dC) * k.a0;
               double ui[3], wi[3];
               planar(two_d, &U[3 * i], &W[3 * i], ui, wi);
               prev_springs(prev, ncontact[i], prev_h, id, h);
-              contact_friction(p, nrm, R[i], ui, wi, 0.0, zero, zero, force, k.FC, acon, dts, h,
-                               fc, tc);
+              contact_friction(p, nrm, R[i], ui, wi, 0.0, zero, zero, R[i], force,
+                               3.0 * M_PI * p->gamma * R[i], acon, xcon, dts, h, fc, tc);
             }
             if (cnt < 512) {
               list[cnt] = id;
-              for (int b = 0; b < 4; ++b) hl[cnt][b] = h[b];
+              for (int b = 0; b < 8; ++b) hl[cnt][b] = h[b];
             }
             ++cnt;
           }
@@ -791,26 +849,24 @@ int or_dem_step(const or_config* c, const or_dem_params* p, int np, double* X,
           double delta = R[i] + R[j] - dist;
           double Reff = 1.0 / (1.0 / R[i] + 1.0 / R[j]);
           if (delta < 0.0 && !in_list(prev, ncontact[i], j)) continue;
-          double force, dC;
-          or_jkr_force(Reff, E, p->gamma, delta, &force, &dC);
+          double force, dC, acon, xcon;
+          normal_contact(Reff, E, p->gamma, delta, &force, &dC, &acon, &xcon);
           if (delta >= 0.0 || delta > -dC) {
-            double nrm[3], vrn = 0.0, h[4] = {0, 0, 0, 0};
+            double nrm[3], vrn = 0.0, h[8] = {0, 0, 0, 0, 0, 0, 0, 0};
             for (int a = 0; a < 3; ++a) nrm[a] = dv[a] / dist;
             for (int a = 0; a < 3; ++a) vrn += (U[3 * j + a] - U[3 * i + a]) * nrm[a];
             for (int a = 0; a < 3; ++a) fc[a] += (-force + p->eta_n * vrn) * nrm[a];
             if (fric) {
-              jkr_consts k = jkr_make(Reff, E, p->gamma);
-              double acon = or_jkr_x(delta / k.dC) * k.a0;
               double ui[3], wi[3], uj[3], wj[3];
               planar(two_d, &U[3 * i], &W[3 * i], ui, wi);
               planar(two_d, &U[3 * j], &W[3 * j], uj, wj);
               prev_springs(prev, ncontact[i], prev_h, j, h);
-              contact_friction(p, nrm, R[i], ui, wi, R[j], uj, wj, force, k.FC, acon, dts, h, fc,
-                               tc);
+              contact_friction(p, nrm, R[i], ui, wi, R[j], uj, wj, Reff, force,
+                               3.0 * M_PI * p->gamma * Reff, acon, xcon, dts, h, fc, tc);
             }
             if (cnt < 512) {
               list[cnt] = j;
-              for (int b = 0; b < 4; ++b) hl[cnt][b] = h[b];
+              for (int b = 0; b < 8; ++b) hl[cnt][b] = h[b];
             }
             ++cnt;
           }
@@ -819,7 +875,7 @@ int or_dem_step(const or_config* c, const or_dem_params* p, int np, double* X,
         nn[i] = cnt;
         for (int k = 0; k < cnt; ++k) {
           nid[(size_t)i * cap + k] = list[k];
-          for (int b = 0; b < 4; ++b) nh[((size_t)i * cap + k) * 4 + b] = hl[k][b];
+          for (int b = 0; b < 8; ++b) nh[((size_t)i * cap + k) * 8 + b] = hl[k][b];
         }
         for (int a = 0; a < 3; ++a) {
           Fc[3 * i + a] = fc[a];
@@ -847,8 +903,8 @@ int or_dem_step(const or_config* c, const or_dem_params* p, int np, double* X,
         for (int k = 0; k < nn[i]; ++k) {
           contact_ids[(size_t)i * cap + k] = nid[(size_t)i * cap + k];
           if (hist)
-            for (int b = 0; b < 4; ++b)
-              hist[((size_t)i * cap + k) * 4 + b] = nh[((size_t)i * cap + k) * 4 + b];
+            for (int b = 0; b < 8; ++b)
+              hist[((size_t)i * cap + k) * 8 + b] = nh[((size_t)i * cap + k) * 8 + b];
         }
       }
     }

@@ -16,6 +16,7 @@ import math
 
 import numpy as np
 import pytest
+from scipy import integrate
 
 import oracle
 import workloads as W
@@ -80,7 +81,7 @@ def test_rolls_without_slipping_below_the_cap(q):
     u, w = h[-1]
     assert abs(u[1] - R0 * w[2]) < 1e-5 * abs(u[1])
     # the spring carries the friction force the rolling needs
-    xi, theta = D.springs(0)[-1]
+    xi, theta, _ = D.springs(0)[-1]
     assert 5e-3 * xi[1] == pytest.approx(-F * I / (m * R0 ** 2 + I), rel=1e-4)
     assert theta == 0.0
 
@@ -102,7 +103,7 @@ def test_slides_at_the_adhesive_coulomb_cap(q):
     # the spring's stretch stays bounded instead of growing with the slip
     u, w = h[-2]                          # state at the start of the last step
     vt = -(u[1] - R0 * w[2])              # the wall's velocity relative to the contact point
-    xi, _ = D.springs(0)[-1]
+    xi, _, _ = D.springs(0)[-1]
     assert 5e-3 * xi[1] + 2.0 * vt == pytest.approx(-Fcrit, rel=1e-12)
 
 
@@ -126,7 +127,7 @@ def test_twist_slips_above_its_cap():
     assert alpha == pytest.approx((T - Mcrit) / I, rel=1e-7)
     # the twist slider holds spring plus dashpot at the cap
     Om = h[-2][1][0]                      # relative twist rate about n = -x
-    _, theta = D.springs(0)[-1]
+    _, theta, _ = D.springs(0)[-1]
     assert 5e-3 * a * a / 2 * theta + 2.0 * a * a / 2 * Om == pytest.approx(Mcrit, rel=1e-9)
     # twisting about the normal moves nothing else
     assert np.abs(h[-1][0]).max() < 1e-15 and np.abs(h[-1][1][1:]).max() < 1e-15
@@ -202,3 +203,123 @@ def test_central_impact_without_spin_feels_no_friction(q):
         runs.append(p)
     assert np.array_equal(runs[0].x, runs[1].x) and np.array_equal(runs[0].u, runs[1].u)
     assert np.abs(runs[1].omega).max() == 0.0
+
+
+# Rolling resistance (Eq. 28 third line, Eq. 29 third line): stiffness
+# k_r = 4 F_C (a/a0)^{3/2} per unit rolling displacement, capped at the
+# displacement theta_crit R.  On the wall R = r and (a/a0)^{3/2} = s^3 of
+# the JKR load relation above.
+
+def _rolling_stiffness(Wl):
+    return 4 * FC * 0.5 * (1.0 + math.sqrt(1.0 + Wl / FC))
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_rolling_resistance_holds_a_torque_below_its_cap(q):
+    # a torque below the cap winds the rolling spring: the sphere (disk), which
+    # rolls without slipping on the sticking contact, oscillates undamped
+    # about phi = T / (k_r r) between 0 and twice that
+    theta = 0.05
+    _, p, D, Wl = _settled(q, k_t=5e-2, eta_t=5.0, mu_f=1.0, theta_r=theta)
+    kr = _rolling_stiffness(Wl)
+    T = 0.5 * kr * theta * R0
+    h = _run(D, p, (0.0, 0.0, 0.0), (0.0, 0.0, T), 12000)
+    phi = np.cumsum([w[2] for _, w in h])                       # dt = 1
+    phi_eq = T / (kr * R0)
+    assert phi.max() == pytest.approx(2 * phi_eq, rel=1e-2)
+    assert phi.min() > -1e-3 * phi_eq
+    _, _, xr = D.springs(0)[-1]
+    assert np.linalg.norm(xr) <= theta * R0 * (1 + 1e-12)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_rolling_resistance_caps_at_theta_crit(q):
+    # above the cap k_r theta_crit r the sphere rolls on, without slipping,
+    # at (T - M_r,crit) / (I + m r^2)
+    theta = 0.02
+    _, p, D, Wl = _settled(q, k_t=5e-2, eta_t=5.0, mu_f=1.0, theta_r=theta)
+    _, m, I = _mass(q)
+    kr = _rolling_stiffness(Wl)
+    Mcrit = kr * theta * R0
+    T = 3 * Mcrit
+    h = _run(D, p, (0.0, 0.0, 0.0), (0.0, 0.0, T), 4000)
+    alpha = (h[-1][1][2] - h[1999][1][2]) / 2000.0
+    assert alpha == pytest.approx((T - Mcrit) / (I + m * R0 ** 2), rel=1e-5)
+    _, _, xr = D.springs(0)[-1]
+    assert np.linalg.norm(xr) == pytest.approx(theta * R0, rel=1e-12)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_rolling_couples_conserve_angular_momentum(q):
+    # normal forces are central and the rolling moments act on the two
+    # bodies as equal and opposite couples, so the total angular momentum
+    # sum(m x cross u + I omega) is conserved (semi-implicit Euler keeps it
+    # exactly for central forces)
+    lat, p = _pair(q, spin=True)
+    dem = W.DemSpec(E_p=1e-3, gamma=1e-5, eta_n=0.05, theta_r=0.01)
+    D = oracle.Dem(lat, dem, 2)
+    V = math.pi * p.r ** 2 if q == 9 else 4.0 / 3.0 * math.pi * p.r ** 3
+    m = dem.rho_p * V
+    I = (0.5 if q == 9 else 0.4) * m * p.r ** 2
+
+    def L():
+        return (m[:, None] * np.cross(p.x, p.u)).sum(axis=0) + (I[:, None] * p.omega).sum(axis=0)
+
+    L0 = L()
+    z = np.zeros((2, 3))
+    w0 = p.omega.copy()
+    tangent_checked = 0
+    for _ in range(800):
+        x0 = p.x.copy()
+        D.step(p, z, z)
+        assert np.allclose(L(), L0, rtol=0, atol=1e-13 * np.abs(L0).max())
+        # the rolling spring lies in the tangent plane of the current normal
+        sp = D.springs(0)
+        if 1 in sp:
+            n = (x0[1] - x0[0]) / np.linalg.norm(x0[1] - x0[0])
+            xr = sp[1][2]
+            assert abs(xr @ n) <= 1e-12 * np.linalg.norm(xr)
+            tangent_checked += np.linalg.norm(xr) > 0
+    assert np.abs(p.omega - w0).max() > 1e-6                      # the couples acted
+    assert tangent_checked > 50
+
+
+# Without adhesion (gamma = 0) the contact is Hertz's.
+
+def test_hertz_collision_time_and_restitution():
+    lat = W.LatticeSpec(q=19, nx=40, ny=40, nz=40)
+    v0, r = 4e-4, 4.0
+    p = W.Particles(np.array([[15.9, 20.0, 20.0], [24.1, 20.0, 20.0]]),
+                    np.array([[v0 / 2, 0.0, 0.0], [-v0 / 2, 0.0, 0.0]]), np.zeros((2, 3)),
+                    np.array([r, r]))
+    dem = W.DemSpec(E_p=1e-3, poisson=0.3, gamma=0.0)
+    D = oracle.Dem(lat, dem, 2)
+    Estar = 1.0 / (2 * (1 - 0.3 ** 2) / 1e-3)
+    m = dem.rho_p * 4.0 / 3.0 * math.pi * r ** 3
+    K = 4.0 / 3.0 * Estar * math.sqrt(r / 2)                    # F = K delta^{3/2}, R = r/2
+    dmax = (5 * (m / 2) * v0 ** 2 / (4 * K)) ** 0.4
+    shape = integrate.quad(lambda s: 1 / math.sqrt(1 - s ** 2.5), 0, 1)[0]
+    t_contact = 2 * dmax / v0 * shape
+    z = np.zeros((2, 3))
+    steps_in_contact = 0
+    for _ in range(int(1.5 * t_contact) + 200):
+        D.step(p, z, z)
+        steps_in_contact += bool(D.contacts()[0])
+    assert steps_in_contact == pytest.approx(t_contact, rel=2e-3)
+    assert p.u[1, 0] - p.u[0, 0] == pytest.approx(v0, rel=1e-4)   # elastic: e = 1
+
+
+def test_hertz_wall_rest_overlap():
+    lat = _wall_lattice(19)
+    dem = W.DemSpec(g=(-G0, 0.0, 0.0), E_p=EP, poisson=POISSON, gamma=0.0, eta_n=5.0)
+    p = W.Particles(np.array([[R0 - 0.5, 20.0, 20.0]]), np.zeros((1, 3)), np.zeros((1, 3)),
+                    np.array([R0]))
+    D = oracle.Dem(lat, dem, 1)
+    z = np.zeros((1, 3))
+    for _ in range(8000):
+        D.step(p, z, z)
+    V, _, _ = _mass(19)
+    Wl = 2.0 * V * G0
+    overlap = R0 - (p.x[0, 0] + 0.5)
+    assert overlap == pytest.approx((Wl / (4.0 / 3.0 * ESTAR * math.sqrt(R0))) ** (2 / 3),
+                                    rel=1e-9)

@@ -113,6 +113,7 @@ class DemSpec:
     k_t: float = 0.0       # tangential stiffness k_T (Eq. 28)
     eta_t: float = 0.0     # tangential dissipation coefficient eta_T (Eq. 28)
     mu_f: float = 0.0      # friction coefficient (Eq. 29); 0: no friction
+    theta_r: float = 0.0   # critical rolling angle theta_crit (Eq. 29); 0: no rolling resistance
 
 
 @dataclass
