@@ -119,6 +119,8 @@ typedef struct {
   double eta_t;               /* tangential dissipation coefficient eta_T (Eq. 28), >= 0 */
   double mu_f;                /* friction coefficient (Eq. 29), >= 0; 0: no sliding or
                                  twisting friction (zero-initialised callers get none) */
+  double theta_r;             /* critical rolling angle theta_crit (Eq. 29), >= 0; 0: no
+                                 rolling resistance */
 } psclbm_dem_params;
 
 typedef struct psclbm_ctx psclbm_ctx;
@@ -203,16 +205,20 @@ int particle_forces(psclbm_ctx* ctx, double* d_force, double* d_torque);
  * capped at 3 pi a F_crit / 16 (a the JKR contact radius); v_t is the slip of
  * the partner's surface point relative to the particle's, xi and theta the
  * slip and twist integrated since the contact began, reset to the capped
- * value while capped; walls are at rest, and a 2D disk moves in its plane
- * and spins about z.  Positions wrap into [0, L) on periodic axes.  2D: disks
- * of unit depth.  Contact history (ids, and with friction each contact's
+ * value while capped.  With theta_r > 0 (and gamma > 0) the rolling
+ * displacement xr, the integral of R (omega_i - omega_j) x n with R the
+ * effective radius, meets the moment 4 F_C (a/a0)^{3/2} (xr x n), xr clamped
+ * at |xr| = theta_r R.  Walls are at rest, and a 2D disk moves in its plane
+ * and spins about z.  gamma == 0 gives Hertz's contact without adhesion,
+ * F = (4/3) E sqrt(R) delta^{3/2}.  Positions wrap into [0, L) on periodic
+ * axes.  2D: disks of unit depth.  Contact history (ids, and with friction each contact's
  * springs; a step without friction leaves every spring unloaded) lives in the
  * workspace (dem_reset_contacts clears it).  d_force and d_torque may
  * both be NULL: the force and torque of the most recent lbm_step are then
  * read from the workspace (n must equal the rasterised count; ESTATE
  * otherwise).  The contact forces of a particle are summed in neighbour-bin
  * order.  Errors: EINVAL (bad params, among them a negative or non-finite
- * k_t, eta_t or mu_f, or k_t == 0 with mu_f > 0; n > max_particles, only one
+ * k_t, eta_t, mu_f or theta_r, or k_t == 0 with mu_f > 0; n > max_particles, only one
  * of the two force pointers NULL, a contact reach delta_C of 1 or more), EHIP;
  * sticky ECONTACTS on contact or bin overflow. */
 int dem_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double* d_u,
@@ -228,7 +234,8 @@ int dem_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double*
  * fused: the DEM wave of a particle, having integrated it, writes its
  * snapshot and enters it in the tile lists and DEM bins of the next step, so
  * a step is two kernels (plus one at the start of the call); with friction
- * (mu_f > 0) the three calls are made in turn.  Afterwards the
+ * (mu_f > 0 or theta_r > 0) or the Hertz contact (gamma == 0) the three
+ * calls are made in turn.  Afterwards the
  * context holds the last step's rasterisation and force / torque
  * accumulators, as after the three calls.  Errors: those of psc_rasterize,
  * lbm_step and dem_step (EINVAL, EHIP; sticky ESLOTS, ECONTACTS). */

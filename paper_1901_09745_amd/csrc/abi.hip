@@ -129,8 +129,8 @@ Layout plan(const psclbm_config* c) {
   l.cid0 = take(sizeof(int) * (size_t)(np > 0 ? np : 1) * mc);
   l.cid1 = take(sizeof(int) * (size_t)(np > 0 ? np : 1) * mc);
   l.fcont = take(sizeof(double) * 3 * (size_t)(np > 0 ? np : 1));
-  l.spr0 = take(sizeof(double) * 4 * (size_t)(np > 0 ? np : 1) * mc);
-  l.spr1 = take(sizeof(double) * 4 * (size_t)(np > 0 ? np : 1) * mc);
+  l.spr0 = take(sizeof(double) * SPRINGS * (size_t)(np > 0 ? np : 1) * mc);
+  l.spr1 = take(sizeof(double) * SPRINGS * (size_t)(np > 0 ? np : 1) * mc);
   l.wsnap = take(sizeof(double) * 3 * (size_t)(np > 0 ? np : 1));
   l.total = off;
   return l;
@@ -335,8 +335,9 @@ static bool dem_material_ok(const psclbm_dem_params* p) {
   if (!(p->rho_p > 0.0) || !(p->E_p > 0.0) || !(p->gamma >= 0.0) ||
       !(p->poisson > -1.0 && p->poisson < 0.5) || !(p->eta_n >= 0.0))
     return false;
-  if (!(p->k_t >= 0.0) || !(p->eta_t >= 0.0) || !(p->mu_f >= 0.0) || !std::isfinite(p->k_t) ||
-      !std::isfinite(p->eta_t) || !std::isfinite(p->mu_f))
+  if (!(p->k_t >= 0.0) || !(p->eta_t >= 0.0) || !(p->mu_f >= 0.0) || !(p->theta_r >= 0.0) ||
+      !std::isfinite(p->k_t) || !std::isfinite(p->eta_t) || !std::isfinite(p->mu_f) ||
+      !std::isfinite(p->theta_r))
     return false;
   return p->mu_f == 0.0 || p->k_t > 0.0;  // the slider divides by k_T
 }

@@ -113,6 +113,10 @@ struct Geom {
   double rho0;
 };
 
+// Doubles of friction springs kept per contact: the tangential displacement
+// xi[3], the twist angle, the rolling displacement xr[3], one unused.
+constexpr int SPRINGS = 8;
+
 // Contact-pass arguments: the binning it reads and the contact lists.
 struct DemArgs {
   int n;
@@ -214,7 +218,7 @@ struct psclbm_ctx {
   int* contact_id[2];
   int contact_cur;
   double* fcontact;  // [max_particles][3] contact forces of the coupled step
-  double* contact_springs[2];  // per contact list: [max_particles][max_contacts][4] friction springs
+  double* contact_springs[2];  // per contact list: [max_particles][max_contacts][SPRINGS]
   int springs_valid;           // the current list's springs were written (friction was on)
   double* wsnap;               // [max_particles][3] spins at the start of a friction sub-step
   double* scalar;  // one FP64 device scalar for reductions

@@ -110,11 +110,11 @@ struct NextOut {
 
 // One wave per particle.  Unless fc_in holds them (the contact forces the
 // coupled step kernel gathered), the contacts are gathered here
-// (dem_contact_wave, with friction when FRIC).  Every lane then integrates
-// the particle (the same values), lane 0 stores it, and with nx.build the
-// wave rasterises it for the next coupled step.  Kinematic particles skip
-// the contacts.
-template <bool FRIC>
+// (dem_contact_wave, with friction when FRIC and Hertz's normal force when
+// HERTZ).  Every lane then integrates the particle (the same values), lane 0
+// stores it, and with nx.build the wave rasterises it for the next coupled
+// step.  Kinematic particles skip the contacts.
+template <bool FRIC, bool HERTZ>
 __global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, FricArgs fr, IntArgs ia,
                                                       NextOut nx, double* x, double* u,
                                                       double* w, const double* r,
@@ -148,8 +148,8 @@ __global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, FricArgs fr, In
   }
   double fsum[3] = {0.0, 0.0, 0.0};
   double tsum[3] = {0.0, 0.0, 0.0};
-  if constexpr (FRIC) {
-    dem_contact_wave<true>(d, i, lane, xs, us, ri, fsum, &fr, ws, tsum);
+  if constexpr (FRIC || HERTZ) {
+    dem_contact_wave<FRIC, HERTZ>(d, i, lane, xs, us, ri, fsum, &fr, ws, tsum);
   } else if (fc_in) {  // contacts gathered by the step kernel's contact workgroups
 #pragma unroll
     for (int a = 0; a < 3; ++a) fsum[a] = fc_in[3 * i + a];
@@ -259,6 +259,11 @@ static DemArgs dem_args(const psclbm_ctx* c, const psclbm_dem_params* prm, int n
   return d;
 }
 
+// Friction of any kind is on: the contacts keep springs.
+static bool dem_friction(const psclbm_dem_params* prm) {
+  return prm->mu_f > 0.0 || prm->theta_r > 0.0;
+}
+
 int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, double* u, double* w,
                     const double* r, int n, const double* F, const double* T) {
   IntArgs ia = int_args(c, prm, n, F, T);
@@ -276,13 +281,14 @@ int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doub
   if (!(E > 0.0)) return PSCLBM_EINVAL;
   NextOut nx;
   std::memset(&nx, 0, sizeof(nx));
-  const bool fric = prm->mu_f > 0.0;
+  const bool fric = dem_friction(prm), hertz = prm->gamma == 0.0;
   FricArgs fr;
   std::memset(&fr, 0, sizeof(fr));
   fr.w = c->wsnap;
   fr.k_t = prm->k_t;
   fr.eta_t = prm->eta_t;
   fr.mu_f = prm->mu_f;
+  fr.theta_r = prm->theta_r;
   fr.dts = prm->dt / prm->n_sub;
   for (int s = 0; s < prm->n_sub; ++s) {
     ia.wrap = s == prm->n_sub - 1;  // positions wrap once, after the last sub-step
@@ -296,12 +302,20 @@ int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doub
       // springs of the previous lists only if they were kept (friction on)
       fr.prev_h = c->springs_valid ? c->contact_springs[c->contact_cur] : nullptr;
       fr.next_h = c->contact_springs[c->contact_cur ^ 1];
-      k_dem_contacts<true><<<(n + 3) / 4, 256, 0, c->stream>>>(d, fr, ia, nx, x, u, w, r, F, T,
-                                                              nullptr);
-    } else {
-      k_dem_contacts<false><<<(n + 3) / 4, 256, 0, c->stream>>>(d, fr, ia, nx, x, u, w, r, F,
-                                                               T, nullptr);
     }
+    const dim3 grid((n + 3) / 4), block(256);
+    if (fric && hertz)
+      k_dem_contacts<true, true><<<grid, block, 0, c->stream>>>(d, fr, ia, nx, x, u, w, r, F, T,
+                                                               nullptr);
+    else if (fric)
+      k_dem_contacts<true, false><<<grid, block, 0, c->stream>>>(d, fr, ia, nx, x, u, w, r, F, T,
+                                                                nullptr);
+    else if (hertz)
+      k_dem_contacts<false, true><<<grid, block, 0, c->stream>>>(d, fr, ia, nx, x, u, w, r, F, T,
+                                                                nullptr);
+    else
+      k_dem_contacts<false, false><<<grid, block, 0, c->stream>>>(d, fr, ia, nx, x, u, w, r, F,
+                                                                 T, nullptr);
     int rc = hip_ok(hipGetLastError());
     if (rc) return rc;
     c->contact_cur ^= 1;
@@ -324,8 +338,9 @@ int launch_coupled(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doubl
     E = dem_modulus(c, prm);
     if (!(E > 0.0)) return PSCLBM_EINVAL;
   }
-  if (prm->n_sub != 1 || n == 0 || (!prm->kinematic && prm->mu_f > 0.0)) {
-    // sub-cycled DEM or friction: the three calls in turn
+  if (prm->n_sub != 1 || n == 0 ||
+      (!prm->kinematic && (dem_friction(prm) || prm->gamma == 0.0))) {
+    // sub-cycled DEM, friction or the Hertz contact: the three calls in turn
     for (int t = 0; t < nsteps; ++t) {
       int rc = launch_rasterize(c, p, false);
       if (!rc) c->np = n;
@@ -365,7 +380,7 @@ int launch_coupled(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doubl
     nx.err = c->err;
     FricArgs fr;
     std::memset(&fr, 0, sizeof(fr));
-    k_dem_contacts<false><<<(n + 3) / 4, 256, 0, c->stream>>>(
+    k_dem_contacts<false, false><<<(n + 3) / 4, 256, 0, c->stream>>>(
         d, fr, ia, nx, x, u, w, r, F, T, prm->kinematic ? nullptr : c->fcontact);
     rc = hip_ok(hipGetLastError());
     if (rc) return rc;

@@ -1,8 +1,9 @@
 // DEM contact gather of the gfx950 PSC-LBM library (FP64), Sec. 2.5: the
-// JKR normal force (Eqs. 25-27) with the jump-on / pull-off hysteresis, and
-// optionally the sliding and twisting friction of Eqs. 22, 28, 29, gathered
-// by one wave per particle from the DEM bins.  Used by the DEM kernel and
-// (without friction) by the contact workgroups of the coupled step kernel.
+// JKR normal force (Eqs. 25-27) with the jump-on / pull-off hysteresis (or
+// Hertz's without adhesion), and optionally the sliding, twisting and
+// rolling friction of Eqs. 22, 28, 29, gathered by one wave per particle
+// from the DEM bins.  Used by the DEM kernel and (JKR without friction) by
+// the contact workgroups of the coupled step kernel.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -28,9 +29,9 @@ __device__ inline double min_img(double d, int periodic, int L) {
 // Solved for s = x^{1/2} by Newton from above (g(s) = 2 s^4 - 4/3 s is convex
 // and increasing on the branch s >= 6^{-1/3}, so the iterates decrease
 // monotonically to the root).  Returns the repulsive-positive force, and the
-// contact radius a = x a0 in *a_out when that is given.
+// contact radius a = x a0 and x in *a_out and *x_out when those are given.
 __device__ inline double jkr_force(double R, double E, double gamma, double delta, double* dC,
-                                   double* a_out = nullptr) {
+                                   double* a_out = nullptr, double* x_out = nullptr) {
   const double c6 = 1.8171205928321397;  // 6^{1/3}
   const double FC = 3.0 * M_PI * gamma * R;
   const double a0 = cbrt(9.0 * M_PI * gamma * R * R / E);
@@ -55,35 +56,73 @@ __device__ inline double jkr_force(double R, double E, double gamma, double delt
   }
   const double x = s * s;
   if (a_out) *a_out = x * a0;
+  if (x_out) *x_out = x;
   return 4.0 * FC * (x * x * x - x * s);
 }
 
+// Hertz's contact, the JKR one without adhesion: F = (4/3) E sqrt(R)
+// delta^{3/2} and a = sqrt(R delta) for delta >= 0, nothing below.
+__device__ inline double hertz_force(double R, double E, double delta, double* a_out) {
+  const double d = delta > 0.0 ? delta : 0.0;
+  *a_out = sqrt(R * d);
+  return (4.0 / 3.0) * E * sqrt(R) * d * sqrt(d);
+}
+
 // Friction arguments of the standalone DEM kernel: each contact's springs
-// (tangential displacement xi[3], twist angle theta) sit beside its id in the
-// contact lists, [particle][max_contacts][4].
+// (tangential displacement xi[3], twist angle theta, rolling displacement
+// xr[3], unused) sit beside its id in the contact lists,
+// [particle][max_contacts][SPRINGS].
 struct FricArgs {
   const double* w;       // [n][3] spins at the start of the sub-step
   const double* prev_h;  // springs of the previous lists; null: every contact starts unloaded
   double* next_h;        // springs of the lists being built
-  double k_t, eta_t, mu_f;
-  double dts;            // sub-step
+  double k_t, eta_t, mu_f;  // sliding and twisting, with mu_f > 0
+  double theta_r;           // rolling, with theta_r > 0 (and adhesion)
+  double dts;               // sub-step
 };
 
-// Sliding and twisting friction on body i from one contact (Eqs. 22, 28, 29),
-// each a linear spring-dashpot-slider.  n: unit normal from i to its partner;
-// vr: velocity of the partner's surface point relative to i's at the contact;
-// om: the partner's spin minus i's, along n; Fne: the JKR elastic force
-// (repulsive positive); FC = 3 pi gamma R; a: the contact radius.  h holds
-// the springs of the previous sub-step and receives the new ones; the force
-// on i is added to f and its torque about i's centre to t.  The stored
+// Sliding, twisting and rolling friction on body i from one contact (Eqs.
+// 22, 28, 29), each a linear spring-dashpot-slider.  n: unit normal from i
+// to its partner; R: the effective radius; vr: velocity of the partner's
+// surface point relative to i's at the contact; dw: i's spin minus the
+// partner's; Fne: the elastic normal force (repulsive positive);
+// FC = 3 pi gamma R; a: the contact radius, x = a / a0.  h holds the springs
+// of the previous sub-step and receives the new ones; the force on i is
+// added to f and its torque about i's centre to t.  Each stored
 // displacement is first turned into the current tangent plane, then the
-// sub-step's slip is added; a force beyond F_crit = mu_f |F_ne + 2 F_C| (a
-// moment beyond 3 pi a F_crit / 16) is capped, the spring reset to the
-// stretch that gives the capped value.
+// sub-step's motion is added.  Sliding: a force beyond
+// F_crit = mu_f |F_ne + 2 F_C| is capped, the spring reset to the stretch
+// that gives the capped value; twisting likewise beyond 3 pi a F_crit / 16.
+// Rolling: xr integrates v_L = R dw x n, clamped at |xr| = theta_crit R, and
+// acts on i with the moment k_r (xr x n), k_r = 4 F_C x^{3/2}.
 __device__ inline void contact_friction(const FricArgs& fr, double n0, double n1, double n2,
-                                        double ri, double vr0, double vr1, double vr2, double om,
-                                        double Fne, double FC, double a, double h[4], double f[3],
+                                        double ri, double R, double vr0, double vr1, double vr2,
+                                        double dw0, double dw1, double dw2, double Fne, double FC,
+                                        double a, double x, double h[SPRINGS], double f[3],
                                         double t[3]) {
+  if (fr.theta_r > 0.0 && FC > 0.0) {
+    const double c0 = dw1 * n2 - dw2 * n1, c1 = dw2 * n0 - dw0 * n2, c2 = dw0 * n1 - dw1 * n0;
+    const double hn = h[4] * n0 + h[5] * n1 + h[6] * n2;
+    double r0 = h[4] - hn * n0 + fr.dts * R * c0;
+    double r1 = h[5] - hn * n1 + fr.dts * R * c1;
+    double r2 = h[6] - hn * n2 + fr.dts * R * c2;
+    const double mag = sqrt(r0 * r0 + r1 * r1 + r2 * r2), cap = fr.theta_r * R;
+    if (mag > cap) {
+      const double sc = cap / mag;
+      r0 *= sc;
+      r1 *= sc;
+      r2 *= sc;
+    }
+    const double kr = 4.0 * FC * x * sqrt(x);
+    t[0] += kr * (r1 * n2 - r2 * n1);
+    t[1] += kr * (r2 * n0 - r0 * n2);
+    t[2] += kr * (r0 * n1 - r1 * n0);
+    h[4] = r0;
+    h[5] = r1;
+    h[6] = r2;
+  }
+  if (!(fr.mu_f > 0.0)) return;
+  const double om = -(dw0 * n0 + dw1 * n1 + dw2 * n2);
   const double vn = vr0 * n0 + vr1 * n1 + vr2 * n2;
   const double vt0 = vr0 - vn * n0, vt1 = vr1 - vn * n1, vt2 = vr2 - vn * n2;
   const double hn = h[0] * n0 + h[1] * n1 + h[2] * n2;
@@ -172,12 +211,13 @@ __device__ inline AxisNb wave_uniform(AxisNb a) {
 // slot) candidates, whose positions and velocities are the binning's records
 // (so no particle sees another's update).  Contacts are compacted into the
 // new contact list (d.next_id / d.next_n) with a ballot, and every lane
-// returns the force summed over the wave in fsum.  With FRIC, each contact
-// also carries the friction of contact_friction (walls at rest; the spins
-// are ws for i and fr->w for the partners, a 2D disk spinning about z only):
-// its springs go beside its id into fr->next_h and the torque summed over the
+// returns the force summed over the wave in fsum.  With HERTZ the normal
+// force is Hertz's (no adhesion, gamma == 0).  With FRIC, each contact also
+// carries the friction of contact_friction (walls at rest; the spins are ws
+// for i and fr->w for the partners, a 2D disk spinning about z only): its
+// springs go beside its id into fr->next_h and the torque summed over the
 // wave is returned in tsum.  Every lane of the wave must be active.
-template <bool FRIC = false>
+template <bool FRIC = false, bool HERTZ = false>
 __device__ inline void dem_contact_wave(const DemArgs& d, int i, int lane, const double* xs,
                                         const double* us, double r_i, double* fsum,
                                         const FricArgs* fr = nullptr, const double* ws = nullptr,
@@ -213,26 +253,38 @@ __device__ inline void dem_contact_wave(const DemArgs& d, int i, int lane, const
     return at;
   };
   // the springs of previous-list entry k (zero for a new contact)
-  auto load_springs = [&](int k, double h[4]) {
+  auto load_springs = [&](int k, double h[SPRINGS]) {
     if (k >= 0 && fr->prev_h) {
-      const double* hp = fr->prev_h + ((size_t)i * d.max_contacts + k) * 4;
-      for (int b = 0; b < 4; ++b) h[b] = hp[b];
+      const double* hp = fr->prev_h + ((size_t)i * d.max_contacts + k) * SPRINGS;
+      for (int b = 0; b < SPRINGS; ++b) h[b] = hp[b];
     } else {
-      for (int b = 0; b < 4; ++b) h[b] = 0.0;
+      for (int b = 0; b < SPRINGS; ++b) h[b] = 0.0;
+    }
+  };
+  // elastic normal force and delta_C, with the contact radius and x = a / a0
+  // when friction needs them
+  auto normal_force = [&](double R, double delta, double* dC, double* acon, double* xcon) {
+    if constexpr (HERTZ) {
+      *dC = 0.0;
+      *xcon = 0.0;
+      return hertz_force(R, d.E, delta, acon);
+    } else {
+      return jkr_force(R, d.E, d.gamma, delta, dC, FRIC ? acon : nullptr,
+                       FRIC ? xcon : nullptr);
     }
   };
   int* next = d.next_id + (size_t)i * d.max_contacts;
   double fs0 = 0.0, fs1 = 0.0, fs2 = 0.0;
   double tq[3] = {0.0, 0.0, 0.0};
-  double h[4] = {0.0, 0.0, 0.0, 0.0};
+  double h[SPRINGS] = {};
   auto store = [&](bool have, int id, unsigned long long m, int cnt) {
     if (have) {
       const int pos = cnt + lanes_below(m);
       if (pos < d.max_contacts) {
         next[pos] = id;
         if constexpr (FRIC) {
-          double* hn = fr->next_h + ((size_t)i * d.max_contacts + pos) * 4;
-          for (int b = 0; b < 4; ++b) hn[b] = h[b];
+          double* hn = fr->next_h + ((size_t)i * d.max_contacts + pos) * SPRINGS;
+          for (int b = 0; b < SPRINGS; ++b) hn[b] = h[b];
         }
       }
     }
@@ -262,8 +314,8 @@ __device__ inline void dem_contact_wave(const DemArgs& d, int i, int lane, const
         if (touch) {
           const double sgn = (face % 2 == 0) ? -1.0 : 1.0;  // normal towards the wall
           const double damp = d.eta_n * (-ua * sgn);
-          double dC, acon;
-          const double F = jkr_force(ri, d.E, d.gamma, delta, &dC, FRIC ? &acon : nullptr);
+          double dC, acon, xcon;
+          const double F = normal_force(ri, delta, &dC, &acon, &xcon);
           if (delta >= 0.0 || delta > -dC) {
             const double fm = (-F + damp) * sgn;
             if (a == 0) fs0 += fm;
@@ -277,11 +329,10 @@ __device__ inline void dem_contact_wave(const DemArgs& d, int i, int lane, const
               const double vr0 = -(ui0 + ri * (wi1 * n2 - wi2 * n1));
               const double vr1 = -(ui1 + ri * (wi2 * n0 - wi0 * n2));
               const double vr2 = -(ui2 + ri * (wi0 * n1 - wi1 * n0));
-              const double om = -(wi0 * n0 + wi1 * n1 + wi2 * n2);
               double f[3] = {0.0, 0.0, 0.0};
               load_springs(kp, h);
-              contact_friction(*fr, n0, n1, n2, ri, vr0, vr1, vr2, om, F,
-                               3.0 * M_PI * d.gamma * ri, acon, h, f, tq);
+              contact_friction(*fr, n0, n1, n2, ri, ri, vr0, vr1, vr2, wi0, wi1, wi2, F,
+                               3.0 * M_PI * d.gamma * ri, acon, xcon, h, f, tq);
               fs0 += f[0];
               fs1 += f[1];
               fs2 += f[2];
@@ -344,8 +395,8 @@ __device__ inline void dem_contact_wave(const DemArgs& d, int i, int lane, const
           if (d.three_d) vrn += (rc[5] - ui2) * n2;
           const double damp = d.eta_n * vrn;
           const double Reff = 1.0 / (1.0 / ri + 1.0 / rj);
-          double dC, acon;
-          const double F = jkr_force(Reff, d.E, d.gamma, delta, &dC, FRIC ? &acon : nullptr);
+          double dC, acon, xcon;
+          const double F = normal_force(Reff, delta, &dC, &acon, &xcon);
           if (delta >= 0.0 || delta > -dC) {
             const double fm = -F + damp;
             fs0 += fm * n0;
@@ -365,11 +416,10 @@ __device__ inline void dem_contact_wave(const DemArgs& d, int i, int lane, const
                                  ri * (wi2 * n0 - wi0 * n2);
               const double vr2 = (uj2 - ui2) - rj * (wj0 * n1 - wj1 * n0) -
                                  ri * (wi0 * n1 - wi1 * n0);
-              const double om = (wj0 - wi0) * n0 + (wj1 - wi1) * n1 + (wj2 - wi2) * n2;
               double f[3] = {0.0, 0.0, 0.0};
               load_springs(kp, h);
-              contact_friction(*fr, n0, n1, n2, ri, vr0, vr1, vr2, om, F,
-                               3.0 * M_PI * d.gamma * Reff, acon, h, f, tq);
+              contact_friction(*fr, n0, n1, n2, ri, Reff, vr0, vr1, vr2, wi0 - wj0, wi1 - wj1,
+                               wi2 - wj2, F, 3.0 * M_PI * d.gamma * Reff, acon, xcon, h, f, tq);
               fs0 += f[0];
               fs1 += f[1];
               fs2 += f[2];

@@ -57,7 +57,7 @@ class DemParams(ctypes.Structure):
                 ("g", ctypes.c_double * 3), ("dt", ctypes.c_double),
                 ("n_sub", ctypes.c_int), ("kinematic", ctypes.c_int),
                 ("k_t", ctypes.c_double), ("eta_t", ctypes.c_double),
-                ("mu_f", ctypes.c_double)]
+                ("mu_f", ctypes.c_double), ("theta_r", ctypes.c_double)]
 
 
 # Every symbol the header declares, with its ctypes signature.
@@ -276,7 +276,7 @@ def make_dem_params(d) -> DemParams:
     for a in range(3):
         p.g[a] = d.g[a]
     p.dt, p.n_sub, p.kinematic = d.dt, d.n_sub, int(d.kinematic)
-    p.k_t, p.eta_t, p.mu_f = d.k_t, d.eta_t, d.mu_f
+    p.k_t, p.eta_t, p.mu_f, p.theta_r = d.k_t, d.eta_t, d.mu_f, d.theta_r
     return p
 
 

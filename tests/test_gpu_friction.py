@@ -1,10 +1,11 @@
-"""GPU parity of the DEM with sliding and twisting friction (Sec. 2.5, Eqs.
-22, 28, 29) against the oracle: dem_step on a dense periodic 2D packing and a
-walled 3D box (sub-cycled), friction switched on mid-run, and coupled_step
-with friction (which makes the three calls in turn).  Tolerances as for the
-frictionless DEM: contact sums are taken in different orders on the two
-sides, so positions agree to 1e-9 and velocities and spins to 1e-11 over
-short windows.  Also the rejected friction parameters."""
+"""GPU parity of the DEM with sliding, twisting and rolling friction (Sec.
+2.5, Eqs. 22, 28, 29) and with Hertz's contact (gamma = 0) against the
+oracle: dem_step on a dense periodic 2D packing and a walled 3D box
+(sub-cycled), friction switched on mid-run, and coupled_step with friction
+or the Hertz contact (which makes the three calls in turn).  Tolerances as
+for the frictionless DEM: contact sums are taken in different orders on the
+two sides, so positions agree to 1e-9 and velocities and spins to 1e-11
+over short windows.  Also the rejected friction parameters."""
 import dataclasses
 
 import numpy as np
@@ -42,15 +43,22 @@ def _walled_3d(seed=22):
     return lat, W.Particles(x, u, w, r).copy()
 
 
+# case: (packing, DEM parameters beyond E_p = 1e-3, eta_n = 0.05)
+CASES = {
+    "2d_periodic": ("2d", dict(g=(0.0, -2e-5, 0.0), gamma=1e-5, mu_f=0.3, theta_r=0.02,
+                               **FRICTION)),
+    "3d_walls": ("3d", dict(g=(-2e-5, 0.0, 0.0), gamma=1e-5, n_sub=2, mu_f=0.05, theta_r=0.02,
+                            **FRICTION)),
+    "3d_rolling_only": ("3d", dict(g=(-2e-5, 0.0, 0.0), gamma=1e-5, theta_r=0.02)),
+    "2d_hertz_friction": ("2d", dict(g=(0.0, -2e-5, 0.0), gamma=0.0, mu_f=0.3, **FRICTION)),
+    "3d_hertz": ("3d", dict(g=(-2e-5, 0.0, 0.0), gamma=0.0)),
+}
+
+
 def _case(case):
-    if case == "2d_periodic":
-        lat, p = _dense_2d()
-        dem = W.DemSpec(g=(0.0, -2e-5, 0.0), E_p=1e-3, gamma=1e-5, eta_n=0.05, mu_f=0.3,
-                        **FRICTION)
-    else:
-        lat, p = _walled_3d()
-        dem = W.DemSpec(g=(-2e-5, 0.0, 0.0), E_p=1e-3, gamma=1e-5, eta_n=0.05, n_sub=2,
-                        mu_f=0.05, **FRICTION)
+    kind, kw = CASES[case]
+    lat, p = _dense_2d() if kind == "2d" else _walled_3d()
+    dem = W.DemSpec(E_p=1e-3, eta_n=0.05, **kw)
     rng = np.random.default_rng(5)
     F = rng.normal(0, 1e-4, (p.n, 3))
     T = rng.normal(0, 1e-4, (p.n, 3))
@@ -77,8 +85,8 @@ def _run_both(lat, p, dems, F, T):
         for _ in range(steps):
             D.step(pr, F, T)
             G.dem_step(prm, dp, Fg, Tg)
-            sprung += sum(np.abs(xi).max() > 0 for i in range(p.n)
-                          for xi, _ in D.springs(i).values())
+            sprung += sum(max(np.abs(xi).max(), np.abs(xr).max()) > 0 for i in range(p.n)
+                          for xi, _, xr in D.springs(i).values())
     G.sync()
     return pr, dp, sprung
 
@@ -89,42 +97,44 @@ def _assert_close(dp, pr):
     assert np.abs(dp.omega.cpu().numpy() - pr.omega).max() < 1e-11
 
 
-@pytest.mark.parametrize("case", ["2d_periodic", "3d_walls"])
+@pytest.mark.parametrize("case", list(CASES))
 def test_friction_dem_parity(case):
     print(f"case: {case}", flush=True)
     lat, p, dem, F, T = _case(case)
     pr, dp, sprung = _run_both(lat, p, [(dem, 150)], F, T)
-    assert sprung > 100
     _assert_close(dp, pr)
-    # friction changed the outcome well beyond the tolerance
-    plain = p.copy()
-    D0 = oracle.Dem(lat, dataclasses.replace(dem, mu_f=0.0), p.n)
-    for _ in range(150):
-        D0.step(plain, F, T)
-    assert np.abs(plain.omega - pr.omega).max() > 1e-7
+    if dem.mu_f > 0 or dem.theta_r > 0:
+        assert sprung > 100
+        # friction changed the outcome well beyond the tolerance
+        plain = p.copy()
+        D0 = oracle.Dem(lat, dataclasses.replace(dem, mu_f=0.0, theta_r=0.0), p.n)
+        for _ in range(150):
+            D0.step(plain, F, T)
+        assert np.abs(plain.omega - pr.omega).max() > 1e-7
 
 
 def test_friction_switched_on_mid_run():
     # contacts that persist into the first friction step start unloaded
     print("case: 2d_periodic off->on->off->on", flush=True)
     lat, p, dem, F, T = _case("2d_periodic")
-    off = dataclasses.replace(dem, mu_f=0.0)
+    off = dataclasses.replace(dem, mu_f=0.0, theta_r=0.0)
     pr, dp, sprung = _run_both(lat, p, [(off, 40), (dem, 40), (off, 10), (dem, 40)], F, T)
     assert sprung > 0
     _assert_close(dp, pr)
 
 
-@pytest.mark.parametrize("case", ["2d_dense", "3d_walls"])
+@pytest.mark.parametrize("case", ["2d_dense", "3d_walls", "3d_walls_hertz"])
 def test_coupled_step_with_friction(case):
     import paper_1901_09745_amd.psclbm as P
     print(f"case: coupled {case}", flush=True)
     if case == "2d_dense":
         lat, p = _dense_2d(seed=23)
-        dem = W.DemSpec(g=(0.0, -1e-5, 0.0), mu_f=0.3, **FRICTION)
+        dem = W.DemSpec(g=(0.0, -1e-5, 0.0), mu_f=0.3, theta_r=0.02, **FRICTION)
         calls = (12, 13)
     else:
         lat, p = _walled_3d(seed=24)
-        dem = W.DemSpec(g=(-1e-5, 0.0, 0.0), mu_f=0.05, **FRICTION)
+        dem = W.DemSpec(g=(-1e-5, 0.0, 0.0), mu_f=0.05, **FRICTION,
+                        **(dict(gamma=0.0) if case.endswith("hertz") else dict(theta_r=0.02)))
         calls = (15,)
     ref = oracle.Lattice(lat)
     D = oracle.Dem(lat, dem, p.n)
@@ -153,7 +163,8 @@ def test_friction_parameters_rejected():
     z = torch.zeros((2, 3), dtype=torch.float64, device="cuda")
     for bad in (dict(mu_f=0.3, k_t=0.0), dict(mu_f=-0.1, k_t=1e-3), dict(mu_f=0.3, k_t=-1e-3),
                 dict(mu_f=0.3, k_t=1e-3, eta_t=-1.0), dict(mu_f=float("inf"), k_t=1e-3),
-                dict(mu_f=0.3, k_t=float("nan"))):
+                dict(mu_f=0.3, k_t=float("nan")), dict(theta_r=-0.01),
+                dict(theta_r=float("inf"))):
         prm = P.make_dem_params(W.DemSpec(**bad))
         with pytest.raises(P.PsclbmError) as e:
             G.dem_step(prm, dp, z, z)
