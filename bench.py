@@ -202,6 +202,54 @@ def settle_packing(w, nsteps):
     return f0, ps, info
 
 
+FRICTION = {"k_t": 1e-3, "eta_t": 0.02, "mu_f": 0.3, "theta_r": 0.02}
+
+
+def run_friction(w, f0, ps, steps, warmup=5, ksteps=20):
+    """The settled 3D packing (canonical state f0, particles ps) continued in
+    the FP16 form without and with sliding, twisting and rolling friction (Eqs. 22,
+    28, 29): wall-clock ms per coupled step (the frictionless run fused, the
+    friction run as the three calls), and the DEM step alone (binning and
+    the contact kernel) between event pairs on the library's stream."""
+    import dataclasses
+    import torch
+    import paper_1901_09745_amd.psclbm as P
+
+    out = {}
+    cases = (("frictionless", w.dem), ("friction", dataclasses.replace(w.dem, **FRICTION)))
+    for label, dem in cases:
+        G = P.Lattice(w.lattice, "fp16", max_particles=ps.n, max_radius=float(ps.r.max()),
+                      max_tile_particles=64, max_contacts=16)
+        G.set_f(f0)
+        dp = P.DeviceParticles.from_host(ps)
+        prm = P.make_dem_params(dem)
+        G.coupled_step(prm, dp, warmup)
+        G.sync()
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        G.coupled_step(prm, dp, steps)
+        end.record()
+        torch.cuda.synchronize()
+        ms = start.elapsed_time(end) / steps
+        G.sync()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(ksteps)]
+        for a, b in evs:
+            a.record()
+            P.dem_step(G.ctx, prm, dp.x, dp.u, dp.omega, dp.r, None, None)
+            b.record()
+        torch.cuda.synchronize()
+        G.sync()
+        out[label] = {"ms_per_step": ms, "mlups": w.lattice.ncells / (ms * 1e-3) / 1e6,
+                      "dem_step_ms": float(np.mean([a.elapsed_time(b) for a, b in evs]))}
+        del G
+        torch.cuda.empty_cache()
+    out["params"] = dict(FRICTION)
+    out["steps"] = steps
+    return out
+
+
 def run_ergun(dps, res, weightings, chunk=500, tol=1e-6, max_steps=200_000):
     """Sec. 3.4 packed bed (8 fixed spheres in simple-cubic contact, periodic
     2 d_p cube, body force): each case run to steady state in the FP64 form
@@ -375,6 +423,9 @@ def main():
                     help="steps of the differentiable 3D packing window (0: skip)")
     ap.add_argument("--settle-steps", type=int, default=19500,
                     help="coupled steps that settle the 3D packing before its window")
+    ap.add_argument("--friction-steps", type=int, default=100,
+                    help="coupled steps of the settled 3D packing timed without and with "
+                         "friction (needs the 3D adjoint leg's packing; 0 skips)")
     ap.add_argument("--ergun-dps", default="10,20,40,80",
                     help="sphere diameters of the packed-bed (Sec. 3.4) runs ('' to skip)")
     ap.add_argument("--no-drag", action="store_true",
@@ -490,6 +541,13 @@ def main():
             _log(f"bench: settling the 3D packing for {args.settle_steps} coupled steps")
             f0, p5, settle = settle_packing(w5, args.settle_steps)
             adj["packing_3d_settle"] = settle
+            if args.friction_steps > 0:
+                _log("bench: the settled 3D packing without and with friction")
+                out["friction"] = {
+                    "workload": "the settled 3D packing (384x192x192, 20000 spheres, FP16 "
+                                "storage) continued without and with sliding, twisting and rolling "
+                                "friction",
+                    **run_friction(w5, f0, p5, args.friction_steps)}
             lowest = np.argsort(p5.x[:, 0])[:100].tolist()
             label = (f"D3Q19 tau=0.65 384x192x192, walls on x, 20000 spheres r~U(3,5) after "
                      f"{args.settle_steps} coupled steps from rest (FP16 storage, JKR DEM, "
