@@ -207,10 +207,11 @@ FRICTION = {"k_t": 1e-3, "eta_t": 0.02, "mu_f": 0.3, "theta_r": 0.02}
 
 def run_friction(w, f0, ps, steps, warmup=5, ksteps=20):
     """The settled 3D packing (canonical state f0, particles ps) continued in
-    the FP16 form without and with sliding, twisting and rolling friction (Eqs. 22,
-    28, 29): wall-clock ms per coupled step (the frictionless run fused, the
-    friction run as the three calls), and the DEM step alone (binning and
-    the contact kernel) between event pairs on the library's stream."""
+    the FP16 form without and with sliding, twisting and rolling friction
+    (Eqs. 22, 28, 29): ms per coupled step (contacts gathered by the step
+    kernel without friction, by the DEM kernel with it), and the DEM step
+    alone (binning and the contact kernel) between event pairs on the
+    library's stream."""
     import dataclasses
     import torch
     import paper_1901_09745_amd.psclbm as P
@@ -464,6 +465,18 @@ def main():
                      "step_kernel_ms": kms,
                      "step_kernel_GBs": bytes_launch / (kms * 1e-3) / 1e9}
     head = "fp32" if "fp32" in res else forms[0]
+    fric2d = None
+    if args.friction_steps > 0 and head in res:
+        import dataclasses
+        _log(f"bench: 2D coupled step with friction, form {head}")
+        w2f = dataclasses.replace(w2, dem=dataclasses.replace(w2.dem, **FRICTION))
+        ms, kms, _ = run_form(w2f, head, args.steps, args.warmup)
+        fric2d = {"workload": "the 2D benchmark workload with sliding, twisting and rolling "
+                              "friction (contacts gathered by the DEM kernel)",
+                  "form": head, "ms_per_step": ms,
+                  "mlups": w2.lattice.ncells / (ms * 1e-3) / 1e6,
+                  "frictionless_ms_per_step": res[head]["ms_per_step"],
+                  "params": dict(FRICTION)}
 
     hbm = {}
     obs3 = {}
@@ -528,6 +541,8 @@ def main():
                        **hbm} if hbm else None),
         "roofline": roof,
     }
+    if fric2d is not None:
+        out["friction"] = {"disks_2d": fric2d}
     if args.adjoint_steps > 0:
         _log("bench: adjoint of the 2D channel run")
         w4 = W.c4()
@@ -543,10 +558,10 @@ def main():
             adj["packing_3d_settle"] = settle
             if args.friction_steps > 0:
                 _log("bench: the settled 3D packing without and with friction")
-                out["friction"] = {
+                out.setdefault("friction", {})["packing_3d"] = {
                     "workload": "the settled 3D packing (384x192x192, 20000 spheres, FP16 "
-                                "storage) continued without and with sliding, twisting and rolling "
-                                "friction",
+                                "storage) continued without and with sliding, twisting and "
+                                "rolling friction",
                     **run_friction(w5, f0, p5, args.friction_steps)}
             lowest = np.argsort(p5.x[:, 0])[:100].tolist()
             label = (f"D3Q19 tau=0.65 384x192x192, walls on x, 20000 spheres r~U(3,5) after "

@@ -233,9 +233,11 @@ int dem_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double*
  * sums of contact forces.  With n_sub == 1 the work of consecutive steps is
  * fused: the DEM wave of a particle, having integrated it, writes its
  * snapshot and enters it in the tile lists and DEM bins of the next step, so
- * a step is two kernels (plus one at the start of the call); with friction
- * (mu_f > 0 or theta_r > 0) or the Hertz contact (gamma == 0) the three
- * calls are made in turn.  Afterwards the
+ * a step is two kernels (plus one at the start of the call).  Without
+ * friction and with adhesion the contacts are gathered by workgroups of the
+ * step kernel; with friction (mu_f > 0 or theta_r > 0) or the Hertz contact
+ * (gamma == 0) by the DEM kernel, which also records the spins the next
+ * step's contacts read.  Afterwards the
  * context holds the last step's rasterisation and force / torque
  * accumulators, as after the three calls.  Errors: those of psc_rasterize,
  * lbm_step and dem_step (EINVAL, EHIP; sticky ESLOTS, ECONTACTS). */

@@ -64,7 +64,7 @@ int validate(const psclbm_config* c) {
 
 struct Layout {
   size_t f, err, scalar, tile_count, tile_list, snap, facc0, facc1, mass_part, outlet_u, outlet_g;
-  size_t bin_count, bin_rec, cn0, cn1, cid0, cid1, fcont, spr0, spr1, wsnap, total;
+  size_t bin_count, bin_rec, cn0, cn1, cid0, cid1, fcont, spr0, spr1, ws0, ws1, total;
   int ntx, nty, ntz, ntiles;
   long long face_stride;
   int nbin[3];
@@ -131,7 +131,8 @@ Layout plan(const psclbm_config* c) {
   l.fcont = take(sizeof(double) * 3 * (size_t)(np > 0 ? np : 1));
   l.spr0 = take(sizeof(double) * SPRINGS * (size_t)(np > 0 ? np : 1) * mc);
   l.spr1 = take(sizeof(double) * SPRINGS * (size_t)(np > 0 ? np : 1) * mc);
-  l.wsnap = take(sizeof(double) * 3 * (size_t)(np > 0 ? np : 1));
+  l.ws0 = take(sizeof(double) * 3 * (size_t)(np > 0 ? np : 1));
+  l.ws1 = take(sizeof(double) * 3 * (size_t)(np > 0 ? np : 1));
   l.total = off;
   return l;
 }
@@ -235,7 +236,8 @@ int lbm_init(const psclbm_config* cfg, void* d_workspace, size_t bytes, void* hi
   c->fcontact = reinterpret_cast<double*>(base + l.fcont);
   c->contact_springs[0] = reinterpret_cast<double*>(base + l.spr0);
   c->contact_springs[1] = reinterpret_cast<double*>(base + l.spr1);
-  c->wsnap = reinterpret_cast<double*>(base + l.wsnap);
+  c->wsnap[0] = reinterpret_cast<double*>(base + l.ws0);
+  c->wsnap[1] = reinterpret_cast<double*>(base + l.ws1);
   // clear everything but the distributions, then set f = f^eq(rho0, 0)
   rc = launch_zero(c, base + l.err, l.total - l.err);
   if (!rc) rc = launch_init_equilibrium(c, nullptr, nullptr);

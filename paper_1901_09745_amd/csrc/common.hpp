@@ -220,7 +220,8 @@ struct psclbm_ctx {
   double* fcontact;  // [max_particles][3] contact forces of the coupled step
   double* contact_springs[2];  // per contact list: [max_particles][max_contacts][SPRINGS]
   int springs_valid;           // the current list's springs were written (friction was on)
-  double* wsnap;               // [max_particles][3] spins at the start of a friction sub-step
+  double* wsnap[2];            // [max_particles][3] spins at the start of a friction (sub-)step;
+                               // the fused coupled step alternates the two
   double* scalar;  // one FP64 device scalar for reductions
   // host-side state
   long long steps;

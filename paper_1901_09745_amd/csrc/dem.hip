@@ -18,7 +18,9 @@
 // The coupled step (n_sub = 1) gathers the contacts in leading workgroups of
 // the step kernel instead, which run beside the tiles (contacts need only
 // the binning of the step's start); its DEM kernel reads their forces,
-// integrates, and rasterises and bins the particles for the next step.
+// integrates, and rasterises and bins the particles for the next step.  With
+// friction or the Hertz contact the DEM kernel gathers the contacts itself
+// from that binning, and records the spins for the next step's contacts.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -105,6 +107,7 @@ struct NextOut {
   int* tile_list;
   int cap;
   DemBinOut db;
+  double* wnext;  // friction: the updated spins, which the next step's contacts read
   unsigned* err;
 };
 
@@ -173,6 +176,10 @@ __global__ void __launch_bounds__(256) k_dem_contacts(DemArgs d, FricArgs fr, In
     nx.snap[i] = P;
     if (!ok) atomicOr(nx.err, ERR_RADIUS);
     if (nx.db.count) dem_bin_insert(nx.db, d.three_d, nx.g, i, xs, us, ri, nx.err);
+    if constexpr (FRIC) {
+      if (nx.wnext)
+        for (int a = 0; a < 3; ++a) nx.wnext[3 * i + a] = ws[a];
+    }
   }
   if (ok) bin_tiles(nx.g, d.three_d, nx.h, P, i, lane, nx.tcount, nx.tile_list, nx.cap, nx.err);
 }
@@ -264,6 +271,43 @@ static bool dem_friction(const psclbm_dem_params* prm) {
   return prm->mu_f > 0.0 || prm->theta_r > 0.0;
 }
 
+// Friction arguments of a contact pass that reads the spins wsnap: the
+// springs of the current lists (if they were kept) and those being built.
+static FricArgs fric_args(psclbm_ctx* c, const psclbm_dem_params* prm, const double* wsnap) {
+  FricArgs fr;
+  std::memset(&fr, 0, sizeof(fr));
+  fr.w = wsnap;
+  fr.prev_h = c->springs_valid ? c->contact_springs[c->contact_cur] : nullptr;
+  fr.next_h = c->contact_springs[c->contact_cur ^ 1];
+  fr.k_t = prm->k_t;
+  fr.eta_t = prm->eta_t;
+  fr.mu_f = prm->mu_f;
+  fr.theta_r = prm->theta_r;
+  fr.dts = prm->dt / prm->n_sub;
+  return fr;
+}
+
+// k_dem_contacts in the instantiation for friction and the Hertz contact.
+static int launch_contacts(psclbm_ctx* c, bool fric, bool hertz, int n, const DemArgs& d,
+                           const FricArgs& fr, const IntArgs& ia, const NextOut& nx, double* x,
+                           double* u, double* w, const double* r, const double* F,
+                           const double* T, const double* fc_in) {
+  const dim3 grid((n + 3) / 4), block(256);
+  if (fric && hertz)
+    k_dem_contacts<true, true><<<grid, block, 0, c->stream>>>(d, fr, ia, nx, x, u, w, r, F, T,
+                                                             fc_in);
+  else if (fric)
+    k_dem_contacts<true, false><<<grid, block, 0, c->stream>>>(d, fr, ia, nx, x, u, w, r, F, T,
+                                                              fc_in);
+  else if (hertz)
+    k_dem_contacts<false, true><<<grid, block, 0, c->stream>>>(d, fr, ia, nx, x, u, w, r, F, T,
+                                                              fc_in);
+  else
+    k_dem_contacts<false, false><<<grid, block, 0, c->stream>>>(d, fr, ia, nx, x, u, w, r, F,
+                                                               T, fc_in);
+  return hip_ok(hipGetLastError());
+}
+
 int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, double* u, double* w,
                     const double* r, int n, const double* F, const double* T) {
   IntArgs ia = int_args(c, prm, n, F, T);
@@ -282,41 +326,16 @@ int launch_dem_step(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doub
   NextOut nx;
   std::memset(&nx, 0, sizeof(nx));
   const bool fric = dem_friction(prm), hertz = prm->gamma == 0.0;
-  FricArgs fr;
-  std::memset(&fr, 0, sizeof(fr));
-  fr.w = c->wsnap;
-  fr.k_t = prm->k_t;
-  fr.eta_t = prm->eta_t;
-  fr.mu_f = prm->mu_f;
-  fr.theta_r = prm->theta_r;
-  fr.dts = prm->dt / prm->n_sub;
   for (int s = 0; s < prm->n_sub; ++s) {
     ia.wrap = s == prm->n_sub - 1;  // positions wrap once, after the last sub-step
     const DemBinOut b = dem_bin_out(c, true);
     const long long bth = b.nbins > n ? b.nbins : n;
     k_dem_bin<<<(unsigned)((bth + 127) / 128), 128, 0, c->stream>>>(
-        b, c->geom, n, c->geom.q == 19, x, u, r, c->err, w, fric ? c->wsnap : nullptr);
+        b, c->geom, n, c->geom.q == 19, x, u, r, c->err, w, fric ? c->wsnap[0] : nullptr);
     dem_bins_advance(c);
     const DemArgs d = dem_args(c, prm, n, E);
-    if (fric) {
-      // springs of the previous lists only if they were kept (friction on)
-      fr.prev_h = c->springs_valid ? c->contact_springs[c->contact_cur] : nullptr;
-      fr.next_h = c->contact_springs[c->contact_cur ^ 1];
-    }
-    const dim3 grid((n + 3) / 4), block(256);
-    if (fric && hertz)
-      k_dem_contacts<true, true><<<grid, block, 0, c->stream>>>(d, fr, ia, nx, x, u, w, r, F, T,
-                                                               nullptr);
-    else if (fric)
-      k_dem_contacts<true, false><<<grid, block, 0, c->stream>>>(d, fr, ia, nx, x, u, w, r, F, T,
-                                                                nullptr);
-    else if (hertz)
-      k_dem_contacts<false, true><<<grid, block, 0, c->stream>>>(d, fr, ia, nx, x, u, w, r, F, T,
-                                                                nullptr);
-    else
-      k_dem_contacts<false, false><<<grid, block, 0, c->stream>>>(d, fr, ia, nx, x, u, w, r, F,
-                                                                 T, nullptr);
-    int rc = hip_ok(hipGetLastError());
+    const FricArgs fr = fric_args(c, prm, c->wsnap[0]);
+    const int rc = launch_contacts(c, fric, hertz, n, d, fr, ia, nx, x, u, w, r, F, T, nullptr);
     if (rc) return rc;
     c->contact_cur ^= 1;
     c->springs_valid = fric ? 1 : 0;
@@ -338,9 +357,8 @@ int launch_coupled(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doubl
     E = dem_modulus(c, prm);
     if (!(E > 0.0)) return PSCLBM_EINVAL;
   }
-  if (prm->n_sub != 1 || n == 0 ||
-      (!prm->kinematic && (dem_friction(prm) || prm->gamma == 0.0))) {
-    // sub-cycled DEM, friction or the Hertz contact: the three calls in turn
+  if (prm->n_sub != 1 || n == 0) {
+    // sub-cycled DEM: the three calls in turn
     for (int t = 0; t < nsteps; ++t) {
       int rc = launch_rasterize(c, p, false);
       if (!rc) c->np = n;
@@ -351,15 +369,23 @@ int launch_coupled(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doubl
     }
     return PSCLBM_OK;
   }
-  // first step's rasterisation, with its DEM binning
+  // with friction or the Hertz contact the DEM kernel gathers the contacts
+  const bool fric = !prm->kinematic && dem_friction(prm);
+  const bool hertz = !prm->kinematic && prm->gamma == 0.0;
+  const bool own_contacts = prm->kinematic || fric || hertz;
+  // first step's rasterisation, with its DEM binning (and spins)
   int rc = launch_rasterize(c, p, !prm->kinematic);
+  if (!rc && fric)
+    rc = hip_ok(hipMemcpyAsync(c->wsnap[0], w, sizeof(double) * 3 * (size_t)n,
+                               hipMemcpyDeviceToDevice, c->stream));
   if (rc) return rc;
   c->np = n;
   const size_t ntiles = (size_t)c->ntiles;
+  int wcur = 0;  // the spin snapshot of the current step's start
   for (int t = 0; t < nsteps; ++t) {
     // the step, with the contact workgroups on the binning of its start
     const DemArgs d = dem_args(c, prm, n, E);
-    rc = prm->kinematic ? launch_step(c) : launch_step_contacts(c, &d, x, u, r);
+    rc = own_contacts ? launch_step(c) : launch_step_contacts(c, &d, x, u, r);
     if (rc) return rc;
     const bool build = t + 1 < nsteps;
     const double* F = nullptr;
@@ -377,17 +403,17 @@ int launch_coupled(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doubl
     nx.tile_list = c->tile_list;
     nx.cap = c->cfg.max_tile_particles;
     nx.db = dem_bin_out(c, build && !prm->kinematic);
+    nx.wnext = build && fric ? c->wsnap[wcur ^ 1] : nullptr;
     nx.err = c->err;
-    FricArgs fr;
-    std::memset(&fr, 0, sizeof(fr));
-    k_dem_contacts<false, false><<<(n + 3) / 4, 256, 0, c->stream>>>(
-        d, fr, ia, nx, x, u, w, r, F, T, prm->kinematic ? nullptr : c->fcontact);
-    rc = hip_ok(hipGetLastError());
+    const FricArgs fr = fric_args(c, prm, c->wsnap[wcur]);
+    rc = launch_contacts(c, fric, hertz, n, d, fr, ia, nx, x, u, w, r, F, T,
+                         own_contacts ? nullptr : c->fcontact);
     if (rc) return rc;
     if (!prm->kinematic) {
       c->contact_cur ^= 1;
-      c->springs_valid = 0;
+      c->springs_valid = fric ? 1 : 0;
     }
+    wcur ^= 1;
     if (build) {
       c->tile_cur ^= 1;
       c->tile_count = c->tile_count_buf[c->tile_cur];

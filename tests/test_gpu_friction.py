@@ -152,6 +152,39 @@ def test_coupled_step_with_friction(case):
     _assert_close(dp, pr)
 
 
+def test_coupled_and_separate_steps_mixed():
+    # fused coupled calls and separate rasterize / step / dem_step calls share
+    # the contact lists and springs; a frictionless call in between leaves
+    # the springs unloaded on both sides
+    import paper_1901_09745_amd.psclbm as P
+    print("case: coupled/separate mix, 2d_dense", flush=True)
+    lat, p = _dense_2d(seed=23)
+    fric = W.DemSpec(g=(0.0, -1e-5, 0.0), mu_f=0.3, theta_r=0.02, **FRICTION)
+    plain = dataclasses.replace(fric, mu_f=0.0, theta_r=0.0)
+    ref = oracle.Lattice(lat)
+    D = oracle.Dem(lat, fric, p.n)
+    pr = p.copy()
+    G = gpu_lattice(lat, p)
+    dp = P.DeviceParticles.from_host(p)
+    for dem, k, fused in ((fric, 8, True), (fric, 4, False), (fric, 6, True), (plain, 3, True),
+                          (fric, 5, True), (fric, 3, False)):
+        D.params = oracle.make_dem(dem)
+        prm = P.make_dem_params(dem)
+        for _ in range(k):
+            F_ref, T_ref = ref.step(pr)
+            D.step(pr, F_ref, T_ref)
+        if fused:
+            G.coupled_step(prm, dp, k)
+        else:
+            for _ in range(k):
+                G.rasterize(dp)
+                G.step(1)
+                G.dem_step(prm, dp)
+    G.sync()
+    assert relerr(G.get_f().cpu().numpy(), ref.f) < 1e-11
+    _assert_close(dp, pr)
+
+
 def test_friction_parameters_rejected():
     import paper_1901_09745_amd.psclbm as P
     lat = W.LatticeSpec(q=9, nx=64, ny=32)
