@@ -251,6 +251,86 @@ def run_friction(w, f0, ps, steps, warmup=5, ksteps=20):
     return out
 
 
+def packing_stats(x, r, L, periodic, reach=0.0):
+    """Packing fraction and coordination number of a bed settled along -x
+    onto the wall at x = -1/2: phi is the solid fraction of the slab from 2d
+    above the wall to 2d below the bed's top (the highest sphere surface),
+    Z the mean number of sphere-sphere contacts (centres closer than
+    r_i + r_j + reach, nearest image on periodic axes) of the spheres whose
+    centres lie in that slab."""
+    x = np.asarray(x, dtype=np.float64)
+    r = np.asarray(r, dtype=np.float64)
+    d = 2.0 * float(r.max())
+    lo = -0.5 + 2.0 * d
+    hi = float((x[:, 0] + r).max()) - 2.0 * d
+    if hi <= lo:
+        return {"phi": None, "Z": None, "slab": [lo, hi]}
+    # volume of each sphere between the planes x = lo and x = hi
+    a = np.clip(lo - x[:, 0], -r, r)
+    b = np.clip(hi - x[:, 0], -r, r)
+    vol = np.pi * ((r ** 2) * (b - a) - (b ** 3 - a ** 3) / 3.0)
+    phi = float(vol.sum() / ((hi - lo) * L[1] * L[2]))
+    dv = x[None, :, :] - x[:, None, :]
+    for ax in (1, 2):
+        if periodic[ax]:
+            dv[:, :, ax] -= L[ax] * np.round(dv[:, :, ax] / L[ax])
+    dist = np.sqrt((dv ** 2).sum(axis=2))
+    touch = dist < (r[:, None] + r[None, :] + reach)
+    np.fill_diagonal(touch, False)
+    inside = (x[:, 0] > lo) & (x[:, 0] < hi)
+    Z = float(touch[inside].sum(axis=1).mean()) if inside.any() else None
+    return {"phi": phi, "Z": Z, "slab": [lo, hi], "spheres_in_slab": int(inside.sum())}
+
+
+def run_packing(steps, chunk=10000, precision="fp32"):
+    """Sec. 3.5: the 500-sphere random packing settled from a random
+    placement, adhesive (JKR) and non-adhesive (Hertz), both with sliding,
+    twisting and rolling friction; phi and Z every chunk steps."""
+    import torch
+    import paper_1901_09745_amd.psclbm as P
+    import workloads as W
+
+    out = {}
+    for adhesive in (True, False):
+        w = W.random_packing(adhesive)
+        lat, p, dem = w.lattice, w.particles, w.dem
+        G = P.Lattice(lat, precision, max_particles=p.n, max_radius=float(p.r.max()),
+                      max_tile_particles=64, max_contacts=dem.max_contacts)
+        dp = P.DeviceParticles.from_host(p)
+        prm = P.make_dem_params(dem)
+        # bonded pairs reach down to -delta_C (Eq. 27 with R = r/2)
+        R = float(p.r[0]) / 2.0
+        Es = dem.E_p / (2.0 * (1.0 - dem.poisson ** 2))
+        a0 = (9.0 * np.pi * dem.gamma * R * R / Es) ** (1.0 / 3.0)
+        reach = a0 * a0 / (2.0 * 6.0 ** (1.0 / 3.0) * R)
+        hist = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        done = 0
+        while done < steps:
+            k = min(chunk, steps - done)
+            G.coupled_step(prm, dp, k)
+            done += k
+            G.sync()
+            st = packing_stats(dp.x.cpu().numpy(), p.r, (lat.nx, lat.ny, lat.nz),
+                               (False, True, True), reach)
+            umax = float(dp.u.abs().max())
+            umean = float(dp.u.norm(dim=1).mean())
+            hist.append({"step": done, "phi": st["phi"], "Z": st["Z"], "u_max": umax,
+                         "u_mean": umean})
+            _log(f"bench: packing {'adhesive' if adhesive else 'Hertz'} step {done}: "
+                 f"phi={st['phi']}, Z={st['Z']}, u_max={umax:.2e}, u_mean={umean:.2e}")
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        out["adhesive" if adhesive else "non_adhesive"] = {
+            "phi": hist[-1]["phi"], "Z": hist[-1]["Z"], "history": hist,
+            "ms_per_step": ms, "contact_reach": reach}
+        del G
+        torch.cuda.empty_cache()
+    out["paper"] = {"adhesive": {"phi": 0.495, "Z": 5.08},
+                    "non_adhesive": {"phi": 0.557, "Z": 5.50}}
+    return out
+
+
 def run_ergun(dps, res, weightings, chunk=500, tol=1e-6, max_steps=200_000):
     """Sec. 3.4 packed bed (8 fixed spheres in simple-cubic contact, periodic
     2 d_p cube, body force): each case run to steady state in the FP64 form
@@ -427,6 +507,8 @@ def main():
     ap.add_argument("--friction-steps", type=int, default=100,
                     help="coupled steps of the settled 3D packing timed without and with "
                          "friction (needs the 3D adjoint leg's packing; 0 skips)")
+    ap.add_argument("--packing-steps", type=int, default=60000,
+                    help="coupled steps of the Sec. 3.5 random packings (0 skips)")
     ap.add_argument("--ergun-dps", default="10,20,40,80",
                     help="sphere diameters of the packed-bed (Sec. 3.4) runs ('' to skip)")
     ap.add_argument("--no-drag", action="store_true",
@@ -583,6 +665,12 @@ def main():
                         "contact, periodic 2d_p cube, D3Q19 tau=0.65, body force from Eq. 35 "
                         "at the target Re_p*, FP64, run to steady state",
             "runs": run_ergun(dps, (1.0, 10.0), ("modified", "original"))}
+    if args.packing_steps > 0:
+        out["packing"] = {
+            "workload": "Sec. 3.5 random packing: 500 spheres d=6 settling in a 100x50x50 box "
+                        "(walls on x, periodic y and z), D3Q19 tau=2, gravity 8e-4 along -x, "
+                        "JKR (gamma=0.128) or Hertz, sliding/twisting/rolling friction, FP32",
+            **run_packing(args.packing_steps)}
     if not args.no_drag:
         out["drag"] = {
             "workload": "Sec. 3.2 fixed sphere at the centre of a 20d x 10d x 10d box, D3Q19, "
