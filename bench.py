@@ -244,6 +244,20 @@ def run_friction(w, f0, ps, steps, warmup=5, ksteps=20):
         G.sync()
         out[label] = {"ms_per_step": ms, "mlups": w.lattice.ncells / (ms * 1e-3) / 1e6,
                       "dem_step_ms": float(np.mean([a.elapsed_time(b) for a, b in evs]))}
+        if label == "frictionless":
+            # the adjoint of one DEM step (its contact set held), event-timed
+            before = P.DeviceParticles(dp.x.clone(), dp.u.clone(), dp.omega.clone(), dp.r)
+            P.dem_step(G.ctx, prm, dp.x, dp.u, dp.omega, dp.r, None, None)
+            g = [torch.randn_like(dp.x) for _ in range(3)]
+            evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+                   for _ in range(ksteps)]
+            for a, b in evs:
+                a.record()
+                G.dem_step_adjoint(prm, before, *g)
+                b.record()
+            torch.cuda.synchronize()
+            G.sync()
+            out[label]["dem_step_adjoint_ms"] = float(np.mean([a.elapsed_time(b) for a, b in evs]))
         del G
         torch.cuda.empty_cache()
     out["params"] = dict(FRICTION)

@@ -244,6 +244,25 @@ int dem_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double*
 int coupled_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double* d_u,
                  double* d_omega, const double* d_radius, int n, int nsteps);
 
+/* Adjoint of the DEM step just taken (Sec. 2.5, Eq. 21 with Eqs. 25-27; the
+ * most recent dem_step, or the last step of coupled_step, with no DEM call
+ * since): given dJ/d(x', u', omega') of the step's result (d_gx, d_gu, d_gw,
+ * [3n] each), writes dJ/d(x, u, omega) of its input (d_ax, d_au, d_aw) and
+ * dJ/d(force, torque) of the hydrodynamic force and torque it was driven by
+ * (d_aF, d_aT), all [3n], none aliasing an input.  d_x, d_u, d_omega,
+ * d_radius: the particle state before the step (a copy the caller kept;
+ * omega is not read).  The step's contact set is held fixed: the contact
+ * lists the step formed are read, and the jump-on / pull-off switches
+ * contribute nothing.  Frictionless steps with n_sub == 1 only (JKR or
+ * Hertz, normal damping, gravity).  2D: the out-of-plane parts of
+ * d_aF and the in-plane parts of d_aT are zero.  Errors: EINVAL (bad
+ * params, friction, n_sub != 1, kinematic, n > max_particles, null
+ * pointers), EHIP. */
+int dem_step_adjoint(psclbm_ctx* ctx, const psclbm_dem_params* prm, const double* d_x,
+                     const double* d_u, const double* d_omega, const double* d_radius, int n,
+                     const double* d_gx, const double* d_gu, const double* d_gw, double* d_ax,
+                     double* d_au, double* d_aw, double* d_aF, double* d_aT);
+
 /* Forget all DEM contacts (no pair is bonded). */
 int dem_reset_contacts(psclbm_ctx* ctx);
 

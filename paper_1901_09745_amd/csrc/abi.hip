@@ -8,6 +8,14 @@
 
 #include "common.hpp"
 
+namespace psclbm {
+// Adjoint of the DEM step just taken (dem.hip).
+int launch_dem_adjoint(psclbm_ctx* c, const psclbm_dem_params* prm, const double* x,
+                       const double* u, const double* r, int n, const double* gx,
+                       const double* gu, const double* gw, double* ax, double* au, double* aw,
+                       double* aF, double* aT);
+}  // namespace psclbm
+
 using namespace psclbm;
 
 namespace {
@@ -373,6 +381,23 @@ int coupled_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, dou
   ctx->np = n;
   ctx->rasterized = 1;
   return PSCLBM_OK;
+}
+
+int dem_step_adjoint(psclbm_ctx* ctx, const psclbm_dem_params* prm, const double* d_x,
+                     const double* d_u, const double* d_omega, const double* d_radius, int n,
+                     const double* d_gx, const double* d_gu, const double* d_gw, double* d_ax,
+                     double* d_au, double* d_aw, double* d_aF, double* d_aT) {
+  if (!ctx || !prm) return PSCLBM_EINVAL;
+  if (n < 0 || n > ctx->cfg.max_particles) return PSCLBM_EINVAL;
+  if (n == 0) return PSCLBM_OK;
+  if (!d_x || !d_u || !d_omega || !d_radius || !d_gx || !d_gu || !d_gw || !d_ax || !d_au ||
+      !d_aw || !d_aF || !d_aT)
+    return PSCLBM_EINVAL;
+  if (prm->kinematic || prm->n_sub != 1 || !(prm->dt > 0.0) || !std::isfinite(prm->dt) ||
+      !dem_material_ok(prm) || prm->mu_f != 0.0 || prm->theta_r != 0.0)
+    return PSCLBM_EINVAL;
+  return launch_dem_adjoint(ctx, prm, d_x, d_u, d_radius, n, d_gx, d_gu, d_gw, d_ax, d_au, d_aw,
+                            d_aF, d_aT);
 }
 
 int dem_reset_contacts(psclbm_ctx* ctx) {

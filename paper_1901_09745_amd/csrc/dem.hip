@@ -423,4 +423,141 @@ int launch_coupled(psclbm_ctx* c, const psclbm_dem_params* prm, double* x, doubl
   return PSCLBM_OK;
 }
 
+
+// ------------------------------------------------------------------------
+// Adjoint of one frictionless DEM step (n_sub = 1) with its contact set held
+// fixed (the jump-on / pull-off switches contribute nothing).  With
+// s_i = dt/m_i (du'_i + dt dx'_i), the adjoint of the contact force of i, and
+// the pair force g_ij = (-F(delta) + eta_n (u_j - u_i).n) n = -g_ji:
+//   dx_i = dx'_i + sum_j (d g_ij / d x_i)^T (s_i - s_j),
+//   du_i = du'_i + dt dx'_i + sum_j (d g_ij / d u_i)^T (s_i - s_j),
+// where walls take s_j = 0; dF = s, dT = dt/I dw', dw = dw'.
+// ------------------------------------------------------------------------
+
+// dF/d delta of the elastic normal force at overlap delta (x = a/a0 from the
+// force evaluation).  JKR: F = 4 F_C (x^3 - x^{3/2}) and
+// delta = delta_C 6^{1/3} (2 x^2 - 4/3 x^{1/2}), so the slope is the ratio
+// of their x-derivatives; zero where the branch is clamped at pull-off.
+// Hertz (gamma = 0): (3/2) (4/3) E sqrt(R) delta^{1/2}.
+__device__ inline double normal_slope(double R, double E, double gamma, double delta, double x) {
+  if (gamma == 0.0) return delta > 0.0 ? 2.0 * E * sqrt(R) * sqrt(delta) : 0.0;
+  const double c6 = 1.8171205928321397;  // 6^{1/3}
+  const double FC = 3.0 * M_PI * gamma * R;
+  const double a0 = cbrt(9.0 * M_PI * gamma * R * R / E);
+  const double dc = a0 * a0 / (2.0 * c6 * R);
+  const double sC = 1.0 / c6;
+  if ((delta / dc) / c6 <= 2.0 * sC * sC * sC * sC - (4.0 / 3.0) * sC) return 0.0;
+  const double sx = sqrt(x);
+  return 4.0 * FC * (3.0 * x * x - 1.5 * sx) / (dc * c6 * (4.0 * x - (2.0 / 3.0) / sx));
+}
+
+// One thread per particle: s_i (written as dF), dT and dw.
+__global__ void k_dem_adj_seed(IntArgs p, const double* r, const double* gx, const double* gu,
+                               const double* gw, double* aF, double* aT, double* aw) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= p.n) return;
+  const int D = p.three_d ? 3 : 2;
+  const double ri = r[i];
+  const double V = p.three_d ? (4.0 / 3.0) * M_PI * ri * ri * ri : M_PI * ri * ri;
+  const double m = p.rho_p * V;
+  const double I = p.three_d ? 0.4 * m * ri * ri : 0.5 * m * ri * ri;
+  for (int a = 0; a < 3; ++a) {
+    const double up = gu[3 * i + a] + (a < D ? p.dt * gx[3 * i + a] : 0.0);
+    aF[3 * i + a] = a < D ? p.dt * up / m : 0.0;
+    aT[3 * i + a] = (p.three_d || a == 2) ? p.dt * gw[3 * i + a] / I : 0.0;
+    aw[3 * i + a] = gw[3 * i + a];
+  }
+}
+
+// One wave per particle, one lane per contact of the step's list (at most 64).
+__global__ void __launch_bounds__(256) k_dem_adj_gather(DemArgs d, IntArgs p, const double* x,
+                                                        const double* u, const double* r,
+                                                        const double* gx, const double* gu,
+                                                        const double* s, double* ax,
+                                                        double* au) {
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = (int)(gid >> 6);
+  const int lane = (int)(threadIdx.x & 63);
+  if (i >= d.n) return;  // uniform over the wave
+  const int D = d.three_d ? 3 : 2;
+  int cnt = d.prev_n[i];
+  if (cnt > d.max_contacts) cnt = d.max_contacts;
+  double bx[3] = {0.0, 0.0, 0.0}, bu[3] = {0.0, 0.0, 0.0};
+  if (lane < cnt) {
+    const int id = d.prev_id[(size_t)i * d.max_contacts + lane];
+    const double ri = r[i];
+    // (partners outside this call's particles or walls of other lattices,
+    // as a list left by a larger step could hold, are skipped)
+    if (id < 0 && -1 - id < 2 * D) {  // wall: n = sgn e_a, d delta / d x_a = sgn, s_j = 0
+      const int face = -1 - id, a = face / 2;
+      const double xa = x[3 * i + a];
+      const double dist = (face % 2 == 0) ? xa + 0.5 : (d.L[a] - 0.5) - xa;
+      const double delta = ri - dist;
+      double dC, acon, xcon = 0.0;
+      if (d.gamma == 0.0) hertz_force(ri, d.E, delta, &acon);
+      else jkr_force(ri, d.E, d.gamma, delta, &dC, &acon, &xcon);
+      const double Fp = normal_slope(ri, d.E, d.gamma, delta, xcon);
+      const double v = s[3 * i + a];
+      bx[a] = -Fp * v;
+      bu[a] = -d.eta_n * v;
+    } else if (id >= 0 && id < d.n) {
+      const int j = id;
+      double dv[3], du[3], v[3];
+      for (int a = 0; a < 3; ++a) {
+        const bool on = a < D;
+        dv[a] = on ? min_img(x[3 * j + a] - x[3 * i + a], d.periodic[a], d.L[a]) : 0.0;
+        du[a] = on ? u[3 * j + a] - u[3 * i + a] : 0.0;
+        v[a] = on ? s[3 * i + a] - s[3 * j + a] : 0.0;
+      }
+      const double rho = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
+      const double n0 = dv[0] / rho, n1 = dv[1] / rho, n2 = dv[2] / rho;
+      const double rj = r[j];
+      const double delta = ri + rj - rho;
+      const double Reff = 1.0 / (1.0 / ri + 1.0 / rj);
+      double dC, acon, xcon = 0.0, F;
+      if (d.gamma == 0.0) F = hertz_force(Reff, d.E, delta, &acon);
+      else F = jkr_force(Reff, d.E, d.gamma, delta, &dC, &acon, &xcon);
+      const double Fp = normal_slope(Reff, d.E, d.gamma, delta, xcon);
+      const double dun = du[0] * n0 + du[1] * n1 + du[2] * n2;
+      const double phi = -F + d.eta_n * dun;
+      const double vn = v[0] * n0 + v[1] * n1 + v[2] * n2;
+      const double nn[3] = {n0, n1, n2};
+      for (int a = 0; a < 3; ++a) {
+        const double Pdu = du[a] - dun * nn[a], Pv = v[a] - vn * nn[a];
+        bx[a] = (-Fp * nn[a] - d.eta_n * Pdu / rho) * vn - phi * Pv / rho;
+        bu[a] = -d.eta_n * nn[a] * vn;
+      }
+    }
+  }
+  for (int a = 0; a < 3; ++a) {
+    bx[a] = wave_sum(bx[a]);
+    bu[a] = wave_sum(bu[a]);
+  }
+  if (lane == 0) {
+    for (int a = 0; a < 3; ++a) {
+      const double gxa = gx[3 * i + a];
+      ax[3 * i + a] = gxa + bx[a];
+      au[3 * i + a] = gu[3 * i + a] + (a < D ? p.dt * gxa : 0.0) + bu[a];
+    }
+  }
+}
+
+int launch_dem_adjoint(psclbm_ctx* c, const psclbm_dem_params* prm, const double* x,
+                       const double* u, const double* r, int n, const double* gx,
+                       const double* gu, const double* gw, double* ax, double* au, double* aw,
+                       double* aF, double* aT) {
+  const double E = dem_modulus(c, prm);
+  if (!(E > 0.0)) return PSCLBM_EINVAL;
+  const double* F = nullptr;
+  const double* T = nullptr;
+  const IntArgs ia = int_args(c, prm, n, F, T);
+  // the contact lists of the step just taken are the current ones
+  const DemArgs d = dem_args(c, prm, n, E);
+  k_dem_adj_seed<<<(n + 127) / 128, 128, 0, c->stream>>>(ia, r, gx, gu, gw, aF, aT, aw);
+  int rc = hip_ok(hipGetLastError());
+  if (rc) return rc;
+  k_dem_adj_gather<<<(n + 3) / 4, 256, 0, c->stream>>>(d, ia, x, u, r, gx, gu, aF, ax, au);
+  return hip_ok(hipGetLastError());
+}
+
 }  // namespace psclbm

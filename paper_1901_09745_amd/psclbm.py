@@ -77,6 +77,8 @@ SIGNATURES = {
     "particle_forces": (_I, [_VP, _VP, _VP]),
     "dem_step": (_I, [_VP, ctypes.POINTER(DemParams), _VP, _VP, _VP, _VP, _I, _VP, _VP]),
     "dem_reset_contacts": (_I, [_VP]),
+    "dem_step_adjoint": (_I, [_VP, ctypes.POINTER(DemParams), _VP, _VP, _VP, _VP, _I, _VP, _VP,
+                              _VP, _VP, _VP, _VP, _VP, _VP]),
     "lbm_mass": (_I, [_VP, ctypes.POINTER(_D)]),
     "psclbm_sync": (_I, [_VP]),
     "psclbm_strerror": (ctypes.c_char_p, [_I]),
@@ -191,6 +193,16 @@ def dem_step(ctx: int, prm: DemParams, x: torch.Tensor, u: torch.Tensor, omega: 
              torque: Optional[torch.Tensor]) -> None:
     _check(load().dem_step(ctx, ctypes.byref(prm), _ptr(x), _ptr(u), _ptr(omega), _ptr(radius),
                            radius.numel(), _ptr(force), _ptr(torque)), "dem_step")
+
+
+def dem_step_adjoint(ctx: int, prm: DemParams, x: torch.Tensor, u: torch.Tensor,
+                     omega: torch.Tensor, radius: torch.Tensor, gx: torch.Tensor,
+                     gu: torch.Tensor, gw: torch.Tensor, ax: torch.Tensor, au: torch.Tensor,
+                     aw: torch.Tensor, aF: torch.Tensor, aT: torch.Tensor) -> None:
+    _check(load().dem_step_adjoint(ctx, ctypes.byref(prm), _ptr(x), _ptr(u), _ptr(omega),
+                                   _ptr(radius), radius.numel(), _ptr(gx), _ptr(gu), _ptr(gw),
+                                   _ptr(ax), _ptr(au), _ptr(aw), _ptr(aF), _ptr(aT)),
+           "dem_step_adjoint")
 
 
 def coupled_step(ctx: int, prm: DemParams, x: torch.Tensor, u: torch.Tensor, omega: torch.Tensor,
@@ -376,6 +388,14 @@ class Lattice:
 
     def dem_step(self, dem_params: DemParams, p: DeviceParticles, F=None, T=None) -> None:
         dem_step(self.ctx, dem_params, p.x, p.u, p.omega, p.r, F, T)
+
+    def dem_step_adjoint(self, dem_params: DemParams, before: DeviceParticles, gx, gu, gw):
+        """Adjoint of the DEM step just taken from the state ``before``: given
+        dJ/d(x', u', omega'), returns dJ/d(x, u, omega, force, torque)."""
+        outs = [torch.empty_like(gx) for _ in range(5)]
+        dem_step_adjoint(self.ctx, dem_params, before.x, before.u, before.omega, before.r,
+                         gx.contiguous(), gu.contiguous(), gw.contiguous(), *outs)
+        return tuple(outs)
 
     def coupled_step(self, dem_params: DemParams, p: DeviceParticles, nsteps: int = 1) -> None:
         coupled_step(self.ctx, dem_params, p.x, p.u, p.omega, p.r, nsteps)

@@ -13,7 +13,8 @@ import workloads as W
 from oracle import torch_dem
 
 
-def _case(name):
+def _start(name):
+    """The seeded initial state of a case: lat, dem, particles, F, T."""
     if name.startswith("2d"):
         lat = W.LatticeSpec(q=9, nx=64, ny=48, faces=(W.PERIODIC, W.PERIODIC, W.BOUNCE_BACK,
                                                        W.BOUNCE_BACK, W.PERIODIC, W.PERIODIC))
@@ -36,8 +37,16 @@ def _case(name):
     p = W.Particles(x, u, rng.normal(0.0, 1e-4, (len(r), 3)), r)
     F = rng.normal(0.0, 1e-4, (len(r), 3))
     T = rng.normal(0.0, 1e-4, (len(r), 3))
+    return lat, dem, p, F, T
+
+
+SETTLE = 300                                # steps into contacts, walls and pairs
+
+
+def _case(name):
+    lat, dem, p, F, T = _start(name)
     D = oracle.Dem(lat, dem, p.n)
-    for _ in range(300):                    # settle into contacts, walls and pairs
+    for _ in range(SETTLE):
         D.step(p, F, T)
     return lat, dem, p, F, T, D
 
