@@ -237,10 +237,10 @@ int dem_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double*
  * friction and with adhesion the contacts are gathered by workgroups of the
  * step kernel; with friction (mu_f > 0 or theta_r > 0) or the Hertz contact
  * (gamma == 0) by the DEM kernel, which also records the spins the next
- * step's contacts read.  Afterwards the
- * context holds the last step's rasterisation and force / torque
- * accumulators, as after the three calls.  Errors: those of psc_rasterize,
- * lbm_step and dem_step (EINVAL, EHIP; sticky ESLOTS, ECONTACTS). */
+ * step's contacts read.  Afterwards the context holds the last step's
+ * rasterisation and force / torque accumulators, as after the three calls.
+ * Errors: those of psc_rasterize, lbm_step and dem_step (EINVAL, EHIP;
+ * sticky ESLOTS, ECONTACTS). */
 int coupled_step(psclbm_ctx* ctx, const psclbm_dem_params* prm, double* d_x, double* d_u,
                  double* d_omega, const double* d_radius, int n, int nsteps);
 
