@@ -59,6 +59,58 @@ def test_dem_step_adjoint_matches_autograd(name):
         assert np.abs(got - want).max() <= 1e-10 * scale, (k, np.abs(got - want).max(), scale)
 
 
+def test_adjoint_of_the_last_coupled_step():
+    # coupled_step gathers the contacts in the step kernel; the adjoint of
+    # its last DEM step reads those lists, with that step's fluid force
+    import paper_1901_09745_amd.psclbm as P
+    import workloads as W
+    print("case: dem adjoint after coupled_step, 3d lattice block", flush=True)
+    # a jittered block of spheres whose neighbours and bottom row overlap by
+    # 0.02, so contacts are loaded from the first step
+    lat = W.LatticeSpec(q=19, nx=32, ny=24, nz=24,
+                        faces=(W.BOUNCE_BACK, W.BOUNCE_BACK) + (W.PERIODIC,) * 4)
+    rng = np.random.default_rng(12)
+    pts = [[2.48 + i * 5.98, 6.0 + j * 5.98, 6.0 + m * 5.98]
+           for i in range(2) for j in range(3) for m in range(3)]
+    n = len(pts)
+    p = W.Particles(np.array(pts) + rng.normal(0.0, 0.005, (n, 3)),
+                    rng.normal(0.0, 1e-3, (n, 3)), rng.normal(0.0, 2e-4, (n, 3)), np.full(n, 3.0))
+    dem = W.DemSpec(g=(-2e-4, 0.0, 0.0), E_p=1e-3, gamma=1e-5, eta_n=0.05)
+    ref = oracle.Lattice(lat)
+    D = oracle.Dem(lat, dem, p.n)
+    pr = p.copy()
+    k = 20
+    for t in range(k):
+        if t == k - 1:
+            before_h = pr.copy()
+        F_ref, T_ref = ref.step(pr)
+        D.step(pr, F_ref, T_ref)
+    contacts = D.contacts()
+    assert sum(len(c) for c in contacts) > 4
+    G = gpu_lattice(lat, p)
+    dp = P.DeviceParticles.from_host(p)
+    prm = P.make_dem_params(dem)
+    G.coupled_step(prm, dp, k - 1)
+    before = P.DeviceParticles(dp.x.clone(), dp.u.clone(), dp.omega.clone(), dp.r)
+    G.coupled_step(prm, dp, 1)
+    G.sync()
+    assert np.abs(dp.x.cpu().numpy() - pr.x).max() < 1e-9
+    rng = np.random.default_rng(11)
+    a, b, c = (rng.normal(size=(p.n, 3)) for _ in range(3))
+    outs = G.dem_step_adjoint(prm, before, *(torch.from_numpy(m).cuda() for m in (a, b, c)))
+    G.sync()
+    ins = [_t(before_h.x), _t(before_h.u), _t(before_h.omega), _t(F_ref), _t(T_ref)]
+    X, U, Wt = torch_dem.dem_step(lat, dem, *ins[:3], list(before_h.r), ins[3], ins[4], contacts)
+    J = sum((torch.from_numpy(m) * v).sum() for m, v in ((a, X), (b, U), (c, Wt)))
+    ref_g = torch.autograd.grad(J, ins)
+    for kk, (got, want) in enumerate(zip(outs, ref_g)):
+        got, want = got.cpu().numpy(), want.numpy()
+        scale = max(np.abs(want).max(), 1e-300)
+        # the GPU's pre-step state differs from the oracle's by the rounding of
+        # the 39 coupled steps before it
+        assert np.abs(got - want).max() <= 1e-7 * scale, (kk, np.abs(got - want).max(), scale)
+
+
 def test_dem_step_adjoint_rejects_what_it_does_not_cover():
     import dataclasses
     import paper_1901_09745_amd.psclbm as P
