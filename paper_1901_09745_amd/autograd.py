@@ -108,3 +108,23 @@ def psc_drag(x, u, omega, face_velocity, spec, radius, steps: int, checkpoint_ev
     `steps` steps, differentiable in x, u, omega and the face velocities."""
     return PscDrag.apply(x, u, omega, face_velocity, spec, radius, steps, checkpoint_every,
                          window, precision, f0, max_tile_particles)
+
+
+def coupled_step_vjp(G, dem_params, f_t: torch.Tensor, before, lam_f: torch.Tensor,
+                     g_x: torch.Tensor, g_u: torch.Tensor, g_omega: torch.Tensor):
+    """Vector-Jacobian product of the coupled step just taken on the lattice
+    ``G`` (rasterise, lbm_step, dem_step driven by that step's force and
+    torque; coupled_step(1) or the three calls, frictionless with n_sub = 1)
+    from the canonical FP64 state ``f_t`` and the particle state ``before``
+    (a DeviceParticles copy kept from before the step).  Given
+    dJ/d(f', x', u', omega') of the step's result, returns
+    dJ/d(f, x, u, omega) of its input, with the moving particles: the DEM
+    step's adjoint (contacts held) gives the sensitivities of the force and
+    torque, which seed lbm_step_adjoint, whose particle sensitivities
+    (through the solid fractions, the rigid-body velocities and the torque
+    arms) add to the DEM's."""
+    ax, au, aw, aF, aT = G.dem_step_adjoint(dem_params, before, g_x, g_u, g_omega)
+    lam_t = torch.empty_like(lam_f)
+    P.lbm_step_adjoint(G.ctx, f_t.contiguous(), lam_f.contiguous(), lam_t, aF, aT, ax, au, aw,
+                       None)
+    return lam_t, ax, au, aw

@@ -1,0 +1,93 @@
+"""GPU vector-Jacobian product of one coupled step with moving particles
+(autograd.coupled_step_vjp: dem_step_adjoint seeding lbm_step_adjoint)
+against torch autograd of the two pinned oracle statements composed
+(oracle/torch_step.py, then oracle/torch_dem.py with the oracle's contact
+set): dJ/d(f, x, u, omega) for J a random functional of the state after
+the step.  The case is a jittered block of disks resting on a wall in
+fluid, their neighbours and bottom row overlapping by 0.02; GPU and oracle
+run in lockstep, then the GPU steps from the oracle's state exactly."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads as W
+from helpers import gpu_lattice, relerr
+from oracle import torch_dem, torch_step
+
+pytestmark = pytest.mark.gpu
+
+
+def _block_2d(seed=13):
+    lat = W.LatticeSpec(q=9, nx=64, ny=48, tau=0.8,
+                        faces=(W.PERIODIC, W.PERIODIC, W.BOUNCE_BACK, W.BOUNCE_BACK,
+                               W.PERIODIC, W.PERIODIC))
+    rng = np.random.default_rng(seed)
+    pts = [[10.0 + i * 9.98, 4.48 + j * 9.98, 0.0] for i in range(4) for j in range(2)]
+    n = len(pts)
+    x = np.array(pts) + rng.normal(0.0, 0.005, (n, 3))
+    x[:, 2] = 0.0
+    u = rng.normal(0.0, 1e-3, (n, 3))
+    u[:, 2] = 0.0
+    w = np.zeros((n, 3))
+    w[:, 2] = rng.normal(0.0, 2e-4, n)
+    dem = W.DemSpec(g=(0.0, -2e-4, 0.0), E_p=1e-3, gamma=1e-5, eta_n=0.05)
+    return lat, W.Particles(x, u, w, np.full(n, 5.0)), dem
+
+
+def test_coupled_step_vjp_matches_autograd():
+    import paper_1901_09745_amd.psclbm as P
+    from paper_1901_09745_amd.autograd import coupled_step_vjp
+    print("case: coupled step vjp, 2d disk block", flush=True)
+    lat, p, dem = _block_2d()
+    ref = oracle.Lattice(lat)
+    D = oracle.Dem(lat, dem, p.n)
+    pr = p.copy()
+    G = gpu_lattice(lat, p)
+    dp = P.DeviceParticles.from_host(p)
+    prm = P.make_dem_params(dem)
+    for _ in range(10):
+        F_ref, T_ref = ref.step(pr)
+        D.step(pr, F_ref, T_ref)
+        G.coupled_step(prm, dp, 1)
+    G.sync()
+    assert np.abs(dp.x.cpu().numpy() - pr.x).max() < 1e-9
+    # the step from the oracle's state exactly
+    f_t = np.array(ref.f, copy=True)          # ref.step overwrites ref.f in place
+    G.set_f(torch.from_numpy(f_t).cuda())
+    for t, a in ((dp.x, pr.x), (dp.u, pr.u), (dp.omega, pr.omega)):
+        t.copy_(torch.from_numpy(a))
+    before = P.DeviceParticles(dp.x.clone(), dp.u.clone(), dp.omega.clone(), dp.r)
+    p_t = pr.copy()
+    G.coupled_step(prm, dp, 1)
+    F_ref, T_ref = ref.step(pr)
+    D.step(pr, F_ref, T_ref)
+    contacts = D.contacts()
+    assert sum(len(c) for c in contacts) > 8
+    G.sync()
+    assert relerr(G.get_f().cpu().numpy(), ref.f) < 1e-12
+    assert np.abs(dp.x.cpu().numpy() - pr.x).max() < 1e-12
+    # J = lam . f' + a . x' + b . u' + c . omega'
+    rng = np.random.default_rng(17)
+    lam = rng.normal(size=f_t.shape)
+    a, b, c = (rng.normal(size=(p.n, 3)) for _ in range(3))
+    a[:, 2] = b[:, 2] = 0.0
+    c[:, :2] = 0.0
+    dev = [torch.from_numpy(np.ascontiguousarray(m)).cuda() for m in (lam, a, b, c)]
+    out = coupled_step_vjp(G, prm, torch.from_numpy(f_t).cuda(), before, *dev)
+    G.sync()
+    q = 9
+    ft = torch.tensor(f_t.reshape(q, -1), dtype=torch.float64, requires_grad=True)
+    X, U, Wt = (torch.tensor(m, dtype=torch.float64, requires_grad=True)
+                for m in (p_t.x, p_t.u, p_t.omega))
+    geo = torch_step.Geometry(lat)
+    f1, F, T = torch_step.step(geo, ft, X, U, Wt, p_t.r, torch.zeros((6, 3), dtype=torch.float64))
+    X1, U1, W1 = torch_dem.dem_step(lat, dem, X, U, Wt, list(p_t.r), F, T, contacts)
+    J = (torch.from_numpy(lam.reshape(q, -1)) * f1).sum() + sum(
+        (torch.from_numpy(m) * v).sum() for m, v in ((a, X1), (b, U1), (c, W1)))
+    want = torch.autograd.grad(J, [ft, X, U, Wt])
+    for k, (got, w) in enumerate(zip(out, want)):
+        got = got.cpu().numpy().reshape(w.shape)
+        w = w.numpy()
+        scale = max(np.abs(w).max(), 1e-300)
+        assert np.abs(got - w).max() <= 1e-10 * scale, (k, np.abs(got - w).max(), scale)
