@@ -266,6 +266,19 @@ int dem_step_adjoint(psclbm_ctx* ctx, const psclbm_dem_params* prm, const double
 /* Forget all DEM contacts (no pair is bonded). */
 int dem_reset_contacts(psclbm_ctx* ctx);
 
+/* Copy the current DEM contact lists, those the most recent DEM step formed
+ * (Sec. 2.5: the bonds of the jump-on / pull-off hysteresis), to caller
+ * device buffers: d_count[max_particles] contacts per particle and
+ * d_ids[max_particles * max_contacts] partner ids (particles, walls -1-face),
+ * each particle's first d_count entries valid.  dem_set_contacts copies such
+ * lists back as the current ones (friction springs are not saved: contacts
+ * restored this way start unloaded).  Together they let a reverse pass put
+ * back the contact set of the step it differentiates (dem_step_adjoint reads
+ * the current lists).  Asynchronous on the context's stream.  Errors:
+ * EINVAL (null pointers), EHIP. */
+int dem_get_contacts(psclbm_ctx* ctx, int* d_count, int* d_ids);
+int dem_set_contacts(psclbm_ctx* ctx, const int* d_count, const int* d_ids);
+
 /* Synchronise the stream and return the total mass sum_n sum_i f_i of the
  * current state in FP64 (*h_mass), or the sticky error if one is set
  * (ENONFINITE if the mass is not finite). */

@@ -128,3 +128,56 @@ def coupled_step_vjp(G, dem_params, f_t: torch.Tensor, before, lam_f: torch.Tens
     P.lbm_step_adjoint(G.ctx, f_t.contiguous(), lam_f.contiguous(), lam_t, aF, aT, ax, au, aw,
                        None)
     return lam_t, ax, au, aw
+
+
+class CoupledRun(torch.autograd.Function):
+    """``steps`` coupled steps with moving particles (rasterise, lbm_step,
+    frictionless dem_step with n_sub = 1, in FP64) from the fluid state
+    ``f0`` (canonical FP64) and the particle state (x, u, omega); returns the
+    final particle state and fluid state.  The backward walks the steps in
+    reverse with coupled_step_vjp, from per-step checkpoints: the FP64 state
+    entering the step, the particle state, and the contact lists the step
+    formed (put back with dem_set_contacts, since the DEM adjoint reads the
+    current lists).  Memory: one canonical FP64 state per step."""
+
+    @staticmethod
+    def forward(ctx, x, u, omega, f0, spec, radius, dem_spec, steps: int):
+        n = x.shape[0]
+        G = P.Lattice(spec, "fp64", max_particles=n, max_radius=float(radius.max()),
+                      max_tile_particles=64, max_contacts=dem_spec.max_contacts)
+        G.set_f(f0.detach().contiguous())
+        dp = P.DeviceParticles(x.detach().clone(), u.detach().clone(), omega.detach().clone(),
+                               radius)
+        prm = P.make_dem_params(dem_spec)
+        ckpt = []
+        for _ in range(steps):
+            f_t = G.get_f()
+            before = P.DeviceParticles(dp.x.clone(), dp.u.clone(), dp.omega.clone(), dp.r)
+            G.coupled_step(prm, dp, 1)
+            ckpt.append((f_t, before) + G.get_contacts())
+        f_end = G.get_f()
+        G.sync()
+        ctx.G, ctx.prm, ctx.ckpt = G, prm, ckpt
+        return dp.x.clone(), dp.u.clone(), dp.omega.clone(), f_end
+
+    @staticmethod
+    def backward(ctx, gx, gu, gw, gf):
+        G, prm = ctx.G, ctx.prm
+        z = lambda t, like: (t if t is not None else torch.zeros_like(like)).contiguous()
+        f_t0, before0 = ctx.ckpt[0][0], ctx.ckpt[0][1]
+        lam_x, lam_u, lam_w = z(gx, before0.x), z(gu, before0.u), z(gw, before0.omega)
+        lam_f = z(gf, f_t0)
+        for f_t, before, cnt, ids in reversed(ctx.ckpt):
+            G.set_contacts(cnt, ids)
+            G.rasterize(before)
+            lam_f, lam_x, lam_u, lam_w = coupled_step_vjp(G, prm, f_t, before, lam_f, lam_x,
+                                                          lam_u, lam_w)
+        G.sync()
+        ctx.G = ctx.ckpt = None
+        return lam_x, lam_u, lam_w, lam_f, None, None, None, None
+
+
+def coupled_run(x, u, omega, f0, spec, radius, dem_spec, steps: int):
+    """Final (x, u, omega, f) after `steps` coupled steps with moving
+    particles, differentiable in x, u, omega and f0."""
+    return CoupledRun.apply(x, u, omega, f0, spec, radius, dem_spec, steps)

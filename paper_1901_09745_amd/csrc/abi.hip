@@ -405,6 +405,33 @@ int dem_reset_contacts(psclbm_ctx* ctx) {
   return launch_dem_reset(ctx);
 }
 
+int dem_get_contacts(psclbm_ctx* ctx, int* d_count, int* d_ids) {
+  if (!ctx || !d_count || !d_ids) return PSCLBM_EINVAL;
+  const size_t np = (size_t)ctx->cfg.max_particles;
+  if (np == 0) return PSCLBM_OK;
+  const size_t mc = (size_t)ctx->cfg.max_contacts;
+  int rc = hip_ok(hipMemcpyAsync(d_count, ctx->contact_n[ctx->contact_cur], sizeof(int) * np,
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+  if (!rc)
+    rc = hip_ok(hipMemcpyAsync(d_ids, ctx->contact_id[ctx->contact_cur], sizeof(int) * np * mc,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+  return rc;
+}
+
+int dem_set_contacts(psclbm_ctx* ctx, const int* d_count, const int* d_ids) {
+  if (!ctx || !d_count || !d_ids) return PSCLBM_EINVAL;
+  const size_t np = (size_t)ctx->cfg.max_particles;
+  if (np == 0) return PSCLBM_OK;
+  const size_t mc = (size_t)ctx->cfg.max_contacts;
+  int rc = hip_ok(hipMemcpyAsync(ctx->contact_n[ctx->contact_cur], d_count, sizeof(int) * np,
+                                 hipMemcpyDeviceToDevice, ctx->stream));
+  if (!rc)
+    rc = hip_ok(hipMemcpyAsync(ctx->contact_id[ctx->contact_cur], d_ids, sizeof(int) * np * mc,
+                               hipMemcpyDeviceToDevice, ctx->stream));
+  ctx->springs_valid = 0;  // springs are not part of the saved lists
+  return rc;
+}
+
 int lbm_mass(psclbm_ctx* ctx, double* h_mass) {
   if (!ctx || !h_mass) return PSCLBM_EINVAL;
   int rc = launch_mass(ctx, h_mass);

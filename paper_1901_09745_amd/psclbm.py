@@ -77,6 +77,8 @@ SIGNATURES = {
     "particle_forces": (_I, [_VP, _VP, _VP]),
     "dem_step": (_I, [_VP, ctypes.POINTER(DemParams), _VP, _VP, _VP, _VP, _I, _VP, _VP]),
     "dem_reset_contacts": (_I, [_VP]),
+    "dem_get_contacts": (_I, [_VP, _VP, _VP]),
+    "dem_set_contacts": (_I, [_VP, _VP, _VP]),
     "dem_step_adjoint": (_I, [_VP, ctypes.POINTER(DemParams), _VP, _VP, _VP, _VP, _I, _VP, _VP,
                               _VP, _VP, _VP, _VP, _VP, _VP]),
     "lbm_mass": (_I, [_VP, ctypes.POINTER(_D)]),
@@ -388,6 +390,20 @@ class Lattice:
 
     def dem_step(self, dem_params: DemParams, p: DeviceParticles, F=None, T=None) -> None:
         dem_step(self.ctx, dem_params, p.x, p.u, p.omega, p.r, F, T)
+
+    def get_contacts(self):
+        """The current DEM contact lists: (counts (max_particles,), ids
+        (max_particles, max_contacts)) int32 device tensors."""
+        n, mc = max(self.cfg.max_particles, 1), self.cfg.max_contacts
+        cnt = torch.empty(n, dtype=torch.int32, device="cuda")
+        ids = torch.empty((n, mc), dtype=torch.int32, device="cuda")
+        _check(load().dem_get_contacts(self.ctx, _ptr(cnt, torch.int32), _ptr(ids, torch.int32)),
+               "dem_get_contacts")
+        return cnt, ids
+
+    def set_contacts(self, cnt: torch.Tensor, ids: torch.Tensor) -> None:
+        _check(load().dem_set_contacts(self.ctx, _ptr(cnt, torch.int32), _ptr(ids, torch.int32)),
+               "dem_set_contacts")
 
     def dem_step_adjoint(self, dem_params: DemParams, before: DeviceParticles, gx, gu, gw):
         """Adjoint of the DEM step just taken from the state ``before``: given

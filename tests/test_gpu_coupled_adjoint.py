@@ -91,3 +91,57 @@ def test_coupled_step_vjp_matches_autograd():
         w = w.numpy()
         scale = max(np.abs(w).max(), 1e-300)
         assert np.abs(got - w).max() <= 1e-10 * scale, (k, np.abs(got - w).max(), scale)
+
+
+def test_coupled_run_gradient_matches_autograd():
+    # autograd.coupled_run over six steps with moving particles: dJ/d(x0,
+    # u0, omega0, f0) for J a random functional of the final state, against
+    # torch autograd of the oracle statements over the same six steps (each
+    # with the contact set the C oracle formed)
+    import paper_1901_09745_amd.psclbm as P
+    from paper_1901_09745_amd.autograd import coupled_run
+    print("case: coupled run gradient, 2d disk block, 6 steps", flush=True)
+    lat, p, dem = _block_2d(seed=14)
+    K = 6
+    ref = oracle.Lattice(lat)
+    f0 = np.array(ref.f, copy=True)
+    D = oracle.Dem(lat, dem, p.n)
+    pr = p.copy()
+    contacts = []
+    for _ in range(K):
+        F_ref, T_ref = ref.step(pr)
+        D.step(pr, F_ref, T_ref)
+        contacts.append(D.contacts())
+    assert all(sum(len(c) for c in cs) > 8 for cs in contacts)
+    dev = lambda m: torch.tensor(np.ascontiguousarray(m), dtype=torch.float64, device="cuda",
+                                 requires_grad=True)
+    xs = [dev(m) for m in (p.x, p.u, p.omega, f0)]
+    r = torch.from_numpy(np.ascontiguousarray(p.r)).cuda()
+    X, U, Wt, f = coupled_run(*xs, lat, r, dem, K)
+    assert np.abs(X.detach().cpu().numpy() - pr.x).max() < 1e-12
+    assert relerr(f.detach().cpu().numpy(), ref.f) < 1e-12
+    rng = np.random.default_rng(19)
+    lam = rng.normal(size=f0.shape)
+    a, b, c = (rng.normal(size=(p.n, 3)) for _ in range(3))
+    a[:, 2] = b[:, 2] = 0.0
+    c[:, :2] = 0.0
+    J = sum((torch.from_numpy(m).cuda() * v).sum()
+            for m, v in ((a, X), (b, U), (c, Wt), (lam, f)))
+    got = torch.autograd.grad(J, xs)
+    q = 9
+    ft = torch.tensor(f0.reshape(q, -1), dtype=torch.float64, requires_grad=True)
+    Xt, Ut, Wtt = (torch.tensor(m, dtype=torch.float64, requires_grad=True)
+                   for m in (p.x, p.u, p.omega))
+    geo = torch_step.Geometry(lat)
+    fh, Xh, Uh, Wh = ft, Xt, Ut, Wtt
+    for k in range(K):
+        fh, F, T = torch_step.step(geo, fh, Xh, Uh, Wh, p.r, torch.zeros((6, 3), dtype=torch.float64))
+        Xh, Uh, Wh = torch_dem.dem_step(lat, dem, Xh, Uh, Wh, list(p.r), F, T, contacts[k])
+    Jh = (torch.from_numpy(lam.reshape(q, -1)) * fh).sum() + sum(
+        (torch.from_numpy(m) * v).sum() for m, v in ((a, Xh), (b, Uh), (c, Wh)))
+    want = torch.autograd.grad(Jh, [Xt, Ut, Wtt, ft])
+    for k, (g, w) in enumerate(zip(got, want)):
+        g = g.cpu().numpy().reshape(w.shape)
+        w = w.numpy()
+        scale = max(np.abs(w).max(), 1e-300)
+        assert np.abs(g - w).max() <= 1e-9 * scale, (k, np.abs(g - w).max(), scale)
