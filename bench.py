@@ -173,6 +173,41 @@ def run_adjoint(lat, p, steps, every, label, select, precision="fp64", f0=None):
             "backward_ms_per_step": bwd / steps}
 
 
+def run_coupled_gradient(w, steps):
+    """Gradient of a coupled run with moving particles (autograd.coupled_run:
+    forward with a checkpoint per step, backward through dem_step_adjoint
+    and lbm_step_adjoint), FP64, J = the mean x of the particles at the end:
+    wall-clock forward and backward, each measured on a second call."""
+    import torch
+    import paper_1901_09745_amd.psclbm as P
+    from paper_1901_09745_amd.autograd import coupled_run
+
+    p = w.particles
+    G = P.Lattice(w.lattice, "fp64", max_particles=p.n, max_radius=float(p.r.max()))
+    f0 = G.get_f()                              # the equilibrium at rest
+    del G
+    r = torch.from_numpy(np.ascontiguousarray(p.r)).cuda()
+    res = None
+    for _ in range(2):
+        xs = [torch.tensor(np.ascontiguousarray(m), dtype=torch.float64, device="cuda",
+                           requires_grad=True) for m in (p.x, p.u, p.omega)]
+        fin = f0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        X, _, _, _ = coupled_run(*xs, fin, w.lattice, r, w.dem, steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        grads = torch.autograd.grad(X[:, 0].mean(), xs + [fin])
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        res = {"steps": steps, "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
+               "ratio": (t2 - t1) / (t1 - t0),
+               "dJ_dx_norm": float(grads[0].norm()), "dJ_df0_norm": float(grads[3].norm())}
+        del X, grads
+    torch.cuda.empty_cache()
+    return res
+
+
 def settle_packing(w, nsteps):
     """The 3D packing after nsteps coupled steps from rest (FP16 storage, JKR
     DEM, gravity): its canonical FP64 state and particle state."""
@@ -642,6 +677,8 @@ def main():
     if args.adjoint_steps > 0:
         _log("bench: adjoint of the 2D channel run")
         w4 = W.c4()
+        _log("bench: gradient of a 2D coupled run with moving particles")
+        adj_run = run_coupled_gradient(w2, 100)
         adj = {"channel_2d": run_adjoint(
             w4.lattice, w4.particles, args.adjoint_steps, 100,
             "D2Q9 tau=0.8 512x256 channel from rest, equilibrium inlet u=0.02, outlet rho=1, "
@@ -670,6 +707,10 @@ def main():
                     w5.lattice, p5, args.adjoint_3d_steps, 50, label, lowest, precision=prec,
                     f0=f0)
             del f0
+        adj["coupled_run_2d"] = {
+            "workload": "the 2D benchmark workload (1024x1024, 2000 JKR disks), 100 coupled "
+                        "steps with moving particles, FP64, J = mean final x",
+            **adj_run}
         adj["ratio"] = adj["channel_2d"]["ratio"]
         out["adjoint"] = adj
     dps = [int(v) for v in args.ergun_dps.split(",") if v.strip()]
