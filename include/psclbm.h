@@ -12,7 +12,14 @@
  *     equation (Sec. 2.1-2.3, Eqs. 1-6, 10, 12-13) with the per-particle
  *     hydrodynamic force and torque of Eq. 14 and a global FP64 mass sum;
  *   - dem_step: the adhesive DEM step with the JKR normal force and
- *     Newton-Euler motion (Sec. 2.5, Eqs. 21, 25-27).
+ *     Newton-Euler motion (Sec. 2.5, Eqs. 21, 25-27), optionally with the
+ *     sliding, twisting and rolling friction of Eqs. 22, 28, 29, or with
+ *     Hertz's contact without adhesion;
+ *   - coupled_step: rasterise, step and DEM for many steps, fused;
+ *   - adjoints: lbm_step_adjoint (with lbm_recompute and
+ *     psc_rasterize_adjoint) for the lattice step, and dem_step_adjoint for a
+ *     frictionless DEM step, which chain into gradients through coupled runs
+ *     with moving particles.
  *
  * Conventions shared by every call:
  *   - All array arguments named d_* are DEVICE pointers; h_* are host pointers.
