@@ -567,9 +567,8 @@ def main():
                          "scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only; --gpus {args.gpus} is not "
-              "supported (the multi-GPU domain decomposition is a design, not built)",
-              file=sys.stderr)
+        print(f"bench.py: one GPU is measured; --gpus {args.gpus} is not supported (the "
+              "multi-GPU domain decomposition is designed, not implemented)", file=sys.stderr)
         sys.exit(2)
 
     import torch
