@@ -173,10 +173,11 @@ def run_adjoint(lat, p, steps, every, label, select, precision="fp64", f0=None):
             "backward_ms_per_step": bwd / steps}
 
 
-def run_coupled_gradient(w, steps):
+def run_coupled_gradient(w, steps, every=10):
     """Gradient of a coupled run with moving particles (autograd.coupled_run:
-    forward with a checkpoint per step, backward through dem_step_adjoint
-    and lbm_step_adjoint), FP64, J = the mean x of the particles at the end:
+    forward with a checkpoint every `every` steps, backward replaying each
+    segment and walking it back through dem_step_adjoint and
+    lbm_step_adjoint), FP64, J = the mean x of the particles at the end:
     wall-clock forward and backward, each measured on a second call."""
     import torch
     import paper_1901_09745_amd.psclbm as P
@@ -194,13 +195,14 @@ def run_coupled_gradient(w, steps):
         fin = f0.clone().requires_grad_(True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        X, _, _, _ = coupled_run(*xs, fin, w.lattice, r, w.dem, steps)
+        X, _, _, _ = coupled_run(*xs, fin, w.lattice, r, w.dem, steps, checkpoint_every=every)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         grads = torch.autograd.grad(X[:, 0].mean(), xs + [fin])
         torch.cuda.synchronize()
         t2 = time.perf_counter()
-        res = {"steps": steps, "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
+        res = {"steps": steps, "checkpoint_every": every,
+               "forward_ms": (t1 - t0) * 1e3, "backward_ms": (t2 - t1) * 1e3,
                "ratio": (t2 - t1) / (t1 - t0),
                "dJ_dx_norm": float(grads[0].norm()), "dJ_df0_norm": float(grads[3].norm())}
         del X, grads

@@ -134,14 +134,18 @@ class CoupledRun(torch.autograd.Function):
     """``steps`` coupled steps with moving particles (rasterise, lbm_step,
     frictionless dem_step with n_sub = 1, in FP64) from the fluid state
     ``f0`` (canonical FP64) and the particle state (x, u, omega); returns the
-    final particle state and fluid state.  The backward walks the steps in
-    reverse with coupled_step_vjp, from per-step checkpoints: the FP64 state
-    entering the step, the particle state, and the contact lists the step
-    formed (put back with dem_set_contacts, since the DEM adjoint reads the
-    current lists).  Memory: one canonical FP64 state per step."""
+    final particle state and fluid state.  The forward keeps, every
+    ``checkpoint_every`` steps, the FP64 state, the particle state and the
+    contact lists in force before that step (dem_get_contacts).  The
+    backward replays each segment from its checkpoint (dem_set_contacts puts
+    its lists back), keeping the state, particles and formed contact lists
+    of every step of the segment, and walks them in reverse with
+    coupled_step_vjp.  Memory: steps / checkpoint_every + checkpoint_every
+    canonical FP64 states."""
 
     @staticmethod
-    def forward(ctx, x, u, omega, f0, spec, radius, dem_spec, steps: int):
+    def forward(ctx, x, u, omega, f0, spec, radius, dem_spec, steps: int,
+                checkpoint_every: int = 32):
         n = x.shape[0]
         G = P.Lattice(spec, "fp64", max_particles=n, max_radius=float(radius.max()),
                       max_tile_particles=64, max_contacts=dem_spec.max_contacts)
@@ -149,35 +153,50 @@ class CoupledRun(torch.autograd.Function):
         dp = P.DeviceParticles(x.detach().clone(), u.detach().clone(), omega.detach().clone(),
                                radius)
         prm = P.make_dem_params(dem_spec)
-        ckpt = []
-        for _ in range(steps):
-            f_t = G.get_f()
-            before = P.DeviceParticles(dp.x.clone(), dp.u.clone(), dp.omega.clone(), dp.r)
+        k = max(1, int(checkpoint_every))
+        segs = []
+        for t in range(steps):
+            if t % k == 0:
+                segs.append((t, G.get_f(), _copy(dp)) + G.get_contacts())
             G.coupled_step(prm, dp, 1)
-            ckpt.append((f_t, before) + G.get_contacts())
         f_end = G.get_f()
         G.sync()
-        ctx.G, ctx.prm, ctx.ckpt = G, prm, ckpt
+        ctx.G, ctx.prm, ctx.segs, ctx.steps, ctx.k = G, prm, segs, steps, k
         return dp.x.clone(), dp.u.clone(), dp.omega.clone(), f_end
 
     @staticmethod
     def backward(ctx, gx, gu, gw, gf):
         G, prm = ctx.G, ctx.prm
+        _, f_first, p_first, _, _ = ctx.segs[0]
         z = lambda t, like: (t if t is not None else torch.zeros_like(like)).contiguous()
-        f_t0, before0 = ctx.ckpt[0][0], ctx.ckpt[0][1]
-        lam_x, lam_u, lam_w = z(gx, before0.x), z(gu, before0.u), z(gw, before0.omega)
-        lam_f = z(gf, f_t0)
-        for f_t, before, cnt, ids in reversed(ctx.ckpt):
-            G.set_contacts(cnt, ids)
-            G.rasterize(before)
-            lam_f, lam_x, lam_u, lam_w = coupled_step_vjp(G, prm, f_t, before, lam_f, lam_x,
-                                                          lam_u, lam_w)
+        lam_x, lam_u, lam_w = z(gx, p_first.x), z(gu, p_first.u), z(gw, p_first.omega)
+        lam_f = z(gf, f_first)
+        for t0, f_c, p_c, cnt_c, ids_c in reversed(ctx.segs):
+            # replay the segment, keeping what each of its steps needs
+            G.set_f(f_c)
+            dq = _copy(p_c)
+            G.set_contacts(cnt_c, ids_c)
+            ring = []
+            for _ in range(t0, min(ctx.steps, t0 + ctx.k)):
+                f_t = G.get_f()
+                before = _copy(dq)
+                G.coupled_step(prm, dq, 1)
+                ring.append((f_t, before) + G.get_contacts())
+            for f_t, before, cnt, ids in reversed(ring):
+                G.set_contacts(cnt, ids)
+                G.rasterize(before)
+                lam_f, lam_x, lam_u, lam_w = coupled_step_vjp(G, prm, f_t, before, lam_f,
+                                                              lam_x, lam_u, lam_w)
         G.sync()
-        ctx.G = ctx.ckpt = None
-        return lam_x, lam_u, lam_w, lam_f, None, None, None, None
+        ctx.G = ctx.segs = None
+        return lam_x, lam_u, lam_w, lam_f, None, None, None, None, None
 
 
-def coupled_run(x, u, omega, f0, spec, radius, dem_spec, steps: int):
+def _copy(p):
+    return P.DeviceParticles(p.x.clone(), p.u.clone(), p.omega.clone(), p.r)
+
+
+def coupled_run(x, u, omega, f0, spec, radius, dem_spec, steps: int, checkpoint_every: int = 32):
     """Final (x, u, omega, f) after `steps` coupled steps with moving
     particles, differentiable in x, u, omega and f0."""
-    return CoupledRun.apply(x, u, omega, f0, spec, radius, dem_spec, steps)
+    return CoupledRun.apply(x, u, omega, f0, spec, radius, dem_spec, steps, checkpoint_every)

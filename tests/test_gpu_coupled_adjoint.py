@@ -145,3 +145,12 @@ def test_coupled_run_gradient_matches_autograd():
         w = w.numpy()
         scale = max(np.abs(w).max(), 1e-300)
         assert np.abs(g - w).max() <= 1e-9 * scale, (k, np.abs(g - w).max(), scale)
+    # the checkpoint interval changes memory, not the gradient
+    for every in (1, 4):
+        xs2 = [dev(m) for m in (p.x, p.u, p.omega, f0)]
+        X2, U2, W2, f2 = coupled_run(*xs2, lat, r, dem, K, checkpoint_every=every)
+        J2 = sum((torch.from_numpy(m).cuda() * v).sum()
+                 for m, v in ((a, X2), (b, U2), (c, W2), (lam, f2)))
+        got2 = torch.autograd.grad(J2, xs2)
+        for g1, g2 in zip(got, got2):
+            assert (g1 - g2).abs().max() <= 1e-12 * g1.abs().max()
