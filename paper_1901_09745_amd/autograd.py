@@ -146,6 +146,10 @@ class CoupledRun(torch.autograd.Function):
     @staticmethod
     def forward(ctx, x, u, omega, f0, spec, radius, dem_spec, steps: int,
                 checkpoint_every: int = 32):
+        if (dem_spec.mu_f or dem_spec.theta_r or dem_spec.n_sub != 1 or dem_spec.kinematic
+                or steps < 1):
+            raise ValueError("coupled_run differentiates frictionless DEM steps with n_sub = 1 "
+                             "and at least one step")
         n = x.shape[0]
         G = P.Lattice(spec, "fp64", max_particles=n, max_radius=float(radius.max()),
                       max_tile_particles=64, max_contacts=dem_spec.max_contacts)
