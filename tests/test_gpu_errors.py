@@ -62,14 +62,20 @@ def test_invalid_radius_is_sticky_einval():
     assert e.value.code == P.EINVAL
 
 
-def test_contact_overflow():
+@pytest.mark.parametrize("kind", ["jkr", "friction", "hertz"])
+def test_contact_overflow(kind):
+    # particle 0 touches two others with room for one contact: the contact
+    # kernel (in each instantiation) keeps the first and raises ECONTACTS
     P = _P()
+    print(f"case: contact overflow, {kind}", flush=True)
     lat = W.LatticeSpec(q=9, nx=64, ny=64)
     x = np.array([[20.0, 20.0, 0], [27.9, 20.0, 0], [12.1, 20.0, 0]])
     p = W.Particles(x, np.zeros((3, 3)), np.zeros((3, 3)), np.full(3, 4.0))
     G = P.Lattice(lat, "fp64", max_particles=3, max_radius=4.0, max_contacts=1)
     dp = P.DeviceParticles.from_host(p)
-    G.dem_step(P.make_dem_params(W.DemSpec()), dp, dp.u * 0, dp.u * 0)
+    dem = {"jkr": W.DemSpec(), "hertz": W.DemSpec(gamma=0.0),
+           "friction": W.DemSpec(mu_f=0.3, k_t=1e-3, eta_t=0.02, theta_r=0.01)}[kind]
+    G.dem_step(P.make_dem_params(dem), dp, dp.u * 0, dp.u * 0)
     with pytest.raises(P.PsclbmError) as e:
         G.sync()
     assert e.value.code == P.ECONTACTS
