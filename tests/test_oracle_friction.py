@@ -39,12 +39,12 @@ def _mass(q, rho=3.0):
     return V, m, I
 
 
-def _settled(q, **fric):
+def _settled(q, gamma=GAMMA, **fric):
     """A sphere (disk) at rest on the wall x = -1/2 under gravity -x, settled
     without friction; returns the particle, the DEM state and the load W."""
     lat = _wall_lattice(q)
     eta_n = 2.0 if q == 9 else 5.0                    # near-critical normal damping
-    base = W.DemSpec(g=(-G0, 0.0, 0.0), gamma=GAMMA, E_p=EP, poisson=POISSON, eta_n=eta_n)
+    base = W.DemSpec(g=(-G0, 0.0, 0.0), gamma=gamma, E_p=EP, poisson=POISSON, eta_n=eta_n)
     p = W.Particles(np.array([[R0 - 0.5, 20.0, 20.0 if q == 19 else 0.0]]), np.zeros((1, 3)),
                     np.zeros((1, 3)), np.array([R0]))
     D = oracle.Dem(lat, base, 1)
@@ -52,7 +52,7 @@ def _settled(q, **fric):
     for _ in range(8000):
         D.step(p, z, z)
     assert D.contacts()[0] == [-1] and abs(p.u[0, 0]) < 1e-12
-    fr = W.DemSpec(g=(-G0, 0.0, 0.0), gamma=GAMMA, E_p=EP, poisson=POISSON, eta_n=eta_n, **fric)
+    fr = W.DemSpec(g=(-G0, 0.0, 0.0), gamma=gamma, E_p=EP, poisson=POISSON, eta_n=eta_n, **fric)
     D.params = oracle.make_dem(fr)
     V, _, _ = _mass(q)
     return lat, p, D, (3.0 - 1.0) * V * G0
@@ -323,3 +323,29 @@ def test_hertz_wall_rest_overlap():
     overlap = R0 - (p.x[0, 0] + 0.5)
     assert overlap == pytest.approx((Wl / (4.0 / 3.0 * ESTAR * math.sqrt(R0))) ** (2 / 3),
                                     rel=1e-9)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_hertz_slides_at_the_coulomb_cap(q):
+    # without adhesion the cap of Eq. 29 is mu_f F_ne = mu_f W: Amontons
+    mu = 0.05
+    _, p, D, Wl = _settled(q, gamma=0.0, k_t=5e-3, eta_t=2.0, mu_f=mu)
+    _, m, I = _mass(q)
+    F = 2e-3
+    assert F > mu * Wl * (1 + m * R0 ** 2 / I)
+    h = _run(D, p, (0.0, F, 0.0), (0.0, 0.0, 0.0), 1500)
+    a = (h[-1][0][1] - h[499][0][1]) / 1000.0
+    assert a == pytest.approx((F - mu * Wl) / m, rel=1e-7)
+
+
+def test_hertz_has_no_rolling_resistance():
+    # rolling resistance scales with F_C, which is zero without adhesion: a
+    # torque rolls the sphere (its contact sticking) at T / (I + m r^2)
+    _, p, D, Wl = _settled(19, gamma=0.0, k_t=5e-2, eta_t=5.0, mu_f=1.0, theta_r=0.05)
+    _, m, I = _mass(19)
+    T = 1e-3
+    h = _run(D, p, (0.0, 0.0, 0.0), (0.0, 0.0, T), 4000)
+    alpha = (h[-1][1][2] - h[1999][1][2]) / 2000.0
+    assert alpha == pytest.approx(T / (I + m * R0 ** 2), rel=1e-5)
+    _, _, xr = D.springs(0)[-1]
+    assert np.abs(xr).max() == 0.0
