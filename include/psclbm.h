@@ -100,7 +100,7 @@ typedef struct {
   double max_radius;          /* largest particle radius the DEM bins are sized for */
   int max_tile_particles;     /* capacity of each tile's particle list (e.g. 256) */
   int max_contacts;           /* DEM contact capacity per particle (e.g. 16) */
-  int weighting;              /* PSCLBM_WEIGHT_MODIFIED (Eqs. 12-14, Table 1 Step 5) or
+  int weighting;              /* PSCLBM_WEIGHT_MODIFIED (Eqs. 12-14, cell total clamped, Table 1) or
                                  PSCLBM_WEIGHT_ORIGINAL (Eqs. 7-9, 11: each particle's
                                  weight from its own fraction, B_n their sum) */
 } psclbm_config;
@@ -168,16 +168,16 @@ int lbm_set_equilibrium(psclbm_ctx* ctx, const double* d_rho, const double* d_u)
 int lbm_get_macros(psclbm_ctx* ctx, double* d_rho, double* d_u);
 
 /* Snapshot the particle state and bin every particle into the lattice tiles
- * its shell box X +- (r + h) touches (Table 1 Step 1).  The following
+ * its shell box X +- (r + h) touches (the candidate cells of Table 1).  The following
  * lbm_step calls use this snapshot for positions, velocities and radii; the
- * solid fractions eps_{n,s} (Eqs. 15-19, Table 1 Steps 2-6) are evaluated per
+ * solid fractions eps_{n,s} (Eqs. 15-19, Table 1) are evaluated per
  * cell inside lbm_step.  Errors: EINVAL (n out of range, NULL arrays), EHIP;
  * sticky ESLOTS if a tile list overflows, sticky EINVAL for a radius outside
  * the domain of Eqs. 17/19. */
 int psc_rasterize(psclbm_ctx* ctx, const psclbm_particles* p);
 
 /* Materialise the rasterised solid fractions for inspection: d_eps_total[N]
- * = min(sum_s eps_{n,s}, 1) (Table 1 Step 5); optionally the first kslots
+ * = min(sum_s eps_{n,s}, 1) (the clamped total of Table 1); optionally the first kslots
  * recorded particles per cell in ascending id, d_slot_id[N*kslots] (-1 when
  * empty) and d_slot_eps[N*kslots] (either may be NULL). */
 int psc_get_solid_fraction(psclbm_ctx* ctx, double* d_eps_total, int* d_slot_id,

@@ -202,7 +202,7 @@ def omega_s(q: int, f: np.ndarray, rho: float, u, us) -> np.ndarray:
 
 
 def weights(eps, tau: float, mode: int = 0) -> Tuple[float, np.ndarray]:
-    """Eq. 13 with Table 1 Step 5 (mode 0, modified) or Eqs. 8-9 (mode 1,
+    """Eq. 13 with the cell total clamped at one (Table 1; mode 0, modified) or Eqs. 8-9 (mode 1,
     original).  Returns (B_n, B_{n,s})."""
     eps = np.ascontiguousarray(eps, dtype=np.float64).ravel()
     Bt = np.zeros(1)

@@ -149,67 +149,81 @@ static double linear_eps_offset(int q, double r) {
   return (q == 9 ? or_va2d(r) : or_va3d(r)) + 0.5;
 }
 
-/* Table 1 for every particle, in ascending particle order.
- * Outputs per cell n: nslot[n] recorded particles (Step 6, eps > 0), their ids
- * and eps_{n,s} in recording order (ascending id), and eps_sum[n] = sum of the
- * recorded eps_{n,s} (Step 5 before its clamp).  Returns 0, or -1 when a cell
- * records more than kmax particles, -2 on an invalid particle. */
+/* Fraction of a cell covered by a particle (Sec. 2.4).  With the gap D = d - r
+ * between the cell centre and the particle surface, Eqs. 15 and 18 reduce the
+ * linear approximation to eps = V_a(r) + 1/2 - d (cs = V_a(r) + 1/2), which is
+ * kept within [0, 1].  The text applies the formula to the shell of half-width
+ * h about the surface only: a cell centre at least r + h from the particle
+ * centre lies outside (0), one at most r - h from it inside (1).  Reading:
+ * Table 1 prints these two values the other way round; the text is followed. */
+static double cell_fraction(double d, double r, double h, double cs) {
+  if (d >= r + h) return 0.0;
+  if (d <= r - h) return 1.0;
+  double eps = cs - d;
+  if (eps <= 0.0) return 0.0;
+  if (eps >= 1.0) return 1.0;
+  return eps;
+}
+
+/* Lattice index of the cell at integer position k (nearest image on periodic
+ * axes); -1 when k lies beyond a walled axis. */
+static int cell_at(const or_config* c, const int* k) {
+  int p[3];
+  for (int a = 0; a < 3; ++a) {
+    int L = dims(c, a);
+    if (axis_periodic(c, a)) p[a] = ((k[a] % L) + L) % L;
+    else if (k[a] < 0 || k[a] >= L) return -1;
+    else p[a] = k[a];
+  }
+  return p[0] + c->nx * (p[1] + c->ny * p[2]);
+}
+
+/* Solid fractions of all particles (Sec. 2.4, Eqs. 15-19).  Every cell whose
+ * fraction can be nonzero has its centre within r + h of the particle centre
+ * along each axis, so those cells are the candidates examined.  Each cell n
+ * gets the list of particles covering it with eps_{n,s} > 0 (nslot[n] of them,
+ * ids in slot_id[n*kmax ..] in ascending order, fractions in slot_eps) and the
+ * unclamped total eps_sum[n] = sum_s eps_{n,s}; the clamp of the total at one
+ * is taken where the total is used (or_weights).  Returns 0, or -1 when a cell
+ * is covered by more than kmax particles, -2 on a radius outside the domain of
+ * Eqs. 17/19. */
 int or_rasterize(const or_config* c, int np, const double* X, const double* R,
                  int kmax, int* nslot, int* slot_id, double* slot_eps,
                  double* eps_sum) {
   const int q = lat_q(c);
   const int N = c->nx * c->ny * c->nz;
+  const int dim = q == 9 ? 2 : 3;
   const double h = c->h;
   for (int n = 0; n < N; ++n) { nslot[n] = 0; eps_sum[n] = 0.0; }
   for (int s = 0; s < np; ++s) {
-    double r = R[s];
+    const double r = R[s];
     if (!(r * r > (q == 9 ? 0.25 : 0.5))) return -2;
-    double cs = linear_eps_offset(q, r);
-    /* Step 1: the cells whose centres lie in the axis-aligned box X +- (r+h). */
-    int lo[3], hi[3];
-    for (int a = 0; a < 3; ++a) {
-      if (a == 2 && q == 9) { lo[a] = hi[a] = 0; continue; }
+    const double cs = linear_eps_offset(q, r);
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) {
       lo[a] = (int)ceil(X[3 * s + a] - (r + h));
       hi[a] = (int)floor(X[3 * s + a] + (r + h));
     }
-    for (int kz = lo[2]; kz <= hi[2]; ++kz)
-      for (int ky = lo[1]; ky <= hi[1]; ++ky)
-        for (int kx = lo[0]; kx <= hi[0]; ++kx) {
-          int k[3] = {kx, ky, kz}, cell[3];
-          int inside = 1;
-          for (int a = 0; a < 3; ++a) {
-            int L = dims(c, a);
-            if (axis_periodic(c, a)) cell[a] = ((k[a] % L) + L) % L;
-            else if (k[a] < 0 || k[a] >= L) inside = 0;
-            else cell[a] = k[a];
-          }
-          if (!inside) continue;
-          /* Step 2: centre-to-centre distance (nearest image). */
+    int k[3];
+    for (k[2] = lo[2]; k[2] <= hi[2]; ++k[2])
+      for (k[1] = lo[1]; k[1] <= hi[1]; ++k[1])
+        for (k[0] = lo[0]; k[0] <= hi[0]; ++k[0]) {
+          const int n = cell_at(c, k);
+          if (n < 0) continue;
+          /* centre-to-centre distance d, nearest image */
+          const int p[3] = {n % c->nx, (n / c->nx) % c->ny, n / (c->nx * c->ny)};
           double d2 = 0.0;
-          for (int a = 0; a < 3; ++a) {
-            if (a == 2 && q == 9) continue;
-            double dx = min_image(c, a, (double)cell[a] - X[3 * s + a]);
+          for (int a = 0; a < dim; ++a) {
+            double dx = min_image(c, a, (double)p[a] - X[3 * s + a]);
             d2 += dx * dx;
           }
-          double d = sqrt(d2);
-          /* Step 3 (Reading: the printed 1.0 / 0.0 are swapped -- the text
-           * says cells fully outside are 0 and fully inside are 1). */
-          double eps;
-          if (d >= r + h) eps = 0.0;
-          else if (d <= r - h) eps = 1.0;
-          else eps = cs - d;
-          /* Step 4: clamp to [0, 1]. */
-          if (eps <= 0.0) eps = 0.0;
-          if (eps >= 1.0) eps = 1.0;
-          /* Steps 5-6: accumulate the cell total and record the particle. */
-          if (eps > 0.0) {
-            int n = cell[0] + c->nx * (cell[1] + c->ny * cell[2]);
-            if (nslot[n] >= kmax) return -1;
-            slot_id[n * kmax + nslot[n]] = s;
-            slot_eps[n * kmax + nslot[n]] = eps;
-            nslot[n] += 1;
-            eps_sum[n] += eps;
-          }
+          const double eps = cell_fraction(sqrt(d2), r, h, cs);
+          if (!(eps > 0.0)) continue;
+          if (nslot[n] >= kmax) return -1;
+          slot_id[n * kmax + nslot[n]] = s;
+          slot_eps[n * kmax + nslot[n]] = eps;
+          nslot[n] += 1;
+          eps_sum[n] += eps;
         }
   }
   return 0;
@@ -263,8 +277,8 @@ void or_omega_s(int q, const double* f, double rho, const double* u,
 }
 
 /* Weighting functions of Sec. 2.3.
- * mode 0 (the paper's modified scheme): eps_n = min(sum eps, 1) (Table 1
- *   Step 5) and Eq. 13, B_{n,s} = eps_{n,s}(tau-1/2)/((1-eps_n)+tau-1/2);
+ * mode 0 (the paper's modified scheme): eps_n = min(sum eps, 1) (the
+ *   clamped cell total of Sec. 2.4) and Eq. 13, B_{n,s} = eps_{n,s}(tau-1/2)/((1-eps_n)+tau-1/2);
  *   B_n = eps_n(tau-1/2)/((1-eps_n)+tau-1/2), which is the sum of the B_{n,s}.
  *   Reading: when the recorded fractions sum above one the total is clamped
  *   to 1 (B_n = 1) and each particle keeps its share, B_{n,s} = eps_{n,s}/sum,

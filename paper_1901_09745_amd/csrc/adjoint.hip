@@ -4,7 +4,7 @@
 // Notation per cell n (all FP64): f the state entering the step (after the
 // inlet / outlet reset), lam*_i = dJ/df*_i the sensitivity of the post-
 // collision population (read where that population streams to), B_n and the
-// per-particle shares B_s (Eq. 13 / Table 1 Step 5), and
+// per-particle shares B_s (Eq. 13 with the clamped cell total of Table 1), and
 //   f*_i = f_i - (1 - B_n) [w (f_i - f^eq_i) - F_i]
 //          + sum_s B_s [f_{-i} - f^eq_{-i}(rho,u) + f^eq_i(rho,u_s) - f_i]   (Eqs. 10, 12)
 //   m_s  = B_s [rho (u_s - u) + F],  F_s -= m_s,  T_s -= r_s x m_s       (Eq. 14)

@@ -403,7 +403,7 @@ __global__ void __launch_bounds__(BLOCK)
     const C kguo = (C)1 - (C)0.5 * omega;
     const C uF = ux * F0 + uy * F1 + uz * F2;
 
-    // Weights (Eq. 13 with Table 1 Step 5): B_n from the clamped cell total;
+    // Weights (Eq. 13 with the cell total clamped at one, Table 1): B_n from the clamped cell total;
     // each particle's share B_s is formed in the second pass below.  The
     // original weighting (Eq. 9) takes each particle's B_s from its own
     // fraction and B_n as their sum.
@@ -774,7 +774,7 @@ __global__ void k_reduce(const double* part, int n, double* out) {
 }
 
 // ---------------------------------------------------------------------------
-// Rasterisation: particle snapshot, then tile binning (Table 1 Step 1).
+// Rasterisation: particle snapshot, then tile binning (the candidate box X +- (r + h) of Table 1).
 // ---------------------------------------------------------------------------
 // One wave per particle: the particle's snapshot (with V_a of Eq. 17 / 19),
 // its force / torque rows cleared in both buffers, and its entry in the list

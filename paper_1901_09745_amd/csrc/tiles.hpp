@@ -20,7 +20,7 @@ __device__ __forceinline__ double min_image(double d, int periodic, int L) {
 }
 
 // ---------------------------------------------------------------------------
-// Solid fraction of one (cell, particle) pair, Table 1 Steps 2-4 with
+// Solid fraction of one (cell, particle) pair, the inside/outside rule of Table 1 with
 // Eq. 15/18: eps = V_a(r) + 1/2 - d inside the shell r +- h.
 // ---------------------------------------------------------------------------
 __device__ inline double pair_eps(double d, double r, double cs, double h) {
@@ -168,7 +168,7 @@ __device__ inline void collect_slots(const Geom& g, int x0, int y, int z, bool a
       double dx = (double)(x0 + cl) - P.x;
       dx = wrapb ? min_image(dx, px, nx) : dx + shb;
       const double d2 = dx * dx + dyz2b;
-      // Table 1 Steps 3-4 on d = sqrt(d2); the root is taken only where the
+      // the Table 1 rule on d = sqrt(d2); the root is taken only where the
       // fraction is not already fixed at 0 or 1 by the shell or the clamp
       const double rh = P.r + h;
       const double rl = P.r - h;
@@ -350,7 +350,7 @@ __device__ __forceinline__ unsigned link(const Dims& d, int x, int y, int z, int
 }
 
 // ---------------------------------------------------------------------------
-// Particle snapshot and tile binning (Table 1 Step 1), shared by the
+// Particle snapshot and tile binning (the candidate box of Table 1), shared by the
 // rasterisation and by the DEM kernel that rasterises the next step.
 // ---------------------------------------------------------------------------
 __device__ inline double va2d(double r) {  // Eq. 19

@@ -187,7 +187,7 @@ def test_small_shell_is_literal():
 
 
 def test_shared_cells_sum_and_order():
-    # Steps 5-6: the cell total is the sum of the recorded fractions, recorded
+    # the cell total is the sum of the recorded fractions, recorded
     # in ascending particle order; periodic images wrap.
     lat = _lat2()
     X = np.array([[10.0, 20.0, 0.0], [22.4, 20.0, 0.0], [39.0, 5.0, 0.0]])

@@ -60,7 +60,7 @@ def test_original_underestimates():
 
 
 def test_overfull_cell_shares():
-    # Table 1 Step 5 clamps the cell total to one; the shares still add to B_n = 1.
+    # Table 1 clamps the cell total to one; the shares still add to B_n = 1.
     b_total, b_slot = oracle.weights([0.7, 0.6], 0.8, 0)
     assert b_total == pytest.approx(1.0, abs=1e-15)
     assert b_slot.sum() == pytest.approx(1.0, abs=1e-15)
