@@ -70,10 +70,42 @@ int validate(const psclbm_config* c) {
   return PSCLBM_OK;
 }
 
+// Tile width along x: the widest of 256, 128 and 64 cells that pads the x
+// extent least (a tile row is four, two or one 64-cell wave segments).  Wide
+// tiles keep the cache lines that the odd steps' shifted accesses split
+// between neighbouring segments inside one workgroup.  PSCLBM_TILE_X in the
+// environment (64, 128 or 256) overrides the choice, for measurements.
+int tile_width(int nx) {
+  if (const char* e = std::getenv("PSCLBM_TILE_X")) {
+    const int v = std::atoi(e);
+    if (v == 64 || v == 128 || v == 256) return v;
+  }
+  int best = 64;
+  long long pad = ((long long)nx + 63) / 64 * 64;
+  for (int tw : {128, 256}) {
+    const long long p = ((long long)nx + tw - 1) / tw * tw;
+    if (p <= pad) {
+      best = tw;
+      pad = p;
+    }
+  }
+  return best;
+}
+
+// Even steps read and write every cell's own slots, each line by one wave
+// only, and stream them with non-temporal hints when the distributions are
+// larger than the 256 MB last-level cache (which they would otherwise sweep
+// out).  PSCLBM_NT=0/1 overrides, for measurements.
+int nt_even(const psclbm_config* c) {
+  if (const char* e = std::getenv("PSCLBM_NT")) return std::atoi(e) ? 1 : 0;
+  const double bytes = (double)c->nx * c->ny * c->nz * c->lattice * storage_bytes(c->precision);
+  return bytes > 256.0 * 1024 * 1024 ? 1 : 0;
+}
+
 struct Layout {
   size_t f, err, scalar, tile_count, tile_list, snap, facc0, facc1, mass_part, outlet_u, outlet_g;
   size_t bin_count, bin_rec, cn0, cn1, cid0, cid1, fcont, spr0, spr1, ws0, ws1, total;
-  int ntx, nty, ntz, ntiles;
+  int ntx, nty, ntz, ntiles, twx, twy;
   long long face_stride;
   int nbin[3];
   double bin_size[3];
@@ -83,9 +115,11 @@ struct Layout {
 Layout plan(const psclbm_config* c) {
   Layout l;
   const long long N = (long long)c->nx * c->ny * c->nz;
-  l.ntx = (c->nx + TX - 1) / TX;
-  l.nty = (c->ny + TY - 1) / TY;
-  l.ntz = (c->nz + TZ - 1) / TZ;
+  l.twx = tile_width(c->nx);
+  l.twy = BLOCK / l.twx;
+  l.ntx = (c->nx + l.twx - 1) / l.twx;
+  l.nty = (c->ny + l.twy - 1) / l.twy;
+  l.ntz = c->nz;
   l.ntiles = l.ntx * l.nty * l.ntz;
   const int np = c->max_particles;
   const int cap = np > 0 ? c->max_tile_particles : 1;
@@ -201,6 +235,10 @@ int lbm_init(const psclbm_config* cfg, void* d_workspace, size_t bytes, void* hi
   g.ntx = l.ntx;
   g.nty = l.nty;
   g.ntz = l.ntz;
+  g.twx = l.twx;
+  g.twy = l.twy;
+  g.remap = l.twx == SEG ? 1 : 0;
+  g.nt_even = nt_even(cfg);
   g.rho0 = cfg->rho0;
   c->prec = cfg->precision;
   c->f = base + l.f;

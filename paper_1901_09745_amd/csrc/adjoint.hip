@@ -89,12 +89,10 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
     for (int k = threadIdx.x; k < 9 * cnt; k += BLOCK) acc[k] = 0.0;
     __syncthreads();
   }
-  int x0, y0, z0;
-  tile_origin(G, tile, x0, y0, z0);
-  const int x = x0 + (int)(threadIdx.x % TX);
-  // y and z are those of the wave's row: uniform over the wave (scalar)
-  const int y = __builtin_amdgcn_readfirstlane(y0 + (int)((threadIdx.x / TX) % TY));
-  const int z = __builtin_amdgcn_readfirstlane(z0 + (int)(threadIdx.x / (TX * TY)));
+  // the wave's 64-cell row segment; y and z are uniform over the wave (scalar)
+  int x0, y, z;
+  wave_segment(G, tile, x0, y, z);
+  const int x = x0 + (int)(threadIdx.x & 63);
   const bool active = x < G.nx && y < G.ny && z < G.nz;
   const unsigned N = (unsigned)G.N;
   const unsigned n = (unsigned)x + (unsigned)G.nx * ((unsigned)y + (unsigned)G.ny * (unsigned)z);
@@ -579,12 +577,10 @@ __global__ void __launch_bounds__(BLOCK) k_rasterize_adjoint(Geom g, double h, i
   LdsEntry* lds = reinterpret_cast<LdsEntry*>(smem_d);
   const int tile = blockIdx.x;
   const int cnt = load_tile_list(tile_count, tile_list, cap, snap, tile, lds, nullptr, np);
-  int x0, y0, z0;
-  tile_origin(g, tile, x0, y0, z0);
-  const int x = x0 + (int)(threadIdx.x % TX);
-  // y and z are those of the wave's row: uniform over the wave (scalar)
-  const int y = __builtin_amdgcn_readfirstlane(y0 + (int)((threadIdx.x / TX) % TY));
-  const int z = __builtin_amdgcn_readfirstlane(z0 + (int)(threadIdx.x / (TX * TY)));
+  // the wave's 64-cell row segment; y and z are uniform over the wave (scalar)
+  int x0, y, z;
+  wave_segment(g, tile, x0, y, z);
+  const int x = x0 + (int)(threadIdx.x & 63);
   const bool active = x < g.nx && y < g.ny && z < g.nz;
   Slots s;
   s.n = 0;

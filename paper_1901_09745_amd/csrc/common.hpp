@@ -79,11 +79,11 @@ struct Form<PSCLBM_FP32_FP16STORE> {
   using C = float;
 };
 
-// Workgroup tile: 64 cells along x (one wave per row) by 4 rows along y.
-constexpr int TX = 64;
-constexpr int TY = 4;
-constexpr int TZ = 1;
-constexpr int BLOCK = TX * TY * TZ;
+// Workgroup tile: 256 cells, twx along x by twy = 256 / twx rows along y (twx
+// 64, 128 or 256, chosen per lattice), worked by four waves; each wave takes
+// one 64-cell segment of one row.
+constexpr int SEG = 64;
+constexpr int BLOCK = 256;
 constexpr int KSLOTS = 4;  // particles a single cell can be covered by
 
 // Sticky device error bits.
@@ -109,6 +109,9 @@ struct Geom {
   int face[6];
   int periodic[3];
   int ntx, nty, ntz;
+  int twx, twy;  // tile extent along x and y (twx * twy == BLOCK)
+  int remap;     // deal the tiles to the XCDs in contiguous runs
+  int nt_even;   // even steps stream the lattice with non-temporal loads and stores
   double face_u[6][3];
   double rho0;
 };
@@ -178,11 +181,12 @@ struct StepArgs {
 // Outlet faces whose cells share a wave with their interior neighbour, so that
 // the neighbour's velocity (and, in the adjoint, the sensitivity flowing back
 // to it) moves between lanes: the x faces, since a wave is one 64-cell x-row
-// segment of a tile; x = nx-1 only when it is not the first lane of a segment.
+// segment (segments start at multiples of 64); x = nx-1 only when it is not
+// the first lane of a segment.
 inline unsigned outlet_wave_mask(const Geom& g, unsigned outlet_mask) {
   unsigned m = 0;
   if ((outlet_mask & 1u) && g.nx >= 2) m |= 1u;
-  if ((outlet_mask & 2u) && g.nx >= 2 && (g.nx - 1) % TX != 0) m |= 2u;
+  if ((outlet_mask & 2u) && g.nx >= 2 && (g.nx - 1) % SEG != 0) m |= 2u;
   return m;
 }
 

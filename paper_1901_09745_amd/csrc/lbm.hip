@@ -49,6 +49,50 @@ __host__ __device__ constexpr bool check_lattice() {
 static_assert(check_lattice<9>() && check_lattice<19>(), "opposite directions");
 
 // ---------------------------------------------------------------------------
+// FP32 arithmetic that keeps the collision free of systematic rounding.
+// ---------------------------------------------------------------------------
+// w_i x in the compute type.  In FP32 the weights are not representable: 4/9,
+// 1/9, 1/18 and 1/36 all round with one relative error of about 7.5e-9 (1/3
+// with 3e-8), which scales the mass and momentum of every equilibrium the
+// collision relaxes towards, and the relaxation then adds that excess to the
+// flow again at every step.  The product is taken with the weight split into
+// its FP32 rounding and the remainder, so that it carries one ordinary
+// rounding of the result instead.
+template <int Q, typename C>
+__device__ __forceinline__ C wmul(int i, C x) {
+  if constexpr (std::is_same<C, double>::value) {
+    return (C)Lattice<Q>::w(i) * x;
+  } else {
+    const float hi = (float)Lattice<Q>::w(i);
+    const float lo = (float)(Lattice<Q>::w(i) - (double)hi);
+    return __builtin_fmaf(x, hi, x * lo);
+  }
+}
+
+// Velocity of Eq. 5, u = (j + F/2) / rho, in the compute type, from the
+// momentum component j, the half force h and q = drho / rho.  In FP32 the half
+// force (of order 1e-7 against a momentum of order 1e-3 in a slowly developing
+// flow) loses its low bits when added to j, the same bits step after step,
+// which biases the force the flow receives; the sum is therefore kept as its
+// rounded value s and the exact remainder e (Knuth's two-sum), and 1/rho as
+// (1 - q) / rho0, so that the rounding of rho only touches the small
+// correction: u = (s + (e - s q)) / rho0.
+template <typename C>
+__device__ __forceinline__ C eq5_velocity(C j, C h, C q, C inv_rho, C inv_rho0) {
+  if constexpr (std::is_same<C, double>::value) {
+    (void)q;
+    (void)inv_rho0;
+    return (j + h) * inv_rho;
+  } else {
+    (void)inv_rho;
+    const C s = j + h;
+    const C bp = s - j;
+    const C e = (j - (s - bp)) + (h - bp);
+    return (s + (e - s * q)) * inv_rho0;
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Storage conversion: deviation g_i = f_i - w_i rho0 in the compute type.
 // ---------------------------------------------------------------------------
 // Element `e` of a per-direction array through a 32-bit byte offset, so the
@@ -57,59 +101,49 @@ template <typename S>
 __device__ __forceinline__ S& elem(S* base, unsigned e) {
   return *reinterpret_cast<S*>(reinterpret_cast<char*>(base) + (e * (unsigned)sizeof(S)));
 }
+// The same element read or written with a non-temporal hint when NT: the
+// line is streamed through the caches rather than kept in them.
+template <bool NT, typename S>
+__device__ __forceinline__ S elem_ld(S* base, unsigned e) {
+  if constexpr (NT) return __builtin_nontemporal_load(&elem(base, e));
+  else return elem(base, e);
+}
+template <bool NT, typename S>
+__device__ __forceinline__ void elem_st(S* base, unsigned e, S v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, &elem(base, e));
+  else elem(base, e) = v;
+}
 
 template <int PREC, int Q>
 struct Store {
   using S = typename Form<PREC>::S;
   using C = typename Form<PREC>::C;
   // direction-i array `b` (= A + i N), element e
+  template <bool NT = false>
   __device__ static C ld(S* b, unsigned e, int i, double rho0) {
-    const S v = elem(b, e);
+    const S v = elem_ld<NT>(b, e);
     if constexpr (PREC == PSCLBM_FP64) {
       return v - Lattice<Q>::w(i) * rho0;
     } else if constexpr (PREC == PSCLBM_FP32) {
       return v;
     } else {
-      return static_cast<float>(v) * static_cast<float>(Lattice<Q>::w(i));
+      return wmul<Q>(i, static_cast<float>(v));
     }
   }
-  // stores deviation g of direction i; returns the deviation memory now holds
-  // (in the compute precision: the per-cell part of the mass sum)
-  __device__ static C st(S* b, unsigned e, int i, C g, double rho0) {
+  // stores deviation g of direction i; returns the deviation memory now holds,
+  // exactly, in FP64 (the per-cell part of the mass sum)
+  template <bool NT = false>
+  __device__ static double st(S* b, unsigned e, int i, C g, double rho0) {
     if constexpr (PREC == PSCLBM_FP64) {
       const double f = Lattice<Q>::w(i) * rho0 + g;
-      elem(b, e) = f;
+      elem_st<NT>(b, e, f);
       return f - Lattice<Q>::w(i) * rho0;
     } else if constexpr (PREC == PSCLBM_FP32) {
-      elem(b, e) = g;
-      return g;
-    } else {
-      const _Float16 h = static_cast<_Float16>(g * static_cast<float>(1.0 / Lattice<Q>::w(i)));
-      elem(b, e) = h;
-      return static_cast<float>(h) * static_cast<float>(Lattice<Q>::w(i));
-    }
-  }
-  __device__ static C load(const S* a, size_t idx, int i, double rho0) {
-    if constexpr (PREC == PSCLBM_FP64) {
-      return a[idx] - Lattice<Q>::w(i) * rho0;
-    } else if constexpr (PREC == PSCLBM_FP32) {
-      return a[idx];
-    } else {
-      return static_cast<float>(a[idx]) * static_cast<float>(Lattice<Q>::w(i));
-    }
-  }
-  // Stores g and returns the deviation actually held by memory (for the mass sum).
-  __device__ static double store(S* a, size_t idx, int i, C g, double rho0) {
-    if constexpr (PREC == PSCLBM_FP64) {
-      const double f = Lattice<Q>::w(i) * rho0 + g;
-      a[idx] = f;
-      return f - Lattice<Q>::w(i) * rho0;
-    } else if constexpr (PREC == PSCLBM_FP32) {
-      a[idx] = g;
+      elem_st<NT>(b, e, g);
       return static_cast<double>(g);
     } else {
       const _Float16 h = static_cast<_Float16>(g * static_cast<float>(1.0 / Lattice<Q>::w(i)));
-      a[idx] = h;
+      elem_st<NT>(b, e, h);
       return static_cast<double>(static_cast<float>(h)) * Lattice<Q>::w(i);
     }
   }
@@ -207,10 +241,13 @@ constexpr int step_waves() {
   return (PREC == PSCLBM_FP32_FP16STORE || WALLS) ? 6 : 5;
 }
 
-template <int Q, int PREC, int PAR, bool WALLS>
+// NT (even steps only): the lattice is streamed with non-temporal loads and
+// stores, each line being read and written by one wave.
+template <int Q, int PREC, int PAR, bool WALLS, bool NT = false>
 __global__ void __launch_bounds__(BLOCK)
     __attribute__((amdgpu_waves_per_eu(step_waves<Q, PREC, WALLS>())))
     k_step(const StepArgs a) {
+  static_assert(!NT || PAR == 0, "non-temporal streaming in the even steps only");
   using L = Lattice<Q>;
   using C = typename Form<PREC>::C;
   using S = typename Form<PREC>::S;
@@ -244,7 +281,7 @@ __global__ void __launch_bounds__(BLOCK)
   // round robin of the tile workgroups is that of their own index)
   const int nb = (int)gridDim.x - a.dem_blocks;
   const int bid = (int)blockIdx.x - a.dem_blocks;
-  const int tile = xcd_tile(bid, nb);
+  const int tile = tile_of(a.g, bid, nb);
 
   // particle list of the tile (LDS) and its force accumulators
   LdsEntry* lds = reinterpret_cast<LdsEntry*>(smem_d);
@@ -252,12 +289,10 @@ __global__ void __launch_bounds__(BLOCK)
   const int cnt = load_tile_list(a.tile_count, a.tile_list, a.cap, a.snap, tile, lds, acc, a.np);
 
   const Dims d = dims_of(a.g);
-  int x0, y0, z0;
-  tile_origin(a.g, tile, x0, y0, z0);
-  const int x = x0 + (int)(threadIdx.x % TX);
-  // y and z are those of the wave's row: uniform over the wave (scalar)
-  const int y = __builtin_amdgcn_readfirstlane(y0 + (int)((threadIdx.x / TX) % TY));
-  const int z = __builtin_amdgcn_readfirstlane(z0 + (int)(threadIdx.x / (TX * TY)));
+  // the wave's 64-cell row segment; y and z are uniform over the wave (scalar)
+  int x0, y, z;
+  wave_segment(a.g, tile, x0, y, z);
+  const int x = x0 + (int)(threadIdx.x & 63);
   const bool active = x < d.nx && y < d.ny && z < d.nz;
   const unsigned n = (unsigned)x + d.sy * (unsigned)y + d.sz * (unsigned)z;
   const unsigned N = (unsigned)a.g.N;
@@ -286,7 +321,7 @@ __global__ void __launch_bounds__(BLOCK)
       if constexpr (PAR == 2) {
         g[i] = ST::ld(const_cast<S*>(static_cast<const S*>(a.src)) + (size_t)i * N, n, i, rho0);
       } else if constexpr (PAR == 0) {
-        g[i] = ST::ld(A + (size_t)i * N, n, i, rho0);
+        g[i] = ST::template ld<NT>(A + (size_t)i * N, n, i, rho0);
       } else {
         unsigned m = n;
         if (!link<WALLS>(d, x, y, z, -L::ex(i), -L::ey(i), -L::ez(i), n, m))
@@ -334,9 +369,10 @@ __global__ void __launch_bounds__(BLOCK)
         j1 = __shfl(j1, src);
         j2 = __shfl(j2, src);
         const C ir = (C)1 / ((C)rho0 + r_);
-        wu0 = (double)((j0 + (C)0.5 * F0) * ir);
-        wu1 = (double)((j1 + (C)0.5 * F1) * ir);
-        wu2 = (double)((j2 + (C)0.5 * F2) * ir);
+        const C qr = r_ * ir, ir0 = (C)(1.0 / rho0);
+        wu0 = (double)eq5_velocity(j0, (C)0.5 * F0, qr, ir, ir0);
+        wu1 = (double)eq5_velocity(j1, (C)0.5 * F1, qr, ir, ir0);
+        wu2 = (double)eq5_velocity(j2, (C)0.5 * F2, qr, ir, ir0);
       }
 #pragma unroll
       for (int f = 0; f < 6; ++f) {  // outlets first, an inlet wins on a corner
@@ -376,7 +412,7 @@ __global__ void __launch_bounds__(BLOCK)
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           const C eu = edot(L::ex(i), L::ey(i), L::ez(i), u0, u1, u2);
-          g[i] = (C)L::w(i) * (C)rho0 * ((C)3 * eu + (C)4.5 * eu * eu - (C)1.5 * uq);
+          g[i] = wmul<Q>(i, (C)rho0 * ((C)3 * eu + (C)4.5 * eu * eu - (C)1.5 * uq));
         }
       }
     }
@@ -395,9 +431,11 @@ __global__ void __launch_bounds__(BLOCK)
     }
     rho = (C)rho0 + drho;
     const C inv_rho = (C)1 / rho;
-    ux = (jx + (C)0.5 * F0) * inv_rho;
-    uy = (jy + (C)0.5 * F1) * inv_rho;
-    uz = (jz + (C)0.5 * F2) * inv_rho;
+    const C q_rho = drho * inv_rho;
+    const C inv_rho0 = (C)(1.0 / rho0);
+    ux = eq5_velocity(jx, (C)0.5 * F0, q_rho, inv_rho, inv_rho0);
+    uy = eq5_velocity(jy, (C)0.5 * F1, q_rho, inv_rho, inv_rho0);
+    uz = eq5_velocity(jz, (C)0.5 * F2, q_rho, inv_rho, inv_rho0);
     uu = ux * ux + uy * uy + uz * uz;
     const C omega = (C)a.omega;
     const C kguo = (C)1 - (C)0.5 * omega;
@@ -430,7 +468,7 @@ __global__ void __launch_bounds__(BLOCK)
     // time (Eqs. 2-4, 10, 12) ----
     {
       const C wi = (C)L::w(0);
-      const C fneq = g[0] - wi * (drho - rho * (C)1.5 * uu);
+      const C fneq = g[0] - wmul<Q>(0, drho - rho * (C)1.5 * uu);
       g[0] = g[0] - relax * fneq - omB * kguo * wi * (C)3 * uF;
     }
 #pragma unroll
@@ -441,8 +479,8 @@ __global__ void __launch_bounds__(BLOCK)
       const C eu = edot(L::ex(i), L::ey(i), L::ez(i), ux, uy, uz);
       const C eF = edot(L::ex(i), L::ey(i), L::ez(i), F0, F1, F2);
       const C sym = drho + rho * ((C)4.5 * eu * eu - (C)1.5 * uu);
-      const C fn_i = g[i] - wi * (sym + rho * (C)3 * eu);
-      const C fn_o = g[o] - wi * (sym - rho * (C)3 * eu);
+      const C fn_i = g[i] - wmul<Q>(i, sym + rho * (C)3 * eu);
+      const C fn_o = g[o] - wmul<Q>(i, sym - rho * (C)3 * eu);
       // Guo term (Eq. 4): even and odd parts under e -> -e
       const C Fsym = kguo * wi * ((C)9 * eu * eF - (C)3 * uF);
       const C Fant = kguo * wi * ((C)3 * eF);
@@ -488,19 +526,19 @@ __global__ void __launch_bounds__(BLOCK)
       const C svx = usx + ux, svy = usy + uy, svz = usz + uz;
       const C du2 = dvx * svx + dvy * svy + dvz * svz;  // |u_s|^2 - |u|^2
       const C rB = rho * Bs;
-      g[0] -= rB * (C)L::w(0) * (C)1.5 * du2;
+      g[0] -= wmul<Q>(0, rB * (C)1.5 * du2);
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
         const int o = L::opp(i);
         if (o < i) continue;
-        const C rBw = rB * (C)L::w(i);
+
         const C de = edot(L::ex(i), L::ey(i), L::ez(i), dvx, dvy, dvz);
         const C se = edot(L::ex(i), L::ey(i), L::ez(i), svx, svy, svz);
         // 4.5 [(e.u_s)^2 - (e.u)^2] - 1.5 (|u_s|^2 - |u|^2), and 3 e.(u_s - u)
         const C ds_s = (C)4.5 * de * se - (C)1.5 * du2;
         const C ds_a = (C)3 * de;
-        g[i] += rBw * (ds_s + ds_a);
-        g[o] += rBw * (ds_s - ds_a);
+        g[i] += wmul<Q>(i, rB * (ds_s + ds_a));
+        g[o] += wmul<Q>(i, rB * (ds_s - ds_a));
       }
       if (!a.facc) return;
       const C mx = Bm * (rho * dvx + F0);
@@ -575,7 +613,7 @@ __global__ void __launch_bounds__(BLOCK)
     unsigned xo = (unsigned)x;
     asm volatile("" : "+v"(xo));
     const unsigned no = xo + d.sy * (unsigned)y + d.sz * (unsigned)z;
-    C cell_dev = 0;
+    double cell_dev = 0.0;  // FP64 sum of the stored deviations, in every form
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       unsigned m = no;
@@ -597,12 +635,14 @@ __global__ void __launch_bounds__(BLOCK)
           v -= (C)(6.0 * L::w(i) * eu) * rho;
         }
       }
-      if (PAR == 0 || out)  // own cell, opposite slot
+      if (PAR == 0)  // own cell, opposite slot
+        cell_dev += ST::template st<NT>(A + (size_t)L::opp(i) * N, no, i, v, rho0);
+      else if (out)  // reflected into the own cell's opposite slot
         cell_dev += ST::st(A + (size_t)L::opp(i) * N, no, i, v, rho0);
       else                  // neighbour cell, same slot
         cell_dev += ST::st(A + (size_t)i * N, m, i, v, rho0);
     }
-    mass_dev = (double)cell_dev;
+    mass_dev = cell_dev;
   }
 
   // ---- per-workgroup FP64 mass partial (sum of the stored deviations) ----
@@ -822,11 +862,11 @@ __global__ void __launch_bounds__(BLOCK) k_solid_fraction(Geom g, double h, int 
   const int tile = blockIdx.x;
   const int cnt = load_tile_list(tile_count, tile_list, cap, snap, tile, lds, nullptr, np);
   int x0, y0, z0;
-  tile_origin(g, tile, x0, y0, z0);
+  wave_segment(g, tile, x0, y0, z0);
   Cell c;
-  c.x = x0 + threadIdx.x % TX;
-  c.y = y0 + (threadIdx.x / TX) % TY;
-  c.z = z0 + threadIdx.x / (TX * TY);
+  c.x = x0 + (int)(threadIdx.x & 63);
+  c.y = y0;
+  c.z = z0;
   const bool active = c.x < g.nx && c.y < g.ny && c.z < g.nz;
   c.n = c.x + (long long)g.nx * (c.y + (long long)g.ny * c.z);
   Slots s;
@@ -875,13 +915,18 @@ static int dispatch_step(psclbm_ctx* c, const StepArgs& a, int par, size_t lds_b
     }
     return PSCLBM_EINVAL;
   }
+  const bool nt = c->geom.nt_even != 0;
   if (walls) {
-    if (par == 0)
+    if (par == 0 && nt)
+      k_step<Q, PREC, 0, true, true><<<nb, BLOCK, lds_bytes, c->stream>>>(a);
+    else if (par == 0)
       k_step<Q, PREC, 0, true><<<nb, BLOCK, lds_bytes, c->stream>>>(a);
     else
       k_step<Q, PREC, 1, true><<<nb, BLOCK, lds_bytes, c->stream>>>(a);
   } else {
-    if (par == 0)
+    if (par == 0 && nt)
+      k_step<Q, PREC, 0, false, true><<<nb, BLOCK, lds_bytes, c->stream>>>(a);
+    else if (par == 0)
       k_step<Q, PREC, 0, false><<<nb, BLOCK, lds_bytes, c->stream>>>(a);
     else
       k_step<Q, PREC, 1, false><<<nb, BLOCK, lds_bytes, c->stream>>>(a);

@@ -89,7 +89,7 @@ __device__ __forceinline__ int wave_scan_incl(int v) {
 // slot of its cell in LDS when the fraction is positive.  Phase 3: each cell reads its
 // slots and orders them by particle id.  At most KSLOTS slots are kept per
 // cell (more set ERR_SLOTS).  All 64 lanes must call this.
-static_assert(TX == 64, "one wave per tile row");
+static_assert(SEG == 64, "one wave per 64-cell row segment");
 
 template <int D, typename E>
 __device__ inline void collect_slots(const Geom& g, int x0, int y, int z, bool active,
@@ -265,15 +265,19 @@ __device__ inline int load_tile_list(const int* tile_count, const int* tile_list
   return cnt;
 }
 
-__device__ inline void tile_origin(const Geom& g, int tile, int& x0, int& y0, int& z0) {
+// The calling wave's cells in a tile: the 64-cell row segment starting at x
+// = xw in row (y, z).  The results are uniform over the wave (scalar).
+__device__ inline void wave_segment(const Geom& g, int tile, int& xw, int& y, int& z) {
   const int tx = tile % g.ntx;
   const int r = tile / g.ntx;
   const int ty = r % g.nty;
-  const int tz = r / g.nty;
-  x0 = tx * TX;
-  y0 = ty * TY;
-  z0 = tz * TZ;
+  const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int segs = g.twx >> 6;  // segments per tile row
+  xw = __builtin_amdgcn_readfirstlane(tx * g.twx + SEG * (w % segs));
+  y = __builtin_amdgcn_readfirstlane(ty * g.twy + w / segs);
+  z = __builtin_amdgcn_readfirstlane(r / g.nty);
 }
+
 
 // Workgroup -> tile map.  The dispatcher deals consecutive workgroups round-
 // robin to the 8 XCDs; this bijection gives each XCD one contiguous run of
@@ -284,6 +288,9 @@ __device__ inline int xcd_tile(int b, int nb) {
   const int xcd = b % NX, k = b / NX;
   return xcd * per + (xcd < rem ? xcd : rem) + k;
 }
+// The remap pays for 64-wide tiles, whose x-neighbours share the halo lines;
+// wider tiles keep those lines inside the workgroup and run as dispatched.
+__device__ inline int tile_of(const Geom& g, int b, int nb) { return g.remap ? xcd_tile(b, nb) : b; }
 
 // Lattice extents and periodicity as plain scalars (no arrays: every access
 // stays a register or a kernel-argument load).
@@ -450,7 +457,7 @@ __device__ inline void bin_tiles(const Geom& g, int three_d, double h, const PSn
                                  int lane, int* count, int* tile_list, int cap, unsigned* err) {
   const double R = P.r + h;
   const int L[3] = {g.nx, g.ny, g.nz};
-  const int T[3] = {TX, TY, TZ};
+  const int T[3] = {g.twx, g.twy, 1};
   AxisRuns runs[3];
   int la[3], lt[3];
 #pragma unroll

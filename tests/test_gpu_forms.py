@@ -1,13 +1,14 @@
 """Accuracy of the reduced-precision forms against the FP64 oracle.
 
 FP32 form (FP32 arithmetic, FP32 storage of f_i - w_i rho0): velocity and
-drag within 1e-5 (relative) on the moving-sphere case.  On the body-force
-channel the flow is built up over 2000 steps from a force increment of about
-3e-7 per step added to deviations of about 1e-3, i.e. some 2000 FP32 ulps;
-the accumulated rounding measured there is 2.5e-5 (velocity) and 3.3e-5
-(drag), and the stated tolerance for that case is 5e-5.  FP16-storage form
-(FP32 arithmetic, FP16 storage of (f_i - w_i rho0) / w_i): the storage
-rounding (2^-11 of the stored deviation) bounds the attainable accuracy; the
+drag within the stated 1e-5 (relative), on the body-force channel after 2000
+steps and on the moving-sphere case.  The channel is the hard case for FP32:
+the flow is built up from a body force of 1e-6 per step, and a collision
+whose rounding is systematic (the half force of Eq. 5 added to a momentum of
+order 1e-3, or lattice weights rounded to FP32) drifts by far more than 1e-5
+over the run; the kernel's arithmetic avoids both.  FP16-storage form (FP32
+arithmetic, FP16 storage of (f_i - w_i rho0) / w_i): the storage rounding
+(2^-11 of the stored deviation) bounds the attainable accuracy; the
 tolerances below are set from that rounding.  Measured errors are printed.
 """
 import numpy as np
@@ -49,7 +50,7 @@ def _run_pair(lat, p, steps, form, kinematic=False):
     return eu, eF, em
 
 
-@pytest.mark.parametrize("form,tol_u,tol_F", [("fp32", 5e-5, 5e-5), ("fp16", 3e-2, 3e-2)])
+@pytest.mark.parametrize("form,tol_u,tol_F", [("fp32", 1e-5, 1e-5), ("fp16", 3e-2, 3e-2)])
 def test_forms_c1_channel(form, tol_u, tol_F):
     # D2Q9 tau=0.8 200x100 channel, body force 1e-6, fixed disk r=10 at (60,50)
     w = W.c1()
