@@ -92,6 +92,7 @@ def _lib():
         L.or_dem_step.argtypes = [ctypes.POINTER(_Config), ctypes.POINTER(_Dem), ctypes.c_int,
                                   _D, _D, _D, _D, _D, _D, ctypes.c_int, _I, _I, _D]
         L.or_num_threads.restype = ctypes.c_int
+        L.or_set_num_threads.argtypes = [ctypes.c_int]
         _lib_handle = L
     return _lib_handle
 
@@ -131,6 +132,11 @@ def make_config(lat) -> _Config:
 
 def num_threads() -> int:
     return int(_lib().or_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the OpenMP cell loop (timing only)."""
+    _lib().or_set_num_threads(int(n))
 
 
 # --------------------------------------------------------------------------

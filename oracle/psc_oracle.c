@@ -560,6 +560,15 @@ int or_num_threads(void) {
 #endif
 }
 
+/* Threads of the OpenMP cell loop (timing only; results do not depend on it). */
+void or_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------ */
 /* Sec. 2.5: JKR adhesive normal contact                                     */
 /* ------------------------------------------------------------------------ */

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libpsclbm.so")
-SOURCES = ["lbm.hip", "dem.hip", "adjoint.hip", "abi.hip"]
+SOURCES = ["lbm.hip", "dem.hip", "adjoint.hip", "abi.hip", "probe.hip"]
 ARCH = "gfx950"
 
 

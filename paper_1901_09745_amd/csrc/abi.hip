@@ -179,6 +179,29 @@ Layout plan(const psclbm_config* c) {
   return l;
 }
 
+// The lattice geometry the kernels take, from a validated configuration.
+void fill_geom(const psclbm_config* cfg, const Layout& l, Geom& g) {
+  g.nx = cfg->nx;
+  g.ny = cfg->ny;
+  g.nz = cfg->nz;
+  g.N = (long long)cfg->nx * cfg->ny * cfg->nz;
+  g.q = cfg->lattice;
+  for (int f = 0; f < 6; ++f) {
+    g.face[f] = cfg->face_bc[f];
+    if (cfg->lattice == 9 && f >= 4) g.face[f] = PSCLBM_PERIODIC;
+    for (int k = 0; k < 3; ++k) g.face_u[f][k] = cfg->face_velocity[f][k];
+  }
+  for (int a = 0; a < 3; ++a) g.periodic[a] = axis_is_periodic(cfg, a) ? 1 : 0;
+  g.ntx = l.ntx;
+  g.nty = l.nty;
+  g.ntz = l.ntz;
+  g.twx = l.twx;
+  g.twy = l.twy;
+  g.remap = l.twx == SEG ? 1 : 0;
+  g.nt_even = nt_even(cfg);
+  g.rho0 = cfg->rho0;
+}
+
 int sticky(psclbm_ctx* c, bool clear) {
   unsigned bits = 0;
   int rc = hip_ok(hipMemcpyAsync(&bits, c->err, sizeof(unsigned), hipMemcpyDeviceToHost,
@@ -220,26 +243,7 @@ int lbm_init(const psclbm_config* cfg, void* d_workspace, size_t bytes, void* hi
   c->cfg = *cfg;
   c->stream = static_cast<hipStream_t>(hip_stream);
   char* base = static_cast<char*>(d_workspace);
-  Geom& g = c->geom;
-  g.nx = cfg->nx;
-  g.ny = cfg->ny;
-  g.nz = cfg->nz;
-  g.N = (long long)cfg->nx * cfg->ny * cfg->nz;
-  g.q = cfg->lattice;
-  for (int f = 0; f < 6; ++f) {
-    g.face[f] = cfg->face_bc[f];
-    if (cfg->lattice == 9 && f >= 4) g.face[f] = PSCLBM_PERIODIC;
-    for (int k = 0; k < 3; ++k) g.face_u[f][k] = cfg->face_velocity[f][k];
-  }
-  for (int a = 0; a < 3; ++a) g.periodic[a] = axis_is_periodic(cfg, a) ? 1 : 0;
-  g.ntx = l.ntx;
-  g.nty = l.nty;
-  g.ntz = l.ntz;
-  g.twx = l.twx;
-  g.twy = l.twy;
-  g.remap = l.twx == SEG ? 1 : 0;
-  g.nt_even = nt_even(cfg);
-  g.rho0 = cfg->rho0;
+  fill_geom(cfg, l, c->geom);
   c->prec = cfg->precision;
   c->f = base + l.f;
   c->err = reinterpret_cast<unsigned*>(base + l.err);

@@ -89,6 +89,9 @@ SIGNATURES = {
     "coupled_step": (_I, [_VP, ctypes.POINTER(DemParams), _VP, _VP, _VP, _VP, _I, _I]),
     "lbm_recompute": (_I, [_VP, _VP, _I, _VP]),
     "psc_rasterize_adjoint": (_I, [_VP, _VP, _I, _VP]),
+    # bandwidth ceilings (include/psclbm_probe.h)
+    "psclbm_stream_copy": (_I, [_VP, _VP, _SZ, _VP]),
+    "psclbm_stream_swap": (_I, [_VP, ctypes.c_longlong, _I, _VP]),
 }
 
 _lib = None
@@ -135,6 +138,28 @@ def _stream() -> int:
 # ---------------------------------------------------------------------------
 # The C functions under their own names
 # ---------------------------------------------------------------------------
+
+def psclbm_stream_copy(src: torch.Tensor, dst: torch.Tensor) -> None:
+    """Copy src to dst (same byte size, a multiple of 16) with the library's
+    streaming copy kernel, on torch's current stream."""
+    if not (src.is_cuda and dst.is_cuda and src.is_contiguous() and dst.is_contiguous()):
+        raise ValueError("expected contiguous CUDA tensors")
+    nbytes = src.numel() * src.element_size()
+    if dst.numel() * dst.element_size() != nbytes:
+        raise ValueError("size mismatch")
+    _check(load().psclbm_stream_copy(src.data_ptr(), dst.data_ptr(), nbytes, _stream()),
+           "psclbm_stream_copy")
+
+
+def psclbm_stream_swap(a: torch.Tensor, q: int) -> None:
+    """The data movement of an even lattice step over the q FP32 arrays of a
+    (shape [q, n]), on torch's current stream."""
+    if not (a.is_cuda and a.dtype == torch.float32 and a.is_contiguous() and a.dim() == 2
+            and a.shape[0] == q):
+        raise ValueError("expected a contiguous CUDA float32 tensor of shape [q, n]")
+    _check(load().psclbm_stream_swap(a.data_ptr(), a.shape[1], q, _stream()),
+           "psclbm_stream_swap")
+
 
 def psclbm_workspace_bytes(cfg: Config) -> int:
     return int(load().psclbm_workspace_bytes(ctypes.byref(cfg)))

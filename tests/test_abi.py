@@ -9,20 +9,23 @@ import pytest
 import workloads as W
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "psclbm.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 
 
 def _declared_functions():
-    src = open(HEADER).read()
-    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    names = re.findall(r"^(?:[A-Za-z_]+[\s*]+)+([a-z_]+)\s*\(", src, flags=re.M)
+    names = []
+    for header in HEADERS:
+        src = open(header).read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        names += re.findall(r"^(?:[A-Za-z_]+[\s*]+)+([a-z_]+)\s*\(", src, flags=re.M)
     return sorted(set(n for n in names if n not in ("if", "while")))
 
 
 def test_header_declares_the_hot_path_calls():
     names = _declared_functions()
     for n in ("lbm_init", "psc_rasterize", "lbm_step", "particle_forces", "dem_step",
-              "lbm_mass", "psclbm_workspace_bytes"):
+              "lbm_mass", "psclbm_workspace_bytes", "psclbm_stream_copy", "psclbm_stream_swap"):
         assert n in names
 
 
