@@ -49,14 +49,18 @@ def force_scale(lat, f, p):
     L = oracle.Lattice(lat, f)
     rho, u = L.macros()
     rho = rho.reshape(-1)
-    u = u.reshape(-1, 3)
+    absu = np.abs(u.reshape(-1, 3)).sum(axis=1)
+    absU = np.abs(p.u).sum(axis=1)
+    absW = np.abs(p.omega).sum(axis=1) * 20
+    absF = float(np.abs(np.asarray(lat.force)).sum())
     scale = np.zeros(p.n)
-    F = np.asarray(lat.force)
-    for n in np.nonzero(nslot)[0]:
-        for k in range(nslot[n]):
-            s = ids[n, k]
-            scale[s] += rho[n] * (np.abs(u[n]).sum() + np.abs(p.u[s]).sum() +
-                                  np.abs(p.omega[s]).sum() * 20) + np.abs(F).sum()
+    covered = np.nonzero(nslot)[0]
+    for k in range(ids.shape[1]):
+        sel = covered[nslot[covered] > k]
+        if sel.size == 0:
+            break
+        s = ids[sel, k]
+        np.add.at(scale, s, rho[sel] * (absu[sel] + absU[s] + absW[s]) + absF)
     return scale
 
 

@@ -35,11 +35,29 @@ def _block_2d(seed=13):
     return lat, W.Particles(x, u, w, np.full(n, 5.0)), dem
 
 
-def test_coupled_step_vjp_matches_autograd():
+def _block_3d(seed=15):
+    # spheres r = 4 in a 2 x 2 x 2 block resting on the wall at x = -1/2 of a
+    # walled D3Q19 box (periodic y, z), neighbours and the bottom layer
+    # overlapping by 0.02, in fluid, gravity along -x
+    lat = W.LatticeSpec(q=19, nx=24, ny=20, nz=20, tau=0.8,
+                        faces=(W.BOUNCE_BACK, W.BOUNCE_BACK) + (W.PERIODIC,) * 4)
+    rng = np.random.default_rng(seed)
+    pts = [[3.48 + i * 7.98, 5.0 + j * 7.98, 5.0 + k * 7.98]
+           for i in range(2) for j in range(2) for k in range(2)]
+    n = len(pts)
+    x = np.array(pts) + rng.normal(0.0, 0.005, (n, 3))
+    u = rng.normal(0.0, 1e-3, (n, 3))
+    w = rng.normal(0.0, 2e-4, (n, 3))
+    dem = W.DemSpec(g=(-2e-4, 0.0, 0.0), E_p=1e-3, gamma=1e-5, eta_n=0.05)
+    return lat, W.Particles(x, u, w, np.full(n, 4.0)), dem
+
+
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_coupled_step_vjp_matches_autograd(case):
     import paper_1901_09745_amd.psclbm as P
     from paper_1901_09745_amd.autograd import coupled_step_vjp
-    print("case: coupled step vjp, 2d disk block", flush=True)
-    lat, p, dem = _block_2d()
+    print(f"case: coupled step vjp, {case} block", flush=True)
+    lat, p, dem = _block_2d() if case == "2d" else _block_3d()
     ref = oracle.Lattice(lat)
     D = oracle.Dem(lat, dem, p.n)
     pr = p.copy()
@@ -71,12 +89,13 @@ def test_coupled_step_vjp_matches_autograd():
     rng = np.random.default_rng(17)
     lam = rng.normal(size=f_t.shape)
     a, b, c = (rng.normal(size=(p.n, 3)) for _ in range(3))
-    a[:, 2] = b[:, 2] = 0.0
-    c[:, :2] = 0.0
+    if lat.q == 9:
+        a[:, 2] = b[:, 2] = 0.0
+        c[:, :2] = 0.0
     dev = [torch.from_numpy(np.ascontiguousarray(m)).cuda() for m in (lam, a, b, c)]
     out = coupled_step_vjp(G, prm, torch.from_numpy(f_t).cuda(), before, *dev)
     G.sync()
-    q = 9
+    q = lat.q
     ft = torch.tensor(f_t.reshape(q, -1), dtype=torch.float64, requires_grad=True)
     X, U, Wt = (torch.tensor(m, dtype=torch.float64, requires_grad=True)
                 for m in (p_t.x, p_t.u, p_t.omega))
@@ -93,15 +112,16 @@ def test_coupled_step_vjp_matches_autograd():
         assert np.abs(got - w).max() <= 1e-10 * scale, (k, np.abs(got - w).max(), scale)
 
 
-def test_coupled_run_gradient_matches_autograd():
+@pytest.mark.parametrize("case", ["2d", "3d"])
+def test_coupled_run_gradient_matches_autograd(case):
     # autograd.coupled_run over six steps with moving particles: dJ/d(x0,
     # u0, omega0, f0) for J a random functional of the final state, against
     # torch autograd of the oracle statements over the same six steps (each
     # with the contact set the C oracle formed)
     import paper_1901_09745_amd.psclbm as P
     from paper_1901_09745_amd.autograd import coupled_run
-    print("case: coupled run gradient, 2d disk block, 6 steps", flush=True)
-    lat, p, dem = _block_2d(seed=14)
+    print(f"case: coupled run gradient, {case} block, 6 steps", flush=True)
+    lat, p, dem = _block_2d(seed=14) if case == "2d" else _block_3d(seed=16)
     K = 6
     ref = oracle.Lattice(lat)
     f0 = np.array(ref.f, copy=True)
@@ -123,12 +143,13 @@ def test_coupled_run_gradient_matches_autograd():
     rng = np.random.default_rng(19)
     lam = rng.normal(size=f0.shape)
     a, b, c = (rng.normal(size=(p.n, 3)) for _ in range(3))
-    a[:, 2] = b[:, 2] = 0.0
-    c[:, :2] = 0.0
+    if lat.q == 9:
+        a[:, 2] = b[:, 2] = 0.0
+        c[:, :2] = 0.0
     J = sum((torch.from_numpy(m).cuda() * v).sum()
             for m, v in ((a, X), (b, U), (c, Wt), (lam, f)))
     got = torch.autograd.grad(J, xs)
-    q = 9
+    q = lat.q
     ft = torch.tensor(f0.reshape(q, -1), dtype=torch.float64, requires_grad=True)
     Xt, Ut, Wtt = (torch.tensor(m, dtype=torch.float64, requires_grad=True)
                    for m in (p.x, p.u, p.omega))

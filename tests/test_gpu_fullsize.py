@@ -139,3 +139,66 @@ def test_2d_workload_fp32_storage_limit_is_not_hit():
         for form in ("fp64", "fp32", "fp16"):
             cfg = P.make_config(w.lattice, form, w.particles.n, 12.0, 64)
             assert P.psclbm_workspace_bytes(cfg) > 0
+
+
+def _window(w, steps, form="fp64"):
+    """steps coupled steps from the workload's initial state (rest, its
+    particle placement) by coupled_step and by the oracle's coupled loop:
+    (relative f error, max position error, max force error over the L1 size
+    of each particle's Eq. 14 summands plus the rounding floor)."""
+    import paper_1901_09745_amd.psclbm as P
+    G, dp = _gpu(w, form)
+    G.coupled_step(P.make_dem_params(w.dem), dp, steps)
+    F, _ = G.forces()
+    G.sync()
+    f = G.get_f().cpu().numpy()
+    x = dp.x.cpu().numpy()
+    ref = oracle.Lattice(w.lattice)
+    D = oracle.Dem(w.lattice, w.dem, w.particles.n)
+    pr = w.particles.copy()
+    f_prev = p_prev = None
+    for _ in range(steps):
+        f_prev, p_prev = ref.f.copy(), pr.copy()
+        F_ref, T_ref = ref.step(pr)
+        D.step(pr, F_ref, T_ref)
+    scale = force_scale(w.lattice, f_prev, p_prev)
+    floor = force_floor(w.lattice, f_prev, p_prev)
+    dF = np.abs(F.cpu().numpy() - F_ref).max(axis=1)
+    return relerr(f, ref.f), float(np.abs(x - pr.x).max()), float(
+        (dF / (1e-12 * scale + floor + 1e-300)).max())
+
+
+def test_2d_workload_window_from_rest():
+    # the 2D workload, 100 coupled steps (JKR DEM with gravity) from its
+    # initial state, GPU against the oracle from the same start
+    w = W.c2()
+    print(f"case: {w.description}, 100-step window", flush=True)
+    ef, ex, rF = _window(w, 100)
+    print(f"f rel err {ef:.3e}, x err {ex:.3e}, force err / bound {rF:.3f}")
+    assert ef < 1e-12
+    assert ex < 1e-9
+    assert rF <= 1.0
+
+
+def test_3d_workload_window_from_rest():
+    # the 3D workload (256^3, 8000 spheres with prescribed velocities), five
+    # coupled steps from rest, GPU against the oracle from the same start
+    w = W.c3()
+    print(f"case: {w.description}, 5-step window", flush=True)
+    ef, ex, rF = _window(w, 5)
+    print(f"f rel err {ef:.3e}, x err {ex:.3e}, force err / bound {rF:.3f}")
+    assert ef < 1e-12
+    assert ex < 1e-12
+    assert rF <= 1.0
+
+
+def test_packing_workload_window_from_rest():
+    # the 3D packing (384x192x192, walls on x, 20000 JKR spheres, gravity),
+    # five coupled steps from rest, GPU against the oracle from the same start
+    w = W.c5()
+    print(f"case: {w.description}, 5-step window", flush=True)
+    ef, ex, rF = _window(w, 5)
+    print(f"f rel err {ef:.3e}, x err {ex:.3e}, force err / bound {rF:.3f}")
+    assert ef < 1e-12
+    assert ex < 1e-9
+    assert rF <= 1.0
