@@ -1,34 +1,44 @@
 """Benchmark of the MI355X PSC-LBM hot path.
 
-One "step" is one coupled time step of the whole hot path on the 2D workload
-(D2Q9 tau=0.7, 1024^2 periodic, 2000 disks r~U(6,12), JKR DEM, gravity on the
-particles): rasterisation -> fused PSC collide-stream with the Eq. 14
-force/torque reduction and the mass partials -> DEM step driven by that
-step's FP64 force/torque accumulators, run by coupled_step (which fuses the
-next step's rasterisation into the DEM kernel).  Inputs are resident in HBM
-before the timed region.
+One "step" is one time step of the whole hot path on the 3D workload (D3Q19
+tau=0.6, 256^3 periodic, 8000 spheres r~U(4,6) with prescribed velocities
+~N(0, 1e-3^2)), in the FP32-compute / FP32-shifted-storage form:
+rasterisation of the spheres at their current positions -> the fused PSC
+collide-stream with the Eq. 14 force/torque reduction and the FP64 mass
+partials -> the particle update (advection by the prescribed velocity, with
+the next step's rasterisation fused into it), run by coupled_step.  Its
+distributions (1.27 GB in FP32) live in HBM, far beyond the 256 MB last-level
+cache.  Inputs are resident in HBM before the timed region; the timed region
+is the median of five repetitions of max(--steps, 200) steps.
 
 The JSON line reports:
-  value          MLUPS (lattice cell updates per second / 1e6) of the coupled
-                 step in the FP32-compute / FP32-shifted-storage form;
-  forms          the same for the FP64 and FP16-storage forms;
-  roofline       the dominant kernel (the fused collide-stream) of the value's
-                 form: algorithmic bytes 2*Q*s per cell per launch over its
-                 event-timed average duration, against the 8 TB/s HBM peak;
-  hbm_bound      the 3D workload (D3Q19 tau=0.6, 256^3 periodic, 8000
-                 spheres with prescribed velocities), whose distributions do
-                 not fit in the on-chip caches, per form;
+  value          MLUPS (lattice cell updates per second / 1e6) of that step;
+  roofline       its dominant kernel, the fused collide-stream k_step<19,fp32>:
+                 algorithmic bytes 2*Q*s per cell per launch over its average
+                 launch duration (HIP events around each launch on the
+                 library's stream), against the 8 TB/s HBM peak;
+  ceiling        the same volume moved by the library's own copy kernel and by
+                 the even step's data movement without arithmetic, GB/s;
+  forms_3d       the 3D workload in the FP64 and FP16-storage forms, with each
+                 form's velocity / drag / mass-drift error against FP64;
+  packing_3d     the 3D packing workload (D3Q19 tau=0.65 384x192x192, walls on
+                 x, 20000 JKR spheres settling under gravity, FP16 storage),
+                 coupled steps with DEM contacts, and its forms' errors;
+  cache_resident the 2D workload (D2Q9 tau=0.7 1024^2 periodic, 2000 JKR
+                 disks), whose distributions fit in the last-level cache, and
+                 its forms' errors;
   adjoint        differentiable runs of the drag through torch.autograd
                  (forward with checkpoints, backward by ring recompute + the
                  hand-written FP64 adjoint): the time of the backward over
                  that of the forward, on the 2D inlet/outlet channel (D2Q9
                  tau=0.8 512x256, 64 fixed disks r=8, 4000 steps, checkpoint
-                 every 100, J = drag of disk 0) and on the last 500 steps of
-                 a 20000-step settling run of the 3D packing (D3Q19
-                 384x192x192, 20000 spheres, FP16 storage, checkpoint every
-                 50, J = drag of the 100 lowest spheres), the window with FP64
-                 and with FP16-storage forwards;
-  cpu_baseline   the FP64 oracle timed on the host on a bounded sample.
+                 every 100, J = drag of disk 0 at the last step) and on the
+                 last 500 steps of a 20000-step settling run of the 3D
+                 packing (checkpoint every 50, J = drag of the 100 lowest
+                 spheres summed over the 500 steps), the window with FP64 and
+                 with FP16-storage forwards;
+  cpu_baseline   the FP64 oracle timed on the host, at all cores and at one
+                 thread, on bounded samples of the 3D workload.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-3d]
 """
@@ -56,22 +66,24 @@ def _log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def run_form(w, form, steps, warmup, coupled=True, observe=False):
+def run_form(w, form, steps, warmup, coupled=True, observe=False, reps=1, ksteps=100,
+             cap=64):
     """Time `steps` coupled steps of workload w in precision form `form`
-    (coupled_step: rasterize -> fused collide-stream with forces -> DEM, the
-    next step's rasterisation fused into the DEM kernel), then the step
-    kernel's launches.  Returns (ms_per_step, avg step-kernel ms)."""
+    (coupled_step: rasterize -> fused collide-stream with forces -> DEM or
+    advection, the next step's rasterisation fused into the DEM kernel), `reps`
+    times, then `ksteps` step-kernel launches between event pairs.  Returns
+    (median ms per coupled step, mean step-kernel ms, observation or None,
+    details: every repetition's ms per step and the even / odd step-kernel
+    means)."""
     import torch
     import paper_1901_09745_amd.psclbm as P
 
     lat = w.lattice
     rmax = float(w.particles.r.max())
     G = P.Lattice(lat, form, max_particles=w.particles.n, max_radius=rmax,
-                  max_tile_particles=64, max_contacts=16)
+                  max_tile_particles=cap, max_contacts=16)
     p = P.DeviceParticles.from_host(w.particles)
     n = p.n
-    F = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
-    T = torch.zeros((n, 3), dtype=torch.float64, device="cuda")
     prm = P.make_dem_params(w.dem)
     ctx = G.ctx
 
@@ -96,25 +108,30 @@ def run_form(w, form, steps, warmup, coupled=True, observe=False):
     run(warmup)
     torch.cuda.synchronize()
     G.sync()
-    # timed region 1: the coupled steps alone
-    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    start.record()
-    run(steps)
-    end.record()
-    torch.cuda.synchronize()
-    total_ms = start.elapsed_time(end)
+    # timed regions: the coupled steps alone
+    per = []
+    for _ in range(reps):
+        start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        start.record()
+        run(steps)
+        end.record()
+        torch.cuda.synchronize()
+        per.append(start.elapsed_time(end) / steps)
     G.sync()
-    # timed region 2: the same workload continued as separate calls, with an
-    # event pair around each step-kernel launch (on the library's stream,
-    # torch's current stream)
-    ksteps = min(steps, 100)
+    # the same workload continued as separate calls, with an event pair around
+    # each step-kernel launch (on the library's stream, torch's current
+    # stream); launches alternate between the even and the odd step
+    par0 = P.lbm_step_count(ctx) % 2
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(ksteps)]
     for k in range(ksteps):
         one(evs[k])
     torch.cuda.synchronize()
-    kern_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    kt = [a.elapsed_time(b) for a, b in evs]
+    kern_ms = float(np.mean(kt))
+    even = [t for k, t in enumerate(kt) if (par0 + k) % 2 == 0]
+    odd = [t for k, t in enumerate(kt) if (par0 + k) % 2 == 1]
     G.sync()
     mass = G.mass()
     if not np.isfinite(mass):
@@ -126,13 +143,67 @@ def run_form(w, form, steps, warmup, coupled=True, observe=False):
         _, uo = G.macros()
         obs = {"F": Fo.clone(), "u": uo, "mass0": mass0, "mass1": mass}
     del G
-    return total_ms / steps, kern_ms, obs
+    torch.cuda.empty_cache()
+    det = {"ms_per_step_reps": per,
+           "step_kernel_ms_even": float(np.mean(even)) if even else None,
+           "step_kernel_ms_odd": float(np.mean(odd)) if odd else None}
+    return float(np.median(per)), kern_ms, obs, det
 
 
-def run_adjoint(lat, p, steps, every, label, select, precision="fp64", f0=None):
+def form_errors(obs, ref):
+    """Velocity, drag and mass-drift error of each form's observation against
+    the FP64 form's on the same trajectory (the FP64 form matches the oracle
+    within 1e-12 per step)."""
+    out = {}
+    for form, ob in obs.items():
+        du = float((ob["u"] - ref["u"]).abs().max() / ref["u"].abs().max())
+        dF = float((ob["F"] - ref["F"]).abs().max() / max(float(ref["F"].abs().max()), 1e-300))
+        out[form] = {"velocity_max_rel_err": du, "drag_max_rel_err": dF,
+                     "mass_drift_rel": (ob["mass1"] - ob["mass0"]) / ob["mass0"],
+                     "mass_vs_fp64_rel": (ob["mass1"] - ref["mass1"]) / ref["mass1"]}
+    return out
+
+
+def ceilings(n_cells, q=19, reps=20):
+    """The library's bandwidth-ceiling kernels on the volume of one lattice of
+    n_cells cells and q FP32 distributions: a streaming copy of that many
+    bytes, and the even step's data movement without arithmetic (read and
+    write in place).  Median GB/s over `reps` launches each."""
+    import torch
+    import paper_1901_09745_amd.psclbm as P
+
+    a = torch.zeros((q, n_cells), dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    out = {}
+    for name, fn in (("copy", lambda: P.psclbm_stream_copy(a, b)),
+                     ("swap", lambda: P.psclbm_stream_swap(a, q))):
+        for _ in range(3):
+            fn()
+        ts = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        out[name] = {"GBs": 2 * 4 * q * n_cells / (ms * 1e-3) / 1e9, "ms": ms}
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_moved": 2 * 4 * q * n_cells,
+            "copy_GBs": out["copy"]["GBs"], "swap_GBs": out["swap"]["GBs"],
+            "attainable_GBs": max(out["copy"]["GBs"], out["swap"]["GBs"]),
+            "note": "psclbm_stream_copy (16-byte non-temporal loads and stores per thread) and "
+                    "psclbm_stream_swap (the even step's in-place exchange of the 19 FP32 "
+                    "arrays, no arithmetic), each the median of 20 launches"}
+
+
+def run_adjoint(lat, p, steps, every, label, select, precision="fp64", f0=None, window=1):
     """Forward and backward wall time of a differentiable run from state f0
-    (None: rest): J = the x drag (Eq. 14) at the last of `steps` steps summed
-    over the particles `select`, with its gradient w.r.t. all particle
+    (None: rest): J = the x drag (Eq. 14) summed over the last `window` of
+    `steps` steps and over the particles `select`, with its gradient w.r.t.
+    all particle
     positions, velocities, spins and the face velocities (checkpoint every
     `every` steps).  The run is made twice and the second one is timed."""
     import torch
@@ -150,7 +221,7 @@ def run_adjoint(lat, p, steps, every, label, select, precision="fp64", f0=None):
                           requires_grad=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        F, _ = psc_drag(x, u, om, fu, lat, r, steps, checkpoint_every=every, window=1,
+        F, _ = psc_drag(x, u, om, fu, lat, r, steps, checkpoint_every=every, window=window,
                         precision=precision, f0=f0)
         J = F[sel, 0].sum()
         torch.cuda.synchronize()
@@ -168,7 +239,7 @@ def run_adjoint(lat, p, steps, every, label, select, precision="fp64", f0=None):
     torch.cuda.empty_cache()
     return {"workload": label, "cells": lat.ncells, "particles": p.n,
             "forward_precision": precision, "adjoint_precision": "fp64", "steps": steps,
-            "checkpoint_every": every, "J": J, "max_abs_dJ_dX": gx, "forward_ms": fwd,
+            "checkpoint_every": every, "window": window, "J": J, "max_abs_dJ_dX": gx, "forward_ms": fwd,
             "backward_ms": bwd, "ratio": bwd / fwd, "forward_ms_per_step": fwd / steps,
             "backward_ms_per_step": bwd / steps}
 
@@ -487,30 +558,59 @@ def run_drag(cases, precision="fp32", chunk=1000, tol=1e-5, max_steps=150_000):
     return out
 
 
-def cpu_baseline(w, budget_s=15.0):
-    """The FP64 oracle on the host: coupled steps of the same workload for
-    about budget_s seconds."""
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(w, budget_s, threads):
+    """The FP64 oracle's coupled steps of workload w (Table 1 + the PSC step +
+    the particle update), timed for about budget_s seconds at `threads`
+    OpenMP threads: (MLUPS, steps, seconds)."""
     import oracle
 
+    oracle.set_num_threads(threads)
     L = oracle.Lattice(w.lattice)
     D = oracle.Dem(w.lattice, w.dem, w.particles.n)
     p = w.particles.copy()
-    t0 = time.perf_counter()
-    F, T = L.step(p)
-    D.step(p, F, T)
-    t1 = time.perf_counter()
-    per = t1 - t0
-    nsteps = max(1, int(budget_s / max(per, 1e-6)))
-    t0 = time.perf_counter()
-    for _ in range(nsteps):
+    steps, t0 = 0, time.perf_counter()
+    while True:
         F, T = L.step(p)
         D.step(p, F, T)
-    dt = time.perf_counter() - t0
-    return {"value": w.lattice.ncells * nsteps / dt / 1e6, "unit": "MLUPS",
-            "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"{nsteps} coupled FP64 steps (PSC-LBM + JKR DEM) of the full "
-                      f"{w.lattice.nx}x{w.lattice.ny} / {w.particles.n}-disk workload, "
-                      f"{dt:.1f} s, OpenMP cell loop, brute-force contact search"}
+        steps += 1
+        dt = time.perf_counter() - t0
+        if dt >= budget_s or dt / steps * (steps + 1) > 1.5 * budget_s:
+            break
+    return w.lattice.ncells * steps / dt / 1e6, steps, dt
+
+
+def cpu_baseline(budget_s=15.0):
+    """The FP64 oracle on the host on bounded samples of the 3D workload: at
+    every core the benchmark's own 256^3 workload, at one thread the same
+    recipe at half the linear size (128^3, 1000 spheres: the rate per cell is
+    that of the full box, whose single-thread step alone would take close to
+    a minute)."""
+    import oracle
+    import workloads as W
+
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    full = W.c3()
+    v_all, n_all, t_all = _oracle_rate(full, budget_s, cores)
+    half = W.c3(scale=0.5)
+    v_one, n_one, t_one = _oracle_rate(half, budget_s, 1)
+    oracle.set_num_threads(cores)
+    return {"value": v_all, "unit": "MLUPS", "cores": cores, "kind": "oracle",
+            "sample": f"{n_all} coupled FP64 steps of the 256^3 / 8000-sphere workload in "
+                      f"{t_all:.1f} s, OpenMP cell loop on {cores} threads",
+            "one_thread": {"value": v_one, "unit": "MLUPS", "cores": 1,
+                           "sample": f"{n_one} coupled FP64 steps of the same recipe at "
+                                     f"128^3 / {half.particles.n} spheres in {t_one:.1f} s"},
+            "cpu_model": _cpu_model(), "host_cpus": os.cpu_count()}
 
 
 # the sources the step kernel is compiled from
@@ -545,10 +645,11 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=200)
     ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--reps", type=int, default=5, help="timed repetitions (median reported)")
     ap.add_argument("--forms", default="fp32,fp64,fp16")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-3d", action="store_true")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D packing and adjoint legs")
+    ap.add_argument("--cpu-budget", type=float, default=12.0)
     ap.add_argument("--adjoint-steps", type=int, default=4000,
                     help="steps of the differentiable channel run (0: skip)")
     ap.add_argument("--adjoint-3d-steps", type=int, default=500,
@@ -564,9 +665,6 @@ def main():
                     help="sphere diameters of the packed-bed (Sec. 3.4) runs ('' to skip)")
     ap.add_argument("--no-drag", action="store_true",
                     help="skip the fixed-sphere drag runs (Sec. 3.2)")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="first run a plain 1 GiB device copy (the reference kernel that "
-                         "scales the FETCH_SIZE / WRITE_SIZE counters to bytes)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: one GPU is measured; --gpus {args.gpus} is not supported (the "
@@ -577,101 +675,125 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
-    if args.calibrate_copy:
-        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
-        b = torch.empty_like(a)
-        for _ in range(3):
-            b.copy_(a)
-        torch.cuda.synchronize()
-        del a, b
+    steps = max(args.steps, 200)
+    reps = max(args.reps, 1)
+    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
+    head = "fp32" if "fp32" in forms else forms[0]
+
+    # ---- the headline: the 3D workload, every form, FP32 first ----
+    _log("bench: generating the 3D workload")
+    w3 = W.c3()
+    N3 = w3.lattice.ncells
+    res3, obs3 = {}, {}
+    for form in [head] + [f for f in forms if f != head]:
+        _log(f"bench: 3D coupled step, form {form}")
+        ms, kms, ob, det = run_form(w3, form, steps, args.warmup, observe=True, reps=reps)
+        obs3[form] = ob
+        b = 2 * 19 * STORE_BYTES[form] * N3
+        res3[form] = {"mlups": N3 / (ms * 1e-3) / 1e6, "ms_per_step": ms,
+                      "step_kernel_ms": kms, "step_kernel_GBs": b / (kms * 1e-3) / 1e9,
+                      "frac_of_hbm_peak": b / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                      "bytes_per_launch": b, **det}
+    if "fp64" in obs3:
+        for form, e in form_errors(obs3, obs3["fp64"]).items():
+            res3[form]["vs_fp64"] = e
+    obs3.clear()
+    torch.cuda.empty_cache()
+    _log("bench: bandwidth ceilings")
+    ceil = ceilings(N3, 19)
+    hr = res3[head]
+    ach = hr["step_kernel_GBs"]
+    roof = {"kernel": f"k_step<19,{head}> (fused PSC collide-stream, 3D workload)",
+            "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": _traffic(f"k_step_d3q19_{head}_c3"),
+            "algorithmic_bytes_per_launch": hr["bytes_per_launch"],
+            "frac_of_attainable": ach / ceil["attainable_GBs"]}
+
+    # ---- the 3D packing: walled box, JKR contacts, its own FP16 form ----
+    pack = None
+    if not args.no_3d:
+        _log("bench: generating the 3D packing workload")
+        w5 = W.c5()
+        N5 = w5.lattice.ncells
+        pack, obs5 = {}, {}
+        for form in ["fp16"] + [f for f in forms if f != "fp16"]:
+            _log(f"bench: 3D packing coupled step, form {form}")
+            ms, kms, ob, det = run_form(w5, form, steps, args.warmup, observe=True, reps=reps)
+            obs5[form] = ob
+            b = 2 * 19 * STORE_BYTES[form] * N5
+            pack[form] = {"mlups": N5 / (ms * 1e-3) / 1e6, "ms_per_step": ms,
+                          "step_kernel_ms": kms, "step_kernel_GBs": b / (kms * 1e-3) / 1e9,
+                          "frac_of_hbm_peak": b / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                          "bytes_per_launch": b, **det}
+        if "fp64" in obs5:
+            for form, e in form_errors(obs5, obs5["fp64"]).items():
+                pack[form]["vs_fp64"] = e
+        obs5.clear()
+        torch.cuda.empty_cache()
+
+    # ---- the 2D workload (cache-resident) ----
     _log("bench: generating the 2D workload")
     w2 = W.c2()
-    forms = [f.strip() for f in args.forms.split(",") if f.strip()]
-    res = {}
+    N2 = w2.lattice.ncells
+    res2, obs2 = {}, {}
     for form in forms:
         _log(f"bench: 2D coupled step, form {form}")
-        ms, kms, _ = run_form(w2, form, args.steps, args.warmup)
-        N = w2.lattice.ncells
-        bytes_launch = 2 * 9 * STORE_BYTES[form] * N
-        res[form] = {"mlups": N / (ms * 1e-3) / 1e6, "ms_per_step": ms,
-                     "step_kernel_ms": kms,
-                     "step_kernel_GBs": bytes_launch / (kms * 1e-3) / 1e9}
-    head = "fp32" if "fp32" in res else forms[0]
+        ms, kms, ob, det = run_form(w2, form, steps, args.warmup, observe=True, reps=reps)
+        obs2[form] = ob
+        b = 2 * 9 * STORE_BYTES[form] * N2
+        res2[form] = {"mlups": N2 / (ms * 1e-3) / 1e6, "ms_per_step": ms,
+                      "step_kernel_ms": kms, "step_kernel_GBs": b / (kms * 1e-3) / 1e9,
+                      **det}
+    if "fp64" in obs2:
+        for form, e in form_errors(obs2, obs2["fp64"]).items():
+            res2[form]["vs_fp64"] = e
+    obs2.clear()
+    torch.cuda.empty_cache()
     fric2d = None
-    if args.friction_steps > 0 and head in res:
+    if args.friction_steps > 0 and head in res2:
         import dataclasses
         _log(f"bench: 2D coupled step with friction, form {head}")
         w2f = dataclasses.replace(w2, dem=dataclasses.replace(w2.dem, **FRICTION))
-        ms, kms, _ = run_form(w2f, head, args.steps, args.warmup)
-        fric2d = {"workload": "the 2D benchmark workload with sliding, twisting and rolling "
+        ms, kms, _, _ = run_form(w2f, head, steps, args.warmup, reps=reps)
+        fric2d = {"workload": "the 2D workload with sliding, twisting and rolling "
                               "friction (contacts gathered by the DEM kernel)",
-                  "form": head, "ms_per_step": ms,
-                  "mlups": w2.lattice.ncells / (ms * 1e-3) / 1e6,
-                  "frictionless_ms_per_step": res[head]["ms_per_step"],
+                  "form": head, "ms_per_step": ms, "mlups": N2 / (ms * 1e-3) / 1e6,
+                  "frictionless_ms_per_step": res2[head]["ms_per_step"],
                   "params": dict(FRICTION)}
 
-    hbm = {}
-    obs3 = {}
-    if not args.no_3d:
-        _log("bench: generating the 3D workload")
-        w3 = W.c3()
-        for form in forms:
-            _log(f"bench: 3D step, form {form}")
-            ms, kms, ob = run_form(w3, form, max(20, args.steps // 4), max(5, args.warmup // 4),
-                                   observe=True)
-            obs3[form] = ob
-            N = w3.lattice.ncells
-            b = 2 * 19 * STORE_BYTES[form] * N
-            hbm[form] = {"mlups": N / (ms * 1e-3) / 1e6, "ms_per_step": ms,
-                         "step_kernel_ms": kms,
-                         "step_kernel_GBs": b / (kms * 1e-3) / 1e9,
-                         "frac_of_hbm_peak": b / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS,
-                         "bytes_per_launch": b}
-
-    if "fp64" in obs3:
-        # accuracy of each form against the FP64 form on the same trajectory
-        # (prescribed particle motion, the same step count); FP64 itself
-        # matches the oracle within 1e-12
-        import torch
-        ref = obs3["fp64"]
-        for form, ob in obs3.items():
-            du = float((ob["u"] - ref["u"]).abs().max() / ref["u"].abs().max())
-            dF = float((ob["F"] - ref["F"]).abs().max() / ref["F"].abs().max())
-            hbm[form]["vs_fp64"] = {
-                "velocity_max_rel_err": du, "drag_max_rel_err": dF,
-                "mass_drift_rel": (ob["mass1"] - ob["mass0"]) / ob["mass0"]}
-        obs3.clear()
-        torch.cuda.empty_cache()
-    N = w2.lattice.ncells
-    ach = res[head]["step_kernel_GBs"]
-    roof = {"kernel": f"k_step<9,{head}> (fused PSC collide-stream)", "bound": "hbm",
-            "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": ach / HBM_PEAK_GBS,
-            "traffic": _traffic(f"k_step_d2q9_{head}_c2"),
-            "algorithmic_bytes_per_launch": 2 * 9 * STORE_BYTES[head] * N,
-            "note": "the 2D workload's distributions (75 MB FP64 / 38 MB FP32) fit in the "
-                    "256 MB Infinity Cache; see hbm_bound for the HBM-resident 3D workload"}
     out = {
         "metric": METRIC,
-        "value": res[head]["mlups"],
+        "value": hr["mlups"],
         "unit": "MLUPS",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": steps,
         "warmup": args.warmup,
-        "ms_per_step": res[head]["ms_per_step"],
+        "repetitions": reps,
+        "steps_requested": args.steps,
+        "ms_per_step": hr["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": DTYPE[head],
-        "data": "synthetic (seeded RSA particle placement)",
-        "config": {"workload": "D2Q9 tau=0.7 1024x1024 periodic, 2000 disks r~U(6,12), "
-                               "JKR DEM, coupled step: rasterize + PSC collide-stream + "
-                               "forces + DEM",
-                   "cells": N, "particles": w2.particles.n, "precision_form": head},
-        "forms": res,
-        "hbm_bound": ({"workload": "D3Q19 tau=0.6 256^3 periodic, 8000 spheres r~U(4,6), "
-                                   "prescribed velocities (rasterize + step + advection)",
-                       **hbm} if hbm else None),
+        "data": "synthetic (seeded RSA particle placement, seeded velocities)",
+        "config": {"workload": "D3Q19 tau=0.6 256^3 periodic, 8000 spheres r~U(4,6) seed 3, "
+                               "prescribed velocities N(0,1e-3^2); step: rasterize + PSC "
+                               "collide-stream + Eq. 14 forces + FP64 mass partials + "
+                               "advection",
+                   "cells": N3, "particles": w3.particles.n, "precision_form": head},
         "roofline": roof,
+        "ceiling": ceil,
+        "frac_fp64": res3.get("fp64", {}).get("frac_of_hbm_peak"),
+        "frac_fp16": res3.get("fp16", {}).get("frac_of_hbm_peak"),
+        "frac_packing_fp16": (pack or {}).get("fp16", {}).get("frac_of_hbm_peak"),
+        "forms_3d": res3,
+        "packing_3d": ({"workload": "D3Q19 tau=0.65 384x192x192, walls at x=-1/2 and 383.5, "
+                                    "20000 JKR spheres r~U(3,5) seed 5 from rest, gravity 1e-6 "
+                                    "along -x; coupled step with DEM contacts", **pack}
+                       if pack else None),
+        "cache_resident": {"workload": "D2Q9 tau=0.7 1024^2 periodic, 2000 disks r~U(6,12) "
+                                       "seed 2, JKR DEM; its distributions (38-75 MB) fit in "
+                                       "the 256 MB last-level cache", **res2},
     }
     if fric2d is not None:
         out["friction"] = {"disks_2d": fric2d}
@@ -684,9 +806,7 @@ def main():
             w4.lattice, w4.particles, args.adjoint_steps, 100,
             "D2Q9 tau=0.8 512x256 channel from rest, equilibrium inlet u=0.02, outlet rho=1, "
             "64 fixed disks r=8; J = x drag of disk 0 at the last step", [0])}
-        if args.adjoint_3d_steps > 0:
-            _log("bench: generating the 3D packing workload")
-            w5 = W.c5()
+        if args.adjoint_3d_steps > 0 and not args.no_3d:
             _log(f"bench: settling the 3D packing for {args.settle_steps} coupled steps")
             f0, p5, settle = settle_packing(w5, args.settle_steps)
             adj["packing_3d_settle"] = settle
@@ -698,18 +818,18 @@ def main():
                                 "rolling friction",
                     **run_friction(w5, f0, p5, args.friction_steps)}
             lowest = np.argsort(p5.x[:, 0])[:100].tolist()
+            win = args.adjoint_3d_steps
             label = (f"D3Q19 tau=0.65 384x192x192, walls on x, 20000 spheres r~U(3,5) after "
                      f"{args.settle_steps} coupled steps from rest (FP16 storage, JKR DEM, "
                      "gravity 1e-6 along -x), held fixed over the window; J = x drag (along "
-                     "gravity) of the 100 lowest spheres at the last step")
+                     f"gravity) of the 100 lowest spheres summed over the {win} steps")
             for prec in ("fp64", "fp16"):
                 _log(f"bench: adjoint of a 3D packing window, {prec} forward")
                 adj[f"packing_3d_{prec}"] = run_adjoint(
-                    w5.lattice, p5, args.adjoint_3d_steps, 50, label, lowest, precision=prec,
-                    f0=f0)
+                    w5.lattice, p5, win, 50, label, lowest, precision=prec, f0=f0, window=win)
             del f0
         adj["coupled_run_2d"] = {
-            "workload": "the 2D benchmark workload (1024x1024, 2000 JKR disks), 100 coupled "
+            "workload": "the 2D workload (1024x1024, 2000 JKR disks), 100 coupled "
                         "steps with moving particles, FP64, J = mean final x",
             **adj_run}
         adj["ratio"] = adj["channel_2d"]["ratio"]
@@ -737,7 +857,7 @@ def main():
                               (10, 10.0, 0.02), (10, 1.0, 0.05)])}
     if not args.no_cpu:
         _log("bench: CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(w2, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_budget)
     print(json.dumps(out), flush=True)
 
 
