@@ -301,6 +301,34 @@ const char* psclbm_strerror(int code);
  * lbm_set_equilibrium (the in-place streaming parity is its low bit). */
 long long lbm_step_count(const psclbm_ctx* ctx);
 
+/* ---- without allocation ------------------------------------------------- */
+
+/* Bytes of the fixed device array psc_solid_fraction_noalloc works in. */
+#define PSCLBM_NOALLOC_SCRATCH_BYTES 33554432
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * solid fractions that psc_rasterize followed by psc_get_solid_fraction give
+ * (same kernels, same results), for the lattice cfg describes and the
+ * particles p, with no context and no workspace.  Outputs as in
+ * psc_get_solid_fraction: d_eps_total[N], and with kslots > 0 d_slot_id and
+ * d_slot_eps [N*kslots] (both then required).  The tile lists and the
+ * particle snapshot live in a fixed device array of
+ * PSCLBM_NOALLOC_SCRATCH_BYTES bytes inside the library, one per GPU, held
+ * until the process ends; the call uses the current device's copy, clears
+ * what must start at zero, enqueues its kernels on hip_stream and then
+ * synchronises that stream to read the device error word back (so it
+ * returns once the outputs are written).  Calls that overlap on one GPU
+ * (from several threads or streams) share the array and race.  Errors:
+ * EINVAL (invalid cfg, n outside [0, max_particles], null pointers, or
+ * tile lists and snapshot needing more than PSCLBM_NOALLOC_SCRATCH_BYTES:
+ * 8 + 4 ntiles (2 + max_tile_particles) + 144 n bytes, about, with ntiles =
+ * N / 256), EHIP, ESLOTS (a tile list or a cell overflowed), EINVAL for a
+ * radius outside the domain of Eqs. 17/19.  Nothing is allocated. */
+int psc_solid_fraction_noalloc(const psclbm_config* cfg, const psclbm_particles* p,
+                               double* d_eps_total, int* d_slot_id, double* d_slot_eps,
+                               int kslots, void* hip_stream);
+
 /* ---- adjoint ------------------------------------------------------------ */
 
 /* Adjoint of one lbm_step (FP64), for gradients of any function J of the

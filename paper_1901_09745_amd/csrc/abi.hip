@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 
 #include "common.hpp"
@@ -217,6 +218,45 @@ int sticky(psclbm_ctx* c, bool clear) {
   if (bits & ERR_CONTACTS) return PSCLBM_ECONTACTS;
   if (bits & ERR_RADIUS) return PSCLBM_EINVAL;
   return PSCLBM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of psc_solid_fraction_noalloc: one fixed device array per GPU,
+// holding the error word, the tile counts, the tile lists, the particle
+// snapshot and the force rows the rasterisation clears.  Host code reaches it
+// only through the address hipGetSymbolAddress returns for the current
+// device (the array's name is not a device address on the host).
+// ---------------------------------------------------------------------------
+constexpr size_t NOALLOC_BYTES = 32u << 20;
+static_assert(NOALLOC_BYTES == (size_t)PSCLBM_NOALLOC_SCRATCH_BYTES, "scratch size of the header");
+static __device__ __align__(256) __attribute__((used)) unsigned char scratch[NOALLOC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mutex;
+void* scratch_ptr[MAX_DEVICES];
+
+// The current device's address of the scratch array, looked up on its first
+// use on that device (with that device current).
+int scratch_address(void** out) {
+  int dev = 0;
+  int rc = hip_ok(hipGetDevice(&dev));
+  if (rc) return rc;
+  if (dev < 0 || dev >= MAX_DEVICES) return PSCLBM_EHIP;
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_ptr[dev]) {
+    void* p = nullptr;
+    rc = hip_ok(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (rc) return rc;
+    scratch_ptr[dev] = p;
+  }
+  *out = scratch_ptr[dev];
+  return PSCLBM_OK;
+}
+
+__global__ void k_zero_words(unsigned* p, long long n) {
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x)
+    p[k] = 0u;
 }
 
 }  // namespace
@@ -521,6 +561,59 @@ int psc_rasterize_adjoint(psclbm_ctx* ctx, const double* d_g_slot_eps, int kslot
   if (!ctx->rasterized) return PSCLBM_ESTATE;
   if (ctx->np == 0) return PSCLBM_OK;
   return launch_rasterize_adjoint(ctx, d_g_slot_eps, kslots, d_g_x);
+}
+
+int psc_solid_fraction_noalloc(const psclbm_config* cfg, const psclbm_particles* p,
+                               double* d_eps_total, int* d_slot_id, double* d_slot_eps,
+                               int kslots, void* hip_stream) {
+  if (!cfg || !p || !d_eps_total || kslots < 0) return PSCLBM_EINVAL;
+  int rc = validate(cfg);
+  if (rc) return rc;
+  if (cfg->max_particles < 1 || p->n < 0 || p->n > cfg->max_particles) return PSCLBM_EINVAL;
+  if (p->n > 0 && (!p->x || !p->u || !p->omega || !p->radius)) return PSCLBM_EINVAL;
+  if (kslots > 0 && (!d_slot_id || !d_slot_eps)) return PSCLBM_EINVAL;
+  const Layout l = plan(cfg);
+  const int np = p->n > 0 ? p->n : 1;
+  // the scratch layout: error word, two sets of tile counts, tile lists,
+  // snapshot, one block of force rows (cleared by the rasterisation)
+  const size_t o_err = 0;
+  const size_t o_cnt = align_up(sizeof(unsigned));
+  const size_t o_list = o_cnt + align_up(sizeof(int) * 2 * (size_t)l.ntiles);
+  const size_t o_snap = o_list + align_up(sizeof(int) * (size_t)l.ntiles * cfg->max_tile_particles);
+  const size_t o_facc = o_snap + align_up(sizeof(PSnap) * (size_t)np);
+  const size_t need = o_facc + align_up(sizeof(double) * 6 * (size_t)np);
+  if (need > NOALLOC_BYTES) return PSCLBM_EINVAL;
+  void* sp = nullptr;
+  rc = scratch_address(&sp);
+  if (rc) return rc;
+  char* base = static_cast<char*>(sp);
+  psclbm_ctx c;
+  std::memset(&c, 0, sizeof(c));
+  c.cfg = *cfg;
+  c.stream = static_cast<hipStream_t>(hip_stream);
+  fill_geom(cfg, l, c.geom);
+  c.err = reinterpret_cast<unsigned*>(base + o_err);
+  c.tile_count_buf[0] = reinterpret_cast<int*>(base + o_cnt);
+  c.tile_count_buf[1] = c.tile_count_buf[0] + l.ntiles;
+  c.tile_cur = 0;
+  c.tile_count = c.tile_count_buf[0];
+  c.tile_list = reinterpret_cast<int*>(base + o_list);
+  c.ntiles = l.ntiles;
+  c.snap = reinterpret_cast<PSnap*>(base + o_snap);
+  c.facc[0] = c.facc[1] = reinterpret_cast<double*>(base + o_facc);
+  // the array keeps the last call's contents: clear the error word and the
+  // tile counts with a kernel (no memset node, no allocation)
+  const long long words = (long long)(o_list / sizeof(unsigned));
+  k_zero_words<<<(unsigned)((words + 255) / 256 < 4096 ? (words + 255) / 256 : 4096), 256, 0,
+                 c.stream>>>(reinterpret_cast<unsigned*>(base), words);
+  rc = hip_ok(hipGetLastError());
+  if (!rc) rc = launch_rasterize(&c, p, false);
+  if (rc) return rc;
+  c.np = p->n;
+  rc = launch_solid_fraction(&c, d_eps_total, kslots > 0 ? d_slot_id : nullptr,
+                             kslots > 0 ? d_slot_eps : nullptr, kslots);
+  if (rc) return rc;
+  return sticky(&c, false);
 }
 
 const char* psclbm_strerror(int code) {

@@ -89,6 +89,8 @@ SIGNATURES = {
     "coupled_step": (_I, [_VP, ctypes.POINTER(DemParams), _VP, _VP, _VP, _VP, _I, _I]),
     "lbm_recompute": (_I, [_VP, _VP, _I, _VP]),
     "psc_rasterize_adjoint": (_I, [_VP, _VP, _I, _VP]),
+    "psc_solid_fraction_noalloc": (_I, [ctypes.POINTER(Config), ctypes.POINTER(ParticlesC), _VP,
+                                        _VP, _VP, _I, _VP]),
     # bandwidth ceilings (include/psclbm_probe.h)
     "psclbm_stream_copy": (_I, [_VP, _VP, _SZ, _VP]),
     "psclbm_stream_swap": (_I, [_VP, ctypes.c_longlong, _I, _VP]),
@@ -205,6 +207,19 @@ def psc_get_solid_fraction(ctx: int, eps_total: Optional[torch.Tensor],
                            kslots: int) -> None:
     _check(load().psc_get_solid_fraction(ctx, _ptr(eps_total), _ptr(slot_id, torch.int32),
                                          _ptr(slot_eps), kslots), "psc_get_solid_fraction")
+
+
+def psc_solid_fraction_noalloc(cfg: Config, x: torch.Tensor, u: torch.Tensor,
+                               omega: torch.Tensor, radius: torch.Tensor,
+                               eps_total: torch.Tensor, slot_id: Optional[torch.Tensor],
+                               slot_eps: Optional[torch.Tensor], kslots: int) -> int:
+    """The context-free solid fractions (no allocation); returns the C code
+    (the caller decides how to treat errors)."""
+    n = radius.numel()
+    p = ParticlesC(n, _ptr(x), _ptr(u), _ptr(omega), _ptr(radius))
+    return int(load().psc_solid_fraction_noalloc(
+        ctypes.byref(cfg), ctypes.byref(p), _ptr(eps_total), _ptr(slot_id, torch.int32),
+        _ptr(slot_eps), kslots, _stream()))
 
 
 def lbm_step(ctx: int, nsteps: int = 1) -> None:
