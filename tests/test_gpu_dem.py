@@ -99,7 +99,7 @@ def test_coupled_steps_parity():
         G.dem_step(prm, dp)          # forces of the step, read in place
     G.sync()
     f = G.get_f().cpu().numpy()
-    assert relerr(f, ref.f) < 1e-11
+    assert relerr(f, ref.f) < 1e-12
     assert np.abs(dp.x.cpu().numpy() - pr.x).max() < 1e-9
     assert np.abs(dp.u.cpu().numpy() - pr.u).max() < 1e-11
 
@@ -141,7 +141,7 @@ def test_coupled_step_entry_matches_oracle(case, calls):
             D.step(pr, F_ref, T_ref)
         G.coupled_step(prm, dp, k)
     G.sync()
-    assert relerr(G.get_f().cpu().numpy(), ref.f) < 1e-11
+    assert relerr(G.get_f().cpu().numpy(), ref.f) < 1e-12
     assert np.abs(dp.x.cpu().numpy() - pr.x).max() < 1e-9
     assert np.abs(dp.u.cpu().numpy() - pr.u).max() < 1e-11
     F, T = G.forces()

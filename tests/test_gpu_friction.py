@@ -148,7 +148,7 @@ def test_coupled_step_with_friction(case):
             D.step(pr, F_ref, T_ref)
         G.coupled_step(prm, dp, k)
     G.sync()
-    assert relerr(G.get_f().cpu().numpy(), ref.f) < 1e-11
+    assert relerr(G.get_f().cpu().numpy(), ref.f) < 1e-12
     _assert_close(dp, pr)
 
 
@@ -181,7 +181,7 @@ def test_coupled_and_separate_steps_mixed():
                 G.step(1)
                 G.dem_step(prm, dp)
     G.sync()
-    assert relerr(G.get_f().cpu().numpy(), ref.f) < 1e-11
+    assert relerr(G.get_f().cpu().numpy(), ref.f) < 1e-12
     _assert_close(dp, pr)
 
 

@@ -43,7 +43,7 @@ def test_packing_parameters_parity(adhesive):
     dp = P.DeviceParticles.from_host(p)
     G.coupled_step(P.make_dem_params(dem), dp, 30)
     G.sync()
-    assert relerr(G.get_f().cpu().numpy(), ref.f) < 1e-11
+    assert relerr(G.get_f().cpu().numpy(), ref.f) < 1e-12
     assert np.abs(dp.x.cpu().numpy() - pr.x).max() < 1e-9
     assert np.abs(dp.u.cpu().numpy() - pr.u).max() < 1e-11
     assert np.abs(dp.omega.cpu().numpy() - pr.omega).max() < 1e-11

@@ -9,7 +9,8 @@ import pytest
 
 import oracle
 import workloads as W
-from helpers import CASES, _particles, _print_case, case_particles, force_scale, gpu_lattice, gpu_run, oracle_run, relerr
+from helpers import (CASES, _particles, _print_case, case_particles, force_floor, force_scale,
+                     gpu_lattice, gpu_run, oracle_run, relerr)
 
 pytestmark = pytest.mark.gpu
 
@@ -115,13 +116,30 @@ def test_c1_full_run():
     _print_case(test="c1", steps=w.steps)
     ref, F_ref, T_ref = oracle_run(w.lattice, None, w.particles, w.steps)
     _, f, F, T = gpu_run(w.lattice, None, w.particles, w.steps)
-    assert relerr(f, ref.f) < 1e-12
+    df = float(np.abs(f - ref.f).max())
+    assert df < 1e-12 * np.abs(ref.f).max()
     rho_r, u_r = ref.macros()
     Lg = oracle.Lattice(w.lattice, f)
     rho_g, u_g = Lg.macros()
-    assert relerr(u_g, u_r) < 1e-10
-    assert abs(F[0, 0] - F_ref[0, 0]) < 1e-11 * abs(F_ref[0, 0])
-    assert abs(F[0, 1] - F_ref[0, 1]) < 1e-11 * abs(F_ref[0, 0])
+    # Eq. 5 carries a state difference df into the velocity as at most
+    # sum_i |df_i| (1 + |u|) / rho <= Q df (1 + |u|max) / rho_min per cell
+    q = w.lattice.q
+    umax = float(np.abs(u_r).max())
+    du_bound = q * df * (1.0 + umax) / float(rho_r.min())
+    print(f"f err {df:.3e}, u err {np.abs(u_g - u_r).max():.3e} (bound {du_bound:.3e})")
+    assert np.abs(u_g - u_r).max() <= du_bound
+    # the drag (Eq. 14) of the last step: the order-dependent rounding of its
+    # sum (1e-12 of the L1 size of the summands, and the rounding floor of
+    # u), plus the state difference carried by each covered cell's exchange
+    # B rho (u_s - u) + F, at most B (|d rho| |u| + rho |du|) per cell
+    nslot, _, _, _ = oracle.rasterize(w.lattice, w.particles.x, w.particles.r)
+    ncov = int((nslot > 0).sum())
+    F_bound = (1e-12 * force_scale(w.lattice, ref.f, w.particles)[0]
+               + force_floor(w.lattice, ref.f, w.particles)[0]
+               + ncov * (q * df * umax + float(rho_r.max()) * du_bound))
+    print(f"drag err {np.abs(F[0, :2] - F_ref[0, :2]).max():.3e} (bound {F_bound:.3e}, "
+          f"drag {F_ref[0, 0]:.3e})")
+    assert np.abs(F[0, :2] - F_ref[0, :2]).max() <= F_bound
 
 
 def test_mass_and_roundtrip():
