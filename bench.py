@@ -614,7 +614,7 @@ def cpu_baseline(budget_s=15.0):
 
 
 # the sources the step kernel is compiled from
-KERNEL_SOURCES = ("lbm.hip", "common.hpp", "tiles.hpp", "dem.hpp")
+KERNEL_SOURCES = ("lbm.hip", "common.hpp", "tiles.hpp", "dem.hpp", "dem.hip")
 
 
 def kernel_digest():
@@ -665,6 +665,11 @@ def main():
                     help="sphere diameters of the packed-bed (Sec. 3.4) runs ('' to skip)")
     ap.add_argument("--no-drag", action="store_true",
                     help="skip the fixed-sphere drag runs (Sec. 3.2)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the 3D workload's forms and the ceilings (for profiler runs)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 1 GiB three times with the library's streaming copy (the "
+                         "reference dispatch that scales the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: one GPU is measured; --gpus {args.gpus} is not supported (the "
@@ -675,6 +680,14 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        import paper_1901_09745_amd.psclbm as P
+        a = torch.ones(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
+        b = torch.empty_like(a)
+        for _ in range(3):
+            P.psclbm_stream_copy(a, b)
+        torch.cuda.synchronize()
+        del a, b
     steps = max(args.steps, 200)
     reps = max(args.reps, 1)
     forms = [f.strip() for f in args.forms.split(",") if f.strip()]
@@ -708,6 +721,12 @@ def main():
             "frac": ach / HBM_PEAK_GBS, "traffic": _traffic(f"k_step_d3q19_{head}_c3"),
             "algorithmic_bytes_per_launch": hr["bytes_per_launch"],
             "frac_of_attainable": ach / ceil["attainable_GBs"]}
+
+    if args.headline_only:
+        print(json.dumps({"metric": METRIC, "value": hr["mlups"], "unit": "MLUPS", "n_gpus": 1,
+                          "steps": steps, "repetitions": reps, "ms_per_step": hr["ms_per_step"],
+                          "roofline": roof, "ceiling": ceil, "forms_3d": res3}), flush=True)
+        return
 
     # ---- the 3D packing: walled box, JKR contacts, its own FP16 form ----
     pack = None
