@@ -483,17 +483,16 @@ __global__ void __launch_bounds__(BLOCK) k_adjoint(const AdjArgs a) {
     }
   }
 
-  // flush the tile's particle gradients
+  // flush the tile's particle gradients, one (entry, component) pair per
+  // thread so that a tile's atomics are issued together
   __syncthreads();
-  for (int e = threadIdx.x; e < cnt; e += BLOCK) {
-    const double* ac = acc + 9 * e;
+  for (int t = threadIdx.x; t < 9 * cnt; t += BLOCK) {
+    const int e = t / 9, k = t - 9 * e;
+    const double v = acc[t];
+    if (v == 0.0) continue;
     const int id = lds[e].id;
-#pragma unroll
-    for (int t = 0; t < 3; ++t) {
-      if (a.gX && ac[t] != 0.0) atomicAdd(a.gX + 3 * id + t, ac[t]);
-      if (a.gU && ac[3 + t] != 0.0) atomicAdd(a.gU + 3 * id + t, ac[3 + t]);
-      if (a.gW && ac[6 + t] != 0.0) atomicAdd(a.gW + 3 * id + t, ac[6 + t]);
-    }
+    double* dst = k < 3 ? a.gX : (k < 6 ? a.gU : a.gW);
+    if (dst) atomicAdd(dst + 3 * id + (k % 3), v);
   }
 }
 
