@@ -313,7 +313,7 @@ __global__ void __launch_bounds__(BLOCK)
   C Bn_cell = 0;
   const C F0 = (C)a.force[0], F1 = (C)a.force[1], F2 = (C)a.force[2];
   const double tm = a.tau - 0.5;
-  double S_ = 0.0, den = 1.0, inv_den = 1.0;
+  double S_ = 0.0, den = 1.0, inv_den = 1.0, bscale = 1.0;
   if (active) {
     // ---- load f as deviations g_i = f_i - w_i rho0 ----
 #pragma unroll
@@ -342,6 +342,84 @@ __global__ void __launch_bounds__(BLOCK)
     return (int)(((k < 2 ? e01 : e23) >> (16 * (k & 1))) & 0xffffu);
   };
   static_assert(KSLOTS == 4, "entries packed for four slots");
+
+  // ---- the covering particles, slot by slot ----
+  // the row's y and z as FP64, converted from their scalar registers at each
+  // use: an empty asm makes each use opaque, so the compiler does not hold
+  // (or spill) one converted copy across the slots
+  auto row_coord = [](int v) {
+    asm volatile("" : "+s"(v));
+    return (double)v;
+  };
+  constexpr int NV = D == 3 ? 6 : 3;
+  // particle s of slot k at this cell: its share B_s, the weight of its
+  // momentum exchange (Eq. 14 weighs it by B_s, Eq. 11 by the cell's B_n),
+  // u_s - u and u_s + u with u_s the rigid-body velocity at the cell centre,
+  // and the cell centre's offset from the particle centre
+  struct SlotKin {
+    C Bs, Bm, dv[3], sv[3], r[3];
+  };
+  auto slot_kin = [&](int k) {
+    SlotKin t;
+    t.Bs = a.original ? (C)(s.eps[k] * tm / ((1.0 - s.eps[k]) + tm)) : (C)(s.eps[k] * bscale);
+    t.Bm = a.original ? Bn_cell : t.Bs;
+    const LdsEntry& P = lds[slot_e(k)];
+    const double rx = min_image((double)x - P.x, d.px, d.nx);
+    const double ry = min_image(row_coord(y) - P.y, d.py, d.ny);
+    const double rz = D == 3 ? min_image(row_coord(z) - P.z, d.pz, d.nz) : 0.0;
+    const C usx = (C)(P.u[0] + P.w[1] * rz - P.w[2] * ry);
+    const C usy = (C)(P.u[1] + P.w[2] * rx - P.w[0] * rz);
+    const C usz = D == 3 ? (C)(P.u[2] + P.w[0] * ry - P.w[1] * rx) : (C)0;
+    t.dv[0] = usx - ux;
+    t.dv[1] = usy - uy;
+    t.dv[2] = usz - uz;
+    t.sv[0] = usx + ux;
+    t.sv[1] = usy + uy;
+    t.sv[2] = usz + uz;
+    t.r[0] = (C)rx;
+    t.r[1] = (C)ry;
+    t.r[2] = (C)rz;
+    return t;
+  };
+  // the negated momentum exchange of Eq. 14, m_s = B [rho (u_s - u) + F]:
+  // force, then torque about the particle centre
+  auto exchange = [&](const SlotKin& t, C (&mv)[NV]) {
+    const C mx = t.Bm * (rho * t.dv[0] + F0);
+    const C my = t.Bm * (rho * t.dv[1] + F1);
+    mv[0] = -mx;
+    mv[1] = -my;
+    if constexpr (D == 3) {
+      const C mz = t.Bm * (rho * t.dv[2] + F2);
+      mv[2] = -mz;
+      mv[3] = -(t.r[1] * mz - t.r[2] * my);
+      mv[4] = -(t.r[2] * mx - t.r[0] * mz);
+      mv[5] = -(t.r[0] * my - t.r[1] * mx);
+    } else {
+      mv[2] = -(t.r[0] * my - t.r[1] * mx);
+    }
+  };
+  // added to the list entry's FP64 accumulators in LDS
+  auto accumulate = [&](int e, const C (&mv)[NV]) {
+    double* ac = acc + 6 * e;
+    atomicAdd(ac + 0, (double)mv[0]);
+    atomicAdd(ac + 1, (double)mv[1]);
+    if constexpr (D == 3) {
+      atomicAdd(ac + 2, (double)mv[2]);
+      atomicAdd(ac + 3, (double)mv[3]);
+      atomicAdd(ac + 4, (double)mv[4]);
+      atomicAdd(ac + 5, (double)mv[5]);
+    } else {
+      atomicAdd(ac + 5, (double)mv[2]);
+    }
+  };
+  // periodic 3D reduced-precision forms: the particles' equilibrium difference
+  // enters the collision through ten per-cell moments (one pass over the
+  // directions); the others add it slot by slot after the collision (with
+  // walls, the moments' registers cost spills of loaded populations)
+  constexpr bool FOLD = D == 3 && PREC != PSCLBM_FP64 && !WALLS;
+  // no body force: the Guo terms vanish (uniform over the launch)
+  const bool forced = __builtin_amdgcn_readfirstlane(
+                          (int)(a.force[0] != 0.0 || a.force[1] != 0.0 || a.force[2] != 0.0)) != 0;
 
   if (active) {
     // ---- inlet / outlet layers: reset to an equilibrium before collision ----
@@ -441,8 +519,8 @@ __global__ void __launch_bounds__(BLOCK)
     const C kguo = (C)1 - (C)0.5 * omega;
     const C uF = ux * F0 + uy * F1 + uz * F2;
 
-    // Weights (Eq. 13 with the cell total clamped at one, Table 1): B_n from the clamped cell total;
-    // each particle's share B_s is formed in the second pass below.  The
+    // Weights (Eq. 13 with the cell total clamped at one, Table 1): B_n from
+    // the clamped cell total, each particle's share B_s per slot.  The
     // original weighting (Eq. 9) takes each particle's B_s from its own
     // fraction and B_n as their sum.
 #pragma unroll
@@ -451,6 +529,10 @@ __global__ void __launch_bounds__(BLOCK)
     const double en = S_ < 1.0 ? S_ : 1.0;
     den = (1.0 - en) + tm;
     if (s.n > 0) inv_den = 1.0 / den;
+    // share of each particle: Eq. 13 when the fractions sum to at most one,
+    // else eps_{n,s} / sum (the clamped total has B_n = 1)
+    bscale = tm * inv_den;
+    if (S_ > 1.0) bscale = 1.0 / S_;
     double Bn_d = s.n > 0 ? en * tm * inv_den : 0.0;
     if (a.original) {
       Bn_d = 0.0;
@@ -463,112 +545,137 @@ __global__ void __launch_bounds__(BLOCK)
     const C omB = (C)1 - Bn;
     const C relax = omB * omega;
 
-    // ---- pass 1: BGK + Guo weighted by (1 - B_n), plus the bounce-back of the
-    // non-equilibrium part, B_n (fneq_{-i} - fneq_i); one opposite pair at a
-    // time (Eqs. 2-4, 10, 12) ----
-    {
-      const C wi = (C)L::w(0);
-      const C fneq = g[0] - wmul<Q>(0, drho - rho * (C)1.5 * uu);
-      g[0] = g[0] - relax * fneq - omB * kguo * wi * (C)3 * uF;
-    }
+    if constexpr (FOLD) {
+      // ---- the slots: the moments A = sum_s B_s (u_s - u) and the symmetric
+      // M = sum_s B_s (u_s u_s - u u) (diagonal in mD, off-diagonal doubled
+      // in mH, formed as B_s [(u_s - u)(u_s + u)^T + transpose] / 2), and the
+      // momentum exchange ----
+      C mA[3] = {0, 0, 0}, mD[3] = {0, 0, 0}, mH[3] = {0, 0, 0};
+      if (s.n > 0) {
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      const int o = L::opp(i);
-      if (o < i) continue;
-      const C wi = (C)L::w(i);
-      const C eu = edot(L::ex(i), L::ey(i), L::ez(i), ux, uy, uz);
-      const C eF = edot(L::ex(i), L::ey(i), L::ez(i), F0, F1, F2);
-      const C sym = drho + rho * ((C)4.5 * eu * eu - (C)1.5 * uu);
-      const C fn_i = g[i] - wmul<Q>(i, sym + rho * (C)3 * eu);
-      const C fn_o = g[o] - wmul<Q>(i, sym - rho * (C)3 * eu);
-      // Guo term (Eq. 4): even and odd parts under e -> -e
-      const C Fsym = kguo * wi * ((C)9 * eu * eF - (C)3 * uF);
-      const C Fant = kguo * wi * ((C)3 * eF);
-      const C bb = Bn * (fn_o - fn_i);
-      g[i] = g[i] - relax * fn_i + omB * (Fsym + Fant) + bb;
-      g[o] = g[o] - relax * fn_o + omB * (Fsym - Fant) - bb;
+        for (int k = 0; k < KSLOTS; ++k) {
+          if (k >= s.n) continue;
+          const SlotKin t = slot_kin(k);
+          C b[3];
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            b[c] = t.Bs * t.dv[c];
+            mA[c] += b[c];
+            mD[c] += b[c] * t.sv[c];
+          }
+          mH[0] += b[0] * t.sv[1] + b[1] * t.sv[0];
+          mH[1] += b[0] * t.sv[2] + b[2] * t.sv[0];
+          mH[2] += b[1] * t.sv[2] + b[2] * t.sv[1];
+          if (a.facc) {
+            C mv[NV];
+            exchange(t, mv);
+            accumulate(slot_e(k), mv);
+          }
+        }
+      }
+      // ---- one pass over the directions: BGK + Guo weighted by 1 - B_n, the
+      // bounce-back of the non-equilibrium part, B_n (fneq_{-i} - fneq_i), and
+      // the particles' sum_s B_s [f^eq_i(rho, u_s) - f^eq_i(rho, u)], which is
+      // w_i rho [3 e_i.A + 4.5 e_i.M.e_i - 1.5 tr M] (Eqs. 2-4, 10-12) ----
+      const C r3 = (C)3 * rho, r45 = (C)4.5 * rho;
+      const C pA[3] = {r3 * mA[0], r3 * mA[1], r3 * mA[2]};
+      const C pD[3] = {r45 * mD[0], r45 * mD[1], r45 * mD[2]};
+      const C pH[3] = {r45 * mH[0], r45 * mH[1], r45 * mH[2]};
+      const C p0 = (C)-1.5 * rho * (mD[0] + mD[1] + mD[2]);
+      auto collide = [&](auto guo) {
+        constexpr bool GUO = decltype(guo)::value;
+        const C gk = omB * kguo;
+        {
+          C x0 = p0;
+          if constexpr (GUO) x0 -= gk * (C)3 * uF;
+          const C fneq = g[0] - wmul<Q>(0, drho - rho * (C)1.5 * uu);
+          g[0] = g[0] - relax * fneq + wmul<Q>(0, x0);
+        }
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+          const int o = L::opp(i);
+          if (o < i) continue;
+          const int ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
+          const C eu = edot(ex, ey, ez, ux, uy, uz);
+          const C sym = drho + rho * ((C)4.5 * eu * eu - (C)1.5 * uu);
+          const C fn_i = g[i] - wmul<Q>(i, sym + rho * (C)3 * eu);
+          const C fn_o = g[o] - wmul<Q>(i, sym - rho * (C)3 * eu);
+          // the even and odd parts under e -> -e of the particles' term and
+          // of the Guo term (Eq. 4)
+          C ps = p0;
+          eacc(ex * ex, ps, pD[0]);
+          eacc(ey * ey, ps, pD[1]);
+          eacc(ez * ez, ps, pD[2]);
+          eacc(ex * ey, ps, pH[0]);
+          eacc(ex * ez, ps, pH[1]);
+          eacc(ey * ez, ps, pH[2]);
+          C pa = edot(ex, ey, ez, pA[0], pA[1], pA[2]);
+          if constexpr (GUO) {
+            const C eF = edot(ex, ey, ez, F0, F1, F2);
+            ps += gk * ((C)9 * eu * eF - (C)3 * uF);
+            pa += gk * ((C)3 * eF);
+          }
+          const C bb = Bn * (fn_o - fn_i);
+          g[i] = g[i] - relax * fn_i + bb + wmul<Q>(i, ps + pa);
+          g[o] = g[o] - relax * fn_o - bb + wmul<Q>(i, ps - pa);
+        }
+      };
+      if (forced)
+        collide(std::true_type{});
+      else
+        collide(std::false_type{});
+    } else {
+      // ---- pass 1: BGK + Guo weighted by (1 - B_n), plus the bounce-back of
+      // the non-equilibrium part, B_n (fneq_{-i} - fneq_i); one opposite pair
+      // at a time (Eqs. 2-4, 10, 12) ----
+      {
+        const C wi = (C)L::w(0);
+        const C fneq = g[0] - wmul<Q>(0, drho - rho * (C)1.5 * uu);
+        g[0] = g[0] - relax * fneq - omB * kguo * wi * (C)3 * uF;
+      }
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const int o = L::opp(i);
+        if (o < i) continue;
+        const C wi = (C)L::w(i);
+        const C eu = edot(L::ex(i), L::ey(i), L::ez(i), ux, uy, uz);
+        const C eF = edot(L::ex(i), L::ey(i), L::ez(i), F0, F1, F2);
+        const C sym = drho + rho * ((C)4.5 * eu * eu - (C)1.5 * uu);
+        const C fn_i = g[i] - wmul<Q>(i, sym + rho * (C)3 * eu);
+        const C fn_o = g[o] - wmul<Q>(i, sym - rho * (C)3 * eu);
+        // Guo term (Eq. 4): even and odd parts under e -> -e
+        const C Fsym = kguo * wi * ((C)9 * eu * eF - (C)3 * uF);
+        const C Fant = kguo * wi * ((C)3 * eF);
+        const C bb = Bn * (fn_o - fn_i);
+        g[i] = g[i] - relax * fn_i + omB * (Fsym + Fant) + bb;
+        g[o] = g[o] - relax * fn_o + omB * (Fsym - Fant) - bb;
+      }
     }
   }
 
-  // ---- pass 2 (covered cells): sum_s B_s [f^eq_i(rho, u_s) - f^eq_i(rho, u)]
-  // and the momentum exchange of Eq. 14, m_s = B_s [rho (u_s - u) + F]
-  // (force, then torque about the particle centre), added to the list
-  // entry's FP64 accumulators in LDS ----
-  {
-    // share of each particle: Eq. 13 when the fractions sum to at most one,
-    // else eps_{n,s} / sum (the clamped total has B_n = 1)
-    double bscale = tm * inv_den;
-    if (S_ > 1.0) bscale = 1.0 / S_;
-    constexpr int NV = D == 3 ? 6 : 3;
-    // the row's y and z as FP64, converted from their scalar registers at each
-    // use: an empty asm makes each use opaque, so the compiler does not hold
-    // (or spill) one converted copy across the slots
-    auto row_coord = [](int v) {
-      asm volatile("" : "+s"(v));
-      return (double)v;
-    };
+  // ---- pass 2 (covered cells of the other forms): sum_s B_s [f^eq_i(rho,
+  // u_s) - f^eq_i(rho, u)] and the momentum exchange ----
+  if constexpr (!FOLD) {
     // slot k of this cell: the equilibrium difference into g and, unless the
     // step accumulates no force (the ring step), the negated exchange into mv
     auto slot_update = [&](int k, C (&mv)[NV]) {
-      const C Bs = a.original ? (C)(s.eps[k] * tm / ((1.0 - s.eps[k]) + tm))
-                              : (C)(s.eps[k] * bscale);
-      // Eq. 14 weighs the momentum exchange by B_s; Eq. 11 by the cell's B_n
-      const C Bm = a.original ? Bn_cell : Bs;
-      const LdsEntry& P = lds[slot_e(k)];
-      const double rx = min_image((double)x - P.x, d.px, d.nx);
-      const double ry = min_image(row_coord(y) - P.y, d.py, d.ny);
-      const double rz = D == 3 ? min_image(row_coord(z) - P.z, d.pz, d.nz) : 0.0;
-      // rigid-body velocity of particle s at the cell centre
-      const C usx = (C)(P.u[0] + P.w[1] * rz - P.w[2] * ry);
-      const C usy = (C)(P.u[1] + P.w[2] * rx - P.w[0] * rz);
-      const C usz = D == 3 ? (C)(P.u[2] + P.w[0] * ry - P.w[1] * rx) : (C)0;
-      const C dvx = usx - ux, dvy = usy - uy, dvz = usz - uz;
-      const C svx = usx + ux, svy = usy + uy, svz = usz + uz;
-      const C du2 = dvx * svx + dvy * svy + dvz * svz;  // |u_s|^2 - |u|^2
-      const C rB = rho * Bs;
+      const SlotKin t = slot_kin(k);
+      const C du2 = t.dv[0] * t.sv[0] + t.dv[1] * t.sv[1] + t.dv[2] * t.sv[2];  // |u_s|^2 - |u|^2
+      const C rB = rho * t.Bs;
       g[0] -= wmul<Q>(0, rB * (C)1.5 * du2);
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
         const int o = L::opp(i);
         if (o < i) continue;
-
-        const C de = edot(L::ex(i), L::ey(i), L::ez(i), dvx, dvy, dvz);
-        const C se = edot(L::ex(i), L::ey(i), L::ez(i), svx, svy, svz);
+        const C de = edot(L::ex(i), L::ey(i), L::ez(i), t.dv[0], t.dv[1], t.dv[2]);
+        const C se = edot(L::ex(i), L::ey(i), L::ez(i), t.sv[0], t.sv[1], t.sv[2]);
         // 4.5 [(e.u_s)^2 - (e.u)^2] - 1.5 (|u_s|^2 - |u|^2), and 3 e.(u_s - u)
         const C ds_s = (C)4.5 * de * se - (C)1.5 * du2;
         const C ds_a = (C)3 * de;
         g[i] += wmul<Q>(i, rB * (ds_s + ds_a));
         g[o] += wmul<Q>(i, rB * (ds_s - ds_a));
       }
-      if (!a.facc) return;
-      const C mx = Bm * (rho * dvx + F0);
-      const C my = Bm * (rho * dvy + F1);
-      const C cx = (C)rx, cy = (C)ry;
-      mv[0] = -mx;
-      mv[1] = -my;
-      if constexpr (D == 3) {
-        const C mz = Bm * (rho * dvz + F2);
-        const C cz = (C)rz;
-        mv[2] = -mz;
-        mv[3] = -(cy * mz - cz * my);
-        mv[4] = -(cz * mx - cx * mz);
-        mv[5] = -(cx * my - cy * mx);
-      } else {
-        mv[2] = -(cx * my - cy * mx);
-      }
-    };
-    auto accumulate = [&](int e, const C (&mv)[NV]) {
-      double* ac = acc + 6 * e;
-      atomicAdd(ac + 0, (double)mv[0]);
-      atomicAdd(ac + 1, (double)mv[1]);
-      if constexpr (D == 3) {
-        atomicAdd(ac + 2, (double)mv[2]);
-        atomicAdd(ac + 3, (double)mv[3]);
-        atomicAdd(ac + 4, (double)mv[4]);
-        atomicAdd(ac + 5, (double)mv[5]);
-      } else {
-        atomicAdd(ac + 5, (double)mv[2]);
-      }
+      if (a.facc) exchange(t, mv);
     };
     if constexpr (PREC == PSCLBM_FP64 || D == 3) {
       // every covered lane adds its own exchange (the LDS unit serialises

@@ -71,3 +71,17 @@ def test_forms_moving_spheres_3d(form, tol_u, tol_F):
     assert eu < tol_u
     assert eF < tol_F
     assert em < (1e-6 if form == "fp32" else 1e-3)
+
+
+@pytest.mark.parametrize("form,tol_u,tol_F", [("fp32", 1e-5, 1e-5), ("fp16", 5e-2, 5e-2)])
+def test_forms_forced_moving_spheres_3d(form, tol_u, tol_F):
+    # the periodic 3D case above with a body force along all three axes: the
+    # collision with the Guo term (Eq. 4) and the particles' share folded in
+    import dataclasses
+    w = W.c3(scale=0.25)
+    lat = dataclasses.replace(w.lattice, force=(4e-6, -2e-6, 1e-6))
+    eu, eF, em = _run_pair(lat, w.particles, 60, form, kinematic=True)
+    print(f"form {form}: u rel err {eu:.3e}, drag rel err {eF:.3e}, mass rel err {em:.3e}")
+    assert eu < tol_u
+    assert eF < tol_F
+    assert em < (1e-6 if form == "fp32" else 1e-3)
