@@ -172,8 +172,9 @@ def ceilings(n_cells, q=19, reps=20):
     import torch
     import paper_1901_09745_amd.psclbm as P
 
-    a = torch.zeros((q, n_cells), dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
+    # non-zero data: zero-filled lines can move less than their size
+    a = torch.ones((q, n_cells), dtype=torch.float32, device="cuda")
+    b = torch.ones_like(a)
     out = {}
     for name, fn in (("copy", lambda: P.psclbm_stream_copy(a, b)),
                      ("swap", lambda: P.psclbm_stream_swap(a, q))):

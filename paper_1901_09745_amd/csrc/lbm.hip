@@ -313,7 +313,7 @@ __global__ void __launch_bounds__(BLOCK)
   C Bn_cell = 0;
   const C F0 = (C)a.force[0], F1 = (C)a.force[1], F2 = (C)a.force[2];
   const double tm = a.tau - 0.5;
-  double S_ = 0.0, den = 1.0, inv_den = 1.0, bscale = 1.0;
+  E bscale = 1;  // B_s / eps_{n,s} of the cell (Eq. 13), formed with the weights
   if (active) {
     // ---- load f as deviations g_i = f_i - w_i rho0 ----
 #pragma unroll
@@ -367,18 +367,21 @@ __global__ void __launch_bounds__(BLOCK)
     const double rx = min_image((double)x - P.x, d.px, d.nx);
     const double ry = min_image(row_coord(y) - P.y, d.py, d.ny);
     const double rz = D == 3 ? min_image(row_coord(z) - P.z, d.pz, d.nz) : 0.0;
-    const C usx = (C)(P.u[0] + P.w[1] * rz - P.w[2] * ry);
-    const C usy = (C)(P.u[1] + P.w[2] * rx - P.w[0] * rz);
-    const C usz = D == 3 ? (C)(P.u[2] + P.w[0] * ry - P.w[1] * rx) : (C)0;
+    // u_s = U + Omega x r in the arithmetic precision (the arm from its
+    // FP64 nearest image)
+    const C cx = (C)rx, cy = (C)ry, cz = (C)rz;
+    const C usx = (C)P.u[0] + (C)P.w[1] * cz - (C)P.w[2] * cy;
+    const C usy = (C)P.u[1] + (C)P.w[2] * cx - (C)P.w[0] * cz;
+    const C usz = D == 3 ? (C)P.u[2] + (C)P.w[0] * cy - (C)P.w[1] * cx : (C)0;
     t.dv[0] = usx - ux;
     t.dv[1] = usy - uy;
     t.dv[2] = usz - uz;
     t.sv[0] = usx + ux;
     t.sv[1] = usy + uy;
     t.sv[2] = usz + uz;
-    t.r[0] = (C)rx;
-    t.r[1] = (C)ry;
-    t.r[2] = (C)rz;
+    t.r[0] = cx;
+    t.r[1] = cy;
+    t.r[2] = cz;
     return t;
   };
   // the negated momentum exchange of Eq. 14, m_s = B [rho (u_s - u) + F]:
@@ -523,24 +526,35 @@ __global__ void __launch_bounds__(BLOCK)
     // the clamped cell total, each particle's share B_s per slot.  The
     // original weighting (Eq. 9) takes each particle's B_s from its own
     // fraction and B_n as their sum.
+    // In the precision the fractions are held in: FP64, or FP32 with the
+    // hardware reciprocal (1 ulp) for the FP32 arithmetic forms; the
+    // denominators are at least tau - 1/2 > 0.
+    auto recip = [](E v) -> E {
+      if constexpr (PREC == PSCLBM_FP64) return 1.0 / v;
+      else return __builtin_amdgcn_rcpf(v);
+    };
+    E S_ = 0;
 #pragma unroll
     for (int k = 0; k < KSLOTS; ++k)
       if (k < s.n) S_ += s.eps[k];
-    const double en = S_ < 1.0 ? S_ : 1.0;
-    den = (1.0 - en) + tm;
-    if (s.n > 0) inv_den = 1.0 / den;
+    const E tme = (E)tm;
+    const E en = S_ < (E)1 ? S_ : (E)1;
+    const E den = ((E)1 - en) + tme;
+    E inv_den = 1;
+    if (s.n > 0) inv_den = recip(den);
     // share of each particle: Eq. 13 when the fractions sum to at most one,
     // else eps_{n,s} / sum (the clamped total has B_n = 1)
-    bscale = tm * inv_den;
-    if (S_ > 1.0) bscale = 1.0 / S_;
-    double Bn_d = s.n > 0 ? en * tm * inv_den : 0.0;
+    bscale = tme * inv_den;
+    if (S_ > (E)1) bscale = recip(S_);
+    E Bn_e = s.n > 0 ? en * tme * inv_den : (E)0;
     if (a.original) {
-      Bn_d = 0.0;
+      double Bn_d = 0.0;
 #pragma unroll
       for (int k = 0; k < KSLOTS; ++k)
         if (k < s.n) Bn_d += s.eps[k] * tm / ((1.0 - s.eps[k]) + tm);
+      Bn_e = (E)Bn_d;
     }
-    const C Bn = (C)Bn_d;
+    const C Bn = (C)Bn_e;
     Bn_cell = Bn;
     const C omB = (C)1 - Bn;
     const C relax = omB * omega;

@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "common.hpp"
 
 namespace psclbm {
@@ -23,15 +25,24 @@ __device__ __forceinline__ double min_image(double d, int periodic, int L) {
 // Solid fraction of one (cell, particle) pair, the inside/outside rule of Table 1 with
 // Eq. 15/18: eps = V_a(r) + 1/2 - d inside the shell r +- h.
 // ---------------------------------------------------------------------------
-template <typename T>
-__device__ inline T pair_eps(T d, T r, T cs, T h) {
-  T e;
-  if (d >= r + h) e = (T)0;
-  else if (d <= r - h) e = (T)1;
+__device__ inline double pair_eps(double d, double r, double cs, double h) {
+  double e;
+  if (d >= r + h) e = 0.0;
+  else if (d <= r - h) e = 1.0;
   else e = cs - d;
-  if (e <= (T)0) e = (T)0;
-  if (e >= (T)1) e = (T)1;
+  if (e <= 0.0) e = 0.0;
+  if (e >= 1.0) e = 1.0;
   return e;
+}
+
+// Square root of v > 0 to FP64 accuracy from the hardware FP32 root, refined
+// by one Newton step in FP64 (relative error about 1e-15: the square of the
+// FP32 root's), in place of the longer correctly rounded FP64 sequence.
+__device__ __forceinline__ double sqrt_nr(double v) {
+  const float s = __builtin_amdgcn_sqrtf((float)v);
+  const double s0 = (double)s;
+  const double res = fma(-s0, s0, v);
+  return s > 0.0f ? s0 + res * (double)(0.5f * __builtin_amdgcn_rcpf(s)) : 0.0;
 }
 
 // LDS image of a tile's particle list.
@@ -168,27 +179,29 @@ __device__ inline void collect_slots(const Geom& g, int x0, int y, int z, bool a
       const LdsEntry& P = lds[valid ? e : 0];
       double dx = (double)(x0 + cl) - P.x;
       dx = wrapb ? min_image(dx, px, nx) : dx + shb;
+      const double d2 = dx * dx + dyz2b;
       // the Table 1 rule on d = sqrt(d2); the root is taken only where the
-      // fraction is not already fixed at 0 or 1 by the shell or the clamp.
-      // In the precision of the held fractions: FP64, or FP32 from the FP64
-      // separation (the FP32 forms hold and use the fraction in FP32)
-      using T = E;
-      const T d2 = (T)dx * (T)dx + (T)dyz2b;
-      const T r = (T)P.r, cs = (T)P.cs, hh = (T)h;
-      const T rh = r + hh;
-      const T rl = r - hh;
-      const T c1 = cs - (T)1;
+      // fraction is not already fixed at 0 or 1 by the shell or the clamp
+      const double rh = P.r + h;
+      const double rl = P.r - h;
+      const double c1 = P.cs - 1.0;
       const bool in_shell = valid && d2 < rh * rh;
-      const bool inner = (rl >= (T)0 && d2 <= rl * rl) || (c1 >= (T)0 && d2 <= c1 * c1);
-      const bool outer = cs <= (T)0 || d2 >= cs * cs;
-      T eps = inner ? (T)1 : (T)0;
-      if (in_shell && !inner && !outer) eps = pair_eps<T>(sqrt(d2), r, cs, hh);
+      const bool inner = (rl >= 0.0 && d2 <= rl * rl) || (c1 >= 0.0 && d2 <= c1 * c1);
+      const bool outer = P.cs <= 0.0 || d2 >= P.cs * P.cs;
+      double eps = inner ? 1.0 : 0.0;
+      if (in_shell && !inner && !outer) {
+        // the FP32 arithmetic forms take the refined FP32 root (the fraction
+        // itself stays accurate to FP64: near eps = 1 the weight B amplifies
+        // its error about (1 + tau - 1/2) / (tau - 1/2) times)
+        const double dd = std::is_same<E, float>::value ? sqrt_nr(d2) : sqrt(d2);
+        eps = pair_eps(dd, P.r, P.cs, h);
+      }
       if (in_shell && eps > 0.0) {
         const int c = wbase + cl;
         const int k = atomicAdd(&sl.n[c], 1);
         if (k < KSLOTS) {
           sl.e[k][c] = e;
-          sl.eps[k][c] = eps;
+          sl.eps[k][c] = (E)eps;
         } else if (err) {
           atomicOr(err, ERR_SLOTS);
         }
