@@ -547,6 +547,10 @@ __global__ void __launch_bounds__(BLOCK)
     bscale = tme * inv_den;
     if (S_ > (E)1) bscale = recip(S_);
     E Bn_e = s.n > 0 ? en * tme * inv_den : (E)0;
+    // a covered cell (en = 1) has B_n = 1 exactly, which the reciprocal's
+    // last bit must not undo (no BGK part may act there)
+    if constexpr (PREC != PSCLBM_FP64)
+      if (en >= (E)1) Bn_e = (E)1;
     if (a.original) {
       double Bn_d = 0.0;
 #pragma unroll
