@@ -1012,7 +1012,7 @@ __global__ void __launch_bounds__(BLOCK) k_solid_fraction(Geom g, double h, int 
 #pragma unroll
   for (int k = 0; k < KSLOTS; ++k) {
     if (k >= kout) break;
-    if (ids) ids[(size_t)c.n * kout + k] = k < s.n ? s.id[k] : -1;
+    if (ids) ids[(size_t)c.n * kout + k] = k < s.n ? lds[s.e[k]].id : -1;
     if (seps) seps[(size_t)c.n * kout + k] = k < s.n ? s.eps[k] : 0.0;
   }
   for (int k = KSLOTS; k < kout; ++k) {

@@ -54,13 +54,12 @@ struct LdsEntry {
   int pad;
 };
 
-// Slots of one cell: up to KSLOTS particles with eps > 0, ascending id.  The
-// fractions are evaluated in FP64 and held as E (FP64, or FP32 for the FP32
-// arithmetic forms, whose weights are formed in FP32 anyway).
+// Slots of one cell: up to KSLOTS particles with eps > 0, ascending particle
+// id (lds[e[k]].id).  The fractions are evaluated in FP64 and held as E (FP64,
+// or FP32 for the FP32 arithmetic forms, whose weights are formed in FP32).
 template <typename E>
 struct SlotsT {
   int n;
-  int id[KSLOTS];
   int e[KSLOTS];  // index in the tile list
   E eps[KSLOTS];
 };
@@ -146,7 +145,7 @@ __device__ inline void collect_slots(const Geom& g, int x0, int y, int z, bool a
           // the chord only bounds the cells examined (their membership is
           // decided in phase 2), so FP32 with a margin of 1e-3 lanes will do
           const double sh = shc == 1 ? -Lx : (shc == 2 ? Lx : 0.0);
-          const float half = sqrtf((float)(rh * rh - dyz2));
+          const float half = __builtin_amdgcn_sqrtf((float)(rh * rh - dyz2));
           const float c0 = (float)((P.x - sh) - (double)x0);  // centre's image, in lanes
           const float l = ceilf(c0 - half - 1e-3f), u = floorf(c0 + half + 1e-3f);
           lo = l < 0.0f ? 0 : (int)l;
@@ -180,21 +179,26 @@ __device__ inline void collect_slots(const Geom& g, int x0, int y, int z, bool a
       double dx = (double)(x0 + cl) - P.x;
       dx = wrapb ? min_image(dx, px, nx) : dx + shb;
       const double d2 = dx * dx + dyz2b;
-      // the Table 1 rule on d = sqrt(d2); the root is taken only where the
-      // fraction is not already fixed at 0 or 1 by the shell or the clamp
+      // the Table 1 rule on d = sqrt(d2)
       const double rh = P.r + h;
-      const double rl = P.r - h;
-      const double c1 = P.cs - 1.0;
       const bool in_shell = valid && d2 < rh * rh;
-      const bool inner = (rl >= 0.0 && d2 <= rl * rl) || (c1 >= 0.0 && d2 <= c1 * c1);
-      const bool outer = P.cs <= 0.0 || d2 >= P.cs * P.cs;
-      double eps = inner ? 1.0 : 0.0;
-      if (in_shell && !inner && !outer) {
-        // the FP32 arithmetic forms take the refined FP32 root (the fraction
+      double eps = 0.0;
+      if constexpr (std::is_same<E, float>::value) {
+        // the FP32 arithmetic forms: the refined FP32 root for every pair in
+        // the shell (a wave with one lane in the band takes the root for all
+        // its lanes anyway), the rule's clamps giving 0 and 1.  The fraction
         // itself stays accurate to FP64: near eps = 1 the weight B amplifies
-        // its error about (1 + tau - 1/2) / (tau - 1/2) times)
-        const double dd = std::is_same<E, float>::value ? sqrt_nr(d2) : sqrt(d2);
-        eps = pair_eps(dd, P.r, P.cs, h);
+        // its error about (1 + tau - 1/2) / (tau - 1/2) times
+        if (in_shell) eps = pair_eps(sqrt_nr(d2), P.r, P.cs, h);
+      } else {
+        // FP64: the root only where the fraction is not already fixed at 0
+        // or 1 by the shell or the clamp
+        const double rl = P.r - h;
+        const double c1 = P.cs - 1.0;
+        const bool inner = (rl >= 0.0 && d2 <= rl * rl) || (c1 >= 0.0 && d2 <= c1 * c1);
+        const bool outer = P.cs <= 0.0 || d2 >= P.cs * P.cs;
+        eps = inner ? 1.0 : 0.0;
+        if (in_shell && !inner && !outer) eps = pair_eps(sqrt(d2), P.r, P.cs, h);
       }
       if (in_shell && eps > 0.0) {
         const int c = wbase + cl;
@@ -220,27 +224,33 @@ __device__ inline void collect_slots(const Geom& g, int x0, int y, int z, bool a
     const bool has = k < n;
     s.e[k] = has ? sl.e[k][tid] : 0;
     s.eps[k] = has ? sl.eps[k][tid] : (E)0;
-    s.id[k] = has ? lds[s.e[k]].id : 0x7fffffff;
   }
+  // the ids are read and compared only where some cell of the wave holds two
+  // slots or more, and the full network only where one holds three or more
   if (__any(n > 1)) {
+    int id[KSLOTS];
+#pragma unroll
+    for (int k = 0; k < KSLOTS; ++k) id[k] = k < n ? lds[s.e[k]].id : 0x7fffffff;
     // compare-exchange network on (id, e, eps): (0,1) (2,3) (0,2) (1,3) (1,2)
     auto cx = [&](int i, int k) {
-      const bool sw = s.id[k] < s.id[i];
-      const int ti = s.id[i], te = s.e[i];
+      const bool sw = id[k] < id[i];
+      const int ti = id[i], te = s.e[i];
       const E tp = s.eps[i];
-      s.id[i] = sw ? s.id[k] : ti;
+      id[i] = sw ? id[k] : ti;
       s.e[i] = sw ? s.e[k] : te;
       s.eps[i] = sw ? s.eps[k] : tp;
-      s.id[k] = sw ? ti : s.id[k];
+      id[k] = sw ? ti : id[k];
       s.e[k] = sw ? te : s.e[k];
       s.eps[k] = sw ? tp : s.eps[k];
     };
     static_assert(KSLOTS == 4, "sorting network for four slots");
     cx(0, 1);
-    cx(2, 3);
-    cx(0, 2);
-    cx(1, 3);
-    cx(1, 2);
+    if (__any(n > 2)) {
+      cx(2, 3);
+      cx(0, 2);
+      cx(1, 3);
+      cx(1, 2);
+    }
   }
 }
 
