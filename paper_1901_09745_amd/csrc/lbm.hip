@@ -603,17 +603,15 @@ __global__ void __launch_bounds__(BLOCK)
       auto collide = [&](auto guo) {
         constexpr bool GUO = decltype(guo)::value;
         const C gk = omB * kguo;
-        // with S_i and 3 rho e_i.u the even and odd parts of the equilibrium
-        // deviation, g_i - relax (g_i - w_i (S_i + 3 rho e_i.u)) + B_n (fneq_-i
-        // - fneq_i) + w_i (P_i) regroups per opposite pair as
-        //   c g_i + B_n g_-i + w_i [(relax S_i + P_even) + ((relax + 2 B_n)
-        //   3 rho e_i.u + P_odd)],  c = 1 - relax - B_n
-        const C cg = (C)1 - relax - Bn;
-        const C rb3 = (relax + (C)2 * Bn) * (C)3 * rho;
+        // g_i - relax fneq_i + B_n (fneq_-i - fneq_i) as g_i - (relax + B_n)
+        // fneq_i + B_n fneq_-i: the non-equilibrium parts stay explicit, so an
+        // equilibrium is kept exactly (no rounding of 1 - relax - B_n enters)
+        const C rB = relax + Bn;
         {
-          C x0 = p0 + relax * (drho - rho * (C)1.5 * uu);
+          C x0 = p0;
           if constexpr (GUO) x0 -= gk * (C)3 * uF;
-          g[0] = ((C)1 - relax) * g[0] + wmul<Q>(0, x0);
+          const C fneq = g[0] - wmul<Q>(0, drho - rho * (C)1.5 * uu);
+          g[0] = g[0] - relax * fneq + wmul<Q>(0, x0);
         }
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
@@ -622,6 +620,8 @@ __global__ void __launch_bounds__(BLOCK)
           const int ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
           const C eu = edot(ex, ey, ez, ux, uy, uz);
           const C sym = drho + rho * ((C)4.5 * eu * eu - (C)1.5 * uu);
+          const C fn_i = g[i] - wmul<Q>(i, sym + rho * (C)3 * eu);
+          const C fn_o = g[o] - wmul<Q>(i, sym - rho * (C)3 * eu);
           // the even and odd parts under e -> -e of the particles' term and
           // of the Guo term (Eq. 4)
           C ps = p0;
@@ -637,11 +637,8 @@ __global__ void __launch_bounds__(BLOCK)
             ps += gk * ((C)9 * eu * eF - (C)3 * uF);
             pa += gk * ((C)3 * eF);
           }
-          const C X = relax * sym + ps;
-          const C Y = rb3 * eu + pa;
-          const C gi = g[i], go = g[o];
-          g[i] = cg * gi + Bn * go + wmul<Q>(i, X + Y);
-          g[o] = cg * go + Bn * gi + wmul<Q>(i, X - Y);
+          g[i] = g[i] - rB * fn_i + Bn * fn_o + wmul<Q>(i, ps + pa);
+          g[o] = g[o] - rB * fn_o + Bn * fn_i + wmul<Q>(i, ps - pa);
         }
       };
       if (forced)
@@ -651,26 +648,29 @@ __global__ void __launch_bounds__(BLOCK)
     } else {
       // ---- pass 1: BGK + Guo weighted by (1 - B_n), plus the bounce-back of
       // the non-equilibrium part, B_n (fneq_{-i} - fneq_i); one opposite pair
-      // at a time (Eqs. 2-4, 10, 12), regrouped as in the folded collision
-      // above with the Guo term in place of the particles' ----
-      const C gk = omB * kguo;
-      const C cg = (C)1 - relax - Bn;
-      const C rb3 = (relax + (C)2 * Bn) * (C)3 * rho;
-      g[0] = ((C)1 - relax) * g[0] +
-             wmul<Q>(0, relax * (drho - rho * (C)1.5 * uu) - gk * (C)3 * uF);
+      // at a time (Eqs. 2-4, 10, 12), the relaxation and the bounce-back
+      // applied as in the folded collision above ----
+      const C rB = relax + Bn;
+      {
+        const C wi = (C)L::w(0);
+        const C fneq = g[0] - wmul<Q>(0, drho - rho * (C)1.5 * uu);
+        g[0] = g[0] - relax * fneq - omB * kguo * wi * (C)3 * uF;
+      }
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
         const int o = L::opp(i);
         if (o < i) continue;
+        const C wi = (C)L::w(i);
         const C eu = edot(L::ex(i), L::ey(i), L::ez(i), ux, uy, uz);
         const C eF = edot(L::ex(i), L::ey(i), L::ez(i), F0, F1, F2);
         const C sym = drho + rho * ((C)4.5 * eu * eu - (C)1.5 * uu);
+        const C fn_i = g[i] - wmul<Q>(i, sym + rho * (C)3 * eu);
+        const C fn_o = g[o] - wmul<Q>(i, sym - rho * (C)3 * eu);
         // Guo term (Eq. 4): even and odd parts under e -> -e
-        const C X = relax * sym + gk * ((C)9 * eu * eF - (C)3 * uF);
-        const C Y = rb3 * eu + gk * ((C)3 * eF);
-        const C gi = g[i], go = g[o];
-        g[i] = cg * gi + Bn * go + wmul<Q>(i, X + Y);
-        g[o] = cg * go + Bn * gi + wmul<Q>(i, X - Y);
+        const C Fsym = kguo * wi * ((C)9 * eu * eF - (C)3 * uF);
+        const C Fant = kguo * wi * ((C)3 * eF);
+        g[i] = g[i] - rB * fn_i + Bn * fn_o + omB * (Fsym + Fant);
+        g[o] = g[o] - rB * fn_o + Bn * fn_i + omB * (Fsym - Fant);
       }
     }
   }
