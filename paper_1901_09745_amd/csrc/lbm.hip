@@ -92,6 +92,20 @@ __device__ __forceinline__ C eq5_velocity(C j, C h, C q, C inv_rho, C inv_rho0) 
   }
 }
 
+// The same without a body force: the sum j + F/2 is j itself, so the FP32
+// form is one fused multiply-add, u = (j - j q) / rho0.
+template <typename C>
+__device__ __forceinline__ C eq5_velocity_unforced(C j, C q, C inv_rho, C inv_rho0) {
+  if constexpr (std::is_same<C, double>::value) {
+    (void)q;
+    (void)inv_rho0;
+    return j * inv_rho;
+  } else {
+    (void)inv_rho;
+    return __builtin_fmaf(-j, q, j) * inv_rho0;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Storage conversion: deviation g_i = f_i - w_i rho0 in the compute type.
 // ---------------------------------------------------------------------------
@@ -514,9 +528,15 @@ __global__ void __launch_bounds__(BLOCK)
     const C inv_rho = (C)1 / rho;
     const C q_rho = drho * inv_rho;
     const C inv_rho0 = (C)(1.0 / rho0);
-    ux = eq5_velocity(jx, (C)0.5 * F0, q_rho, inv_rho, inv_rho0);
-    uy = eq5_velocity(jy, (C)0.5 * F1, q_rho, inv_rho, inv_rho0);
-    uz = eq5_velocity(jz, (C)0.5 * F2, q_rho, inv_rho, inv_rho0);
+    if (forced) {
+      ux = eq5_velocity(jx, (C)0.5 * F0, q_rho, inv_rho, inv_rho0);
+      uy = eq5_velocity(jy, (C)0.5 * F1, q_rho, inv_rho, inv_rho0);
+      uz = eq5_velocity(jz, (C)0.5 * F2, q_rho, inv_rho, inv_rho0);
+    } else {
+      ux = eq5_velocity_unforced(jx, q_rho, inv_rho, inv_rho0);
+      uy = eq5_velocity_unforced(jy, q_rho, inv_rho, inv_rho0);
+      uz = eq5_velocity_unforced(jz, q_rho, inv_rho, inv_rho0);
+    }
     uu = ux * ux + uy * uy + uz * uz;
     const C omega = (C)a.omega;
     const C kguo = (C)1 - (C)0.5 * omega;
