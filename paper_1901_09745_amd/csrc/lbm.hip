@@ -246,13 +246,16 @@ __device__ inline Cell cell_of(const Geom& g, long long n) {
 // Waves per SIMD of each form, the register budget of the tiles (which the
 // contact workgroups' code must fit as well), each as measured fastest: 2D
 // FP32 / FP16 8 (their slot fractions held in FP32, so that eight
-// workgroups' LDS fits a CU), 3D FP16 and walled 3D FP32 6, periodic 3D FP32
-// and 2D FP64 5, 3D FP64 4.
+// workgroups' LDS fits a CU), walled 3D FP32 / FP16 7, periodic 3D FP32 /
+// FP16 6 (the per-cell moments keep their registers lower), 2D FP64 5, 3D
+// FP64 4.  The reduced 3D forms are bound by instruction issue, and more
+// waves hide more of the loads' and the tile list's latency under it, up to
+// the point where spills cost more.
 template <int Q, int PREC, bool WALLS>
 constexpr int step_waves() {
   if (PREC == PSCLBM_FP64) return Q == 9 ? 5 : 4;
   if (Q == 9) return 8;
-  return (PREC == PSCLBM_FP32_FP16STORE || WALLS) ? 6 : 5;
+  return WALLS ? 7 : 6;
 }
 
 // NT (even steps only): the lattice is streamed with non-temporal loads and
