@@ -381,12 +381,18 @@ __global__ void __launch_bounds__(BLOCK)
     t.Bs = a.original ? (C)(s.eps[k] * tm / ((1.0 - s.eps[k]) + tm)) : (C)(s.eps[k] * bscale);
     t.Bm = a.original ? Bn_cell : t.Bs;
     const LdsEntry& P = lds[slot_e(k)];
-    const double rx = min_image((double)x - P.x, d.px, d.nx);
-    const double ry = min_image(row_coord(y) - P.y, d.py, d.ny);
-    const double rz = D == 3 ? min_image(row_coord(z) - P.z, d.pz, d.nz) : 0.0;
-    // u_s = U + Omega x r in the arithmetic precision (the arm from its
-    // FP64 nearest image)
-    const C cx = (C)rx, cy = (C)ry, cz = (C)rz;
+    // u_s = U + Omega x r in the arithmetic precision: the arm from its FP64
+    // nearest image, or in the FP32 forms from the centre's FP32 pair
+    C cx, cy, cz;
+    if constexpr (PREC == PSCLBM_FP64) {
+      cx = min_image((double)x - P.x, d.px, d.nx);
+      cy = min_image(row_coord(y) - P.y, d.py, d.ny);
+      cz = D == 3 ? min_image(row_coord(z) - P.z, d.pz, d.nz) : 0.0;
+    } else {
+      cx = min_image_f((float)x - P.xh[0], d.px, d.nx) - P.xl[0];
+      cy = min_image_f((float)y - P.xh[1], d.py, d.ny) - P.xl[1];
+      cz = D == 3 ? min_image_f((float)z - P.xh[2], d.pz, d.nz) - P.xl[2] : 0.0f;
+    }
     const C usx = (C)P.u[0] + (C)P.w[1] * cz - (C)P.w[2] * cy;
     const C usy = (C)P.u[1] + (C)P.w[2] * cx - (C)P.w[0] * cz;
     const C usz = D == 3 ? (C)P.u[2] + (C)P.w[0] * cy - (C)P.w[1] * cx : (C)0;

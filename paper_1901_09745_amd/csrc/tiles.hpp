@@ -21,6 +21,18 @@ __device__ __forceinline__ double min_image(double d, int periodic, int L) {
   return periodic ? d + t : d;
 }
 
+// The same in FP32 for c - xh, c an integer cell coordinate and xh the FP32
+// high part of a centre in [0, L): the difference and the shift by L are
+// exact (both are multiples of xh's last place and no larger than L), so the
+// arm c - x = min_image(c - xh) - xl rounds once.
+__device__ __forceinline__ float min_image_f(float d, int periodic, int L) {
+  const float Lf = (float)L;
+  const float hL = 0.5f * Lf;
+  float t = d > hL ? -Lf : 0.0f;
+  t = d < -hL ? Lf : t;
+  return periodic ? d + t : d;
+}
+
 // ---------------------------------------------------------------------------
 // Solid fraction of one (cell, particle) pair, the inside/outside rule of Table 1 with
 // Eq. 15/18: eps = V_a(r) + 1/2 - d inside the shell r +- h.
@@ -50,6 +62,9 @@ struct LdsEntry {
   double x, y, z;
   double r, cs;
   double u[3], w[3];
+  // the centre as an FP32 pair, x = xh + xl to FP64 accuracy: the FP32
+  // arithmetic forms take the arm of u_s = U + Omega x r from it
+  float xh[3], xl[3];
   int id;
   int pad;
 };
@@ -278,6 +293,11 @@ __device__ inline int load_tile_list(const int* tile_count, const int* tile_list
     L.x = P.x[0];
     L.y = P.x[1];
     L.z = P.x[2];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      L.xh[a] = (float)P.x[a];
+      L.xl[a] = (float)(P.x[a] - (double)L.xh[a]);
+    }
     L.r = P.r;
     L.cs = P.cs;
 #pragma unroll
