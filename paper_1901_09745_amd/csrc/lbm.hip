@@ -393,9 +393,20 @@ __global__ void __launch_bounds__(BLOCK)
       cy = min_image_f((float)y - P.xh[1], d.py, d.ny) - P.xl[1];
       cz = D == 3 ? min_image_f((float)z - P.xh[2], d.pz, d.nz) - P.xl[2] : 0.0f;
     }
-    const C usx = (C)P.u[0] + (C)P.w[1] * cz - (C)P.w[2] * cy;
-    const C usy = (C)P.u[1] + (C)P.w[2] * cx - (C)P.w[0] * cz;
-    const C usz = D == 3 ? (C)P.u[2] + (C)P.w[0] * cy - (C)P.w[1] * cx : (C)0;
+    C U[3], W[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if constexpr (PREC == PSCLBM_FP64) {
+        U[c] = P.u[c];
+        W[c] = P.w[c];
+      } else {
+        U[c] = P.uf[c];
+        W[c] = P.wf[c];
+      }
+    }
+    const C usx = U[0] + W[1] * cz - W[2] * cy;
+    const C usy = U[1] + W[2] * cx - W[0] * cz;
+    const C usz = D == 3 ? U[2] + W[0] * cy - W[1] * cx : (C)0;
     t.dv[0] = usx - ux;
     t.dv[1] = usy - uy;
     t.dv[2] = usz - uz;

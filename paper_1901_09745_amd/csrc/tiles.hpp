@@ -62,9 +62,11 @@ struct LdsEntry {
   double x, y, z;
   double r, cs;
   double u[3], w[3];
-  // the centre as an FP32 pair, x = xh + xl to FP64 accuracy: the FP32
-  // arithmetic forms take the arm of u_s = U + Omega x r from it
+  // the centre as an FP32 pair, x = xh + xl to FP64 accuracy, and U and
+  // Omega rounded to FP32: the FP32 arithmetic forms take u_s = U + Omega x r
+  // from these
   float xh[3], xl[3];
+  float uf[3], wf[3];
   int id;
   int pad;
 };
@@ -84,7 +86,7 @@ using Slots = SlotsT<double>;
 template <typename E>
 struct SlotLdsT {
   int n[BLOCK];
-  int e[KSLOTS][BLOCK];
+  unsigned short e[KSLOTS][BLOCK];  // list entries (the list holds at most 512)
   E eps[KSLOTS][BLOCK];
 };
 using SlotLds = SlotLdsT<double>;
@@ -219,7 +221,7 @@ __device__ inline void collect_slots(const Geom& g, int x0, int y, int z, bool a
         const int c = wbase + cl;
         const int k = atomicAdd(&sl.n[c], 1);
         if (k < KSLOTS) {
-          sl.e[k][c] = e;
+          sl.e[k][c] = (unsigned short)e;
           sl.eps[k][c] = (E)eps;
         } else if (err) {
           atomicOr(err, ERR_SLOTS);
@@ -297,6 +299,8 @@ __device__ inline int load_tile_list(const int* tile_count, const int* tile_list
     for (int a = 0; a < 3; ++a) {
       L.xh[a] = (float)P.x[a];
       L.xl[a] = (float)(P.x[a] - (double)L.xh[a]);
+      L.uf[a] = (float)P.u[a];
+      L.wf[a] = (float)P.w[a];
     }
     L.r = P.r;
     L.cs = P.cs;
