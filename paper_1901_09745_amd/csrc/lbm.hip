@@ -315,6 +315,19 @@ __global__ void __launch_bounds__(BLOCK)
   const unsigned N = (unsigned)a.g.N;
   const double rho0 = a.g.rho0;
   double mass_dev = 0.0;
+  // the wave's cells and all their neighbours inside the lattice (no face
+  // within one cell of the segment): every link is the plain offset, with no
+  // wrap and no wall (uniform over the wave).  Taken by the odd steps of the
+  // FP32 form and of the walled FP16 one, whose pulled loads and pushed
+  // stores otherwise resolve 2 x 18 links (the walled 384x192x192 odd step
+  // 503 -> 449 us in FP32, 496 -> 436 us in FP16); in the other forms the
+  // second copy of the loops measured neutral to 2 % slower.
+  constexpr bool INNER_PATH =
+      PAR == 1 && (PREC == PSCLBM_FP32 || (PREC == PSCLBM_FP32_FP16STORE && WALLS));
+  const bool inner = INNER_PATH &&
+                     __builtin_amdgcn_readfirstlane(
+                         (int)(x0 >= 1 && x0 + SEG <= d.nx - 1 && y >= 1 && y <= d.ny - 2 &&
+                               (D == 2 || (z >= 1 && z <= d.nz - 2)))) != 0;
 
   // ---- solid fractions of the covering particles (Table 1), whole wave; in
   // 3D after the loads of f are issued, so that their latency overlaps the
@@ -333,18 +346,29 @@ __global__ void __launch_bounds__(BLOCK)
   E bscale = 1;  // B_s / eps_{n,s} of the cell (Eq. 13), formed with the weights
   if (active) {
     // ---- load f as deviations g_i = f_i - w_i rho0 ----
+    bool loaded = false;
+    if constexpr (INNER_PATH) {
+      if (inner) {  // plain offsets
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      if constexpr (PAR == 2) {
-        g[i] = ST::ld(const_cast<S*>(static_cast<const S*>(a.src)) + (size_t)i * N, n, i, rho0);
-      } else if constexpr (PAR == 0) {
-        g[i] = ST::template ld<NT>(A + (size_t)i * N, n, i, rho0);
-      } else {
-        unsigned m = n;
-        if (!link<WALLS>(d, x, y, z, -L::ex(i), -L::ey(i), -L::ez(i), n, m))
-          g[i] = ST::ld(A + (size_t)L::opp(i) * N, m, i, rho0);
-        else  // reflected at a wall during the previous (even) step
-          g[i] = ST::ld(A + (size_t)i * N, n, i, rho0);
+        for (int i = 0; i < Q; ++i)
+          g[i] = ST::ld(A + (size_t)L::opp(i) * N, n - link_offset<L>(d, i), i, rho0);
+        loaded = true;
+      }
+    }
+    if (!loaded) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        if constexpr (PAR == 2) {
+          g[i] = ST::ld(const_cast<S*>(static_cast<const S*>(a.src)) + (size_t)i * N, n, i, rho0);
+        } else if constexpr (PAR == 0) {
+          g[i] = ST::template ld<NT>(A + (size_t)i * N, n, i, rho0);
+        } else {
+          unsigned m = n;
+          if (!link<WALLS>(d, x, y, z, -L::ex(i), -L::ey(i), -L::ez(i), n, m))
+            g[i] = ST::ld(A + (size_t)L::opp(i) * N, m, i, rho0);
+          else  // reflected at a wall during the previous (even) step
+            g[i] = ST::ld(A + (size_t)i * N, n, i, rho0);
+        }
       }
     }
   }
@@ -783,6 +807,16 @@ __global__ void __launch_bounds__(BLOCK)
     asm volatile("" : "+v"(xo));
     const unsigned no = xo + d.sy * (unsigned)y + d.sz * (unsigned)z;
     double cell_dev = 0.0;  // FP64 sum of the stored deviations, in every form
+    bool stored = false;
+    if constexpr (INNER_PATH) {
+      if (inner) {  // plain offsets: every population to its neighbour
+#pragma unroll
+        for (int i = 0; i < Q; ++i)
+          cell_dev += ST::st(A + (size_t)i * N, no + link_offset<L>(d, i), i, g[i], rho0);
+        stored = true;
+      }
+    }
+    if (!stored) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       unsigned m = no;
@@ -810,6 +844,7 @@ __global__ void __launch_bounds__(BLOCK)
         cell_dev += ST::st(A + (size_t)L::opp(i) * N, no, i, v, rho0);
       else                  // neighbour cell, same slot
         cell_dev += ST::st(A + (size_t)i * N, m, i, v, rho0);
+    }
     }
     mass_dev = cell_dev;
   }

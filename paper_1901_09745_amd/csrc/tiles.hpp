@@ -369,6 +369,12 @@ __device__ __forceinline__ Dims dims_of(const Geom& g) {
 // offset m (periodic wrap applied) and returns the mask of non-periodic faces
 // the link leaves through (bit f for face f; 0 when the neighbour exists).
 // WALLS == false: every axis is periodic and no link ever leaves.
+// Offset of the neighbour e_i of a cell far from every face (no wrap, no wall).
+template <typename L>
+__device__ __forceinline__ unsigned link_offset(const Dims& d, int i) {
+  return (unsigned)(L::ex(i) + L::ey(i) * (int)d.sy + L::ez(i) * (int)d.sz);
+}
+
 template <bool WALLS>
 __device__ __forceinline__ unsigned link(const Dims& d, int x, int y, int z, int dx, int dy,
                                          int dz, unsigned n, unsigned& m) {
