@@ -820,8 +820,12 @@ __global__ void __launch_bounds__(BLOCK)
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       unsigned m = no;
+      // the even step stores into the own cell: its links matter only for a
+      // moving wall's term
       const unsigned out =
-          i == 0 ? 0u : link<WALLS>(d, x, y, z, L::ex(i), L::ey(i), L::ez(i), no, m);
+          (i == 0 || (PAR == 0 && !a.moving_mask))
+              ? 0u
+              : link<WALLS>(d, x, y, z, L::ex(i), L::ey(i), L::ez(i), no, m);
       C v = g[i];
       if (out) {
         const unsigned mw = out & a.moving_mask;
