@@ -160,6 +160,9 @@ struct StepArgs {
   long long face_stride;   // cells per face slot in outlet_u
   unsigned* err;
   double omega;            // 1 / tau
+  double inv_rho0;         // 1 / rho0
+  // the same uniform values rounded to FP32 for the FP32 arithmetic forms
+  float force_f[3], omega_f, inv_rho0_f, rho0_f, tm_f;  // tm = tau - 1/2
   unsigned inlet_mask;     // faces of kind INLET_EQ (bit f)
   unsigned outlet_mask;    // faces of kind OUTLET_EQ
   unsigned open_mask;      // inlet | outlet

@@ -106,14 +106,37 @@ __device__ __forceinline__ C eq5_velocity_unforced(C j, C q, C inv_rho, C inv_rh
   }
 }
 
+// 1/rho for Eq. 5: exact in FP64. The FP32 forms use it only for q = drho /
+// rho, the small correction in both velocities above, where the hardware
+// reciprocal's last bit stays below the velocity's own rounding.
+template <typename C>
+__device__ __forceinline__ C inv_density(C rho) {
+  if constexpr (std::is_same<C, double>::value) return 1.0 / rho;
+  else return __builtin_amdgcn_rcpf(rho);
+}
+
 // ---------------------------------------------------------------------------
 // Storage conversion: deviation g_i = f_i - w_i rho0 in the compute type.
 // ---------------------------------------------------------------------------
-// Element `e` of a per-direction array through a 32-bit byte offset, so the
-// address is a uniform 64-bit base (SGPRs) plus one 32-bit VGPR offset.
+// Direction i's array of a state with N cells, as a base the compiler holds
+// in scalar registers and cannot re-derive from the others. Where all Q
+// accesses of a cell share one offset (the even step's own-cell accesses) it
+// otherwise forms each 64-bit address with a vector add from the previous one.
 template <typename S>
-__device__ __forceinline__ S& elem(S* base, unsigned e) {
-  return *reinterpret_cast<S*>(reinterpret_cast<char*>(base) + (e * (unsigned)sizeof(S)));
+__device__ __forceinline__ S* dir_ptr(S* A, int i, unsigned N) {
+  S* p = A + (size_t)i * N;
+  asm("" : "+s"(p));
+  return p;
+}
+// Element `e` of a per-direction array through a 32-bit byte offset, in the
+// global address space, so the access is the scalar base plus one 32-bit
+// vector offset.
+template <typename S>
+using GlobalT = __attribute__((address_space(1))) S;
+template <typename S>
+__device__ __forceinline__ GlobalT<S>& elem(S* base, unsigned e) {
+  auto* gb = (__attribute__((address_space(1))) char*)base;
+  return *(GlobalT<S>*)(gb + (e * (unsigned)sizeof(S)));
 }
 // The same element read or written with a non-temporal hint when NT: the
 // line is streamed through the caches rather than kept in them.
@@ -341,7 +364,15 @@ __global__ void __launch_bounds__(BLOCK)
   C g[Q];
   C rho = (C)1, ux = 0, uy = 0, uz = 0, uu = 0;
   C Bn_cell = 0;
-  const C F0 = (C)a.force[0], F1 = (C)a.force[1], F2 = (C)a.force[2];
+  // uniform parameters in the compute type (the FP32 copies are rounded on
+  // the host, to the values a conversion here would give)
+  auto uni = [](double v, float vf) -> C {
+    if constexpr (std::is_same<C, double>::value) { (void)vf; return v; }
+    else { (void)v; return vf; }
+  };
+  const C F0 = uni(a.force[0], a.force_f[0]), F1 = uni(a.force[1], a.force_f[1]),
+          F2 = uni(a.force[2], a.force_f[2]);
+  const C rho0c = uni(a.g.rho0, a.rho0_f), inv_rho0 = uni(a.inv_rho0, a.inv_rho0_f);
   const double tm = a.tau - 0.5;
   E bscale = 1;  // B_s / eps_{n,s} of the cell (Eq. 13), formed with the weights
   if (active) {
@@ -359,9 +390,9 @@ __global__ void __launch_bounds__(BLOCK)
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         if constexpr (PAR == 2) {
-          g[i] = ST::ld(const_cast<S*>(static_cast<const S*>(a.src)) + (size_t)i * N, n, i, rho0);
+          g[i] = ST::ld(dir_ptr(const_cast<S*>(static_cast<const S*>(a.src)), i, N), n, i, rho0);
         } else if constexpr (PAR == 0) {
-          g[i] = ST::template ld<NT>(A + (size_t)i * N, n, i, rho0);
+          g[i] = ST::template ld<NT>(dir_ptr(A, i, N), n, i, rho0);
         } else {
           unsigned m = n;
           if (!link<WALLS>(d, x, y, z, -L::ex(i), -L::ey(i), -L::ez(i), n, m))
@@ -507,8 +538,8 @@ __global__ void __launch_bounds__(BLOCK)
         j0 = __shfl(j0, src);
         j1 = __shfl(j1, src);
         j2 = __shfl(j2, src);
-        const C ir = (C)1 / ((C)rho0 + r_);
-        const C qr = r_ * ir, ir0 = (C)(1.0 / rho0);
+        const C ir = inv_density(rho0c + r_);
+        const C qr = r_ * ir, ir0 = inv_rho0;
         wu0 = (double)eq5_velocity(j0, (C)0.5 * F0, qr, ir, ir0);
         wu1 = (double)eq5_velocity(j1, (C)0.5 * F1, qr, ir, ir0);
         wu2 = (double)eq5_velocity(j2, (C)0.5 * F2, qr, ir, ir0);
@@ -568,10 +599,9 @@ __global__ void __launch_bounds__(BLOCK)
       if (L::ez(i) > 0) jz += g[i];
       if (L::ez(i) < 0) jz -= g[i];
     }
-    rho = (C)rho0 + drho;
-    const C inv_rho = (C)1 / rho;
+    rho = rho0c + drho;
+    const C inv_rho = inv_density(rho);
     const C q_rho = drho * inv_rho;
-    const C inv_rho0 = (C)(1.0 / rho0);
     if (forced) {
       ux = eq5_velocity(jx, (C)0.5 * F0, q_rho, inv_rho, inv_rho0);
       uy = eq5_velocity(jy, (C)0.5 * F1, q_rho, inv_rho, inv_rho0);
@@ -582,7 +612,7 @@ __global__ void __launch_bounds__(BLOCK)
       uz = eq5_velocity_unforced(jz, q_rho, inv_rho, inv_rho0);
     }
     uu = ux * ux + uy * uy + uz * uz;
-    const C omega = (C)a.omega;
+    const C omega = uni(a.omega, a.omega_f);
     const C kguo = (C)1 - (C)0.5 * omega;
     const C uF = ux * F0 + uy * F1 + uz * F2;
 
@@ -601,7 +631,7 @@ __global__ void __launch_bounds__(BLOCK)
 #pragma unroll
     for (int k = 0; k < KSLOTS; ++k)
       if (k < s.n) S_ += s.eps[k];
-    const E tme = (E)tm;
+    const E tme = uni(tm, a.tm_f);  // E is the compute type
     const E en = S_ < (E)1 ? S_ : (E)1;
     const E den = ((E)1 - en) + tme;
     E inv_den = 1;
@@ -843,7 +873,7 @@ __global__ void __launch_bounds__(BLOCK)
         }
       }
       if (PAR == 0)  // own cell, opposite slot
-        cell_dev += ST::template st<NT>(A + (size_t)L::opp(i) * N, no, i, v, rho0);
+        cell_dev += ST::template st<NT>(dir_ptr(A, L::opp(i), N), no, i, v, rho0);
       else if (out)  // reflected into the own cell's opposite slot
         cell_dev += ST::st(A + (size_t)L::opp(i) * N, no, i, v, rho0);
       else                  // neighbour cell, same slot
@@ -1255,6 +1285,12 @@ static StepArgs step_args(psclbm_ctx* c) {
   a.face_stride = c->face_stride;
   a.err = c->err;
   a.omega = 1.0 / c->cfg.tau;
+  a.inv_rho0 = 1.0 / c->geom.rho0;
+  for (int k = 0; k < 3; ++k) a.force_f[k] = (float)a.force[k];
+  a.omega_f = (float)a.omega;
+  a.inv_rho0_f = (float)a.inv_rho0;
+  a.rho0_f = (float)c->geom.rho0;
+  a.tm_f = (float)(a.tau - 0.5);
   a.inlet_mask = a.outlet_mask = a.moving_mask = 0;
   for (int f = 0; f < 6; ++f) {
     if (c->geom.face[f] == PSCLBM_INLET_EQ) a.inlet_mask |= 1u << f;
