@@ -69,6 +69,58 @@ __device__ __forceinline__ C wmul(int i, C x) {
   }
 }
 
+// The FP16 storage form keeps a cell's populations in registers as it stores
+// them, h_i = g_i / w_i: the collision then takes no weight per direction,
+// and the weights enter the moments once per weight class.
+template <int PREC>
+constexpr bool scaled_form() {
+  return PREC == PSCLBM_FP32_FP16STORE;
+}
+// w_i x, or x itself in the scaled form
+template <int Q, bool SC, typename C>
+__device__ __forceinline__ C wq(int i, C x) {
+  if constexpr (SC) return x;
+  else return wmul<Q>(i, x);
+}
+// The density deviation sum_i g_i and the momentum sum_i e_i g_i of a cell;
+// in the scaled form as sum_c w_c (sums over the rest, axis and diagonal
+// classes of h_i).
+template <int Q, bool SC, typename C>
+__device__ __forceinline__ void cell_moments(const C (&g)[Q], C& r, C& jx, C& jy, C& jz) {
+  using L = Lattice<Q>;
+  if constexpr (!SC) {
+    r = jx = jy = jz = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      r += g[i];
+      if (L::ex(i) > 0) jx += g[i];
+      if (L::ex(i) < 0) jx -= g[i];
+      if (L::ey(i) > 0) jy += g[i];
+      if (L::ey(i) < 0) jy -= g[i];
+      if (L::ez(i) > 0) jz += g[i];
+      if (L::ez(i) < 0) jz -= g[i];
+    }
+  } else {
+    C R[3] = {0, 0, 0}, X[3] = {0, 0, 0}, Y[3] = {0, 0, 0}, Z[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int c = L::ex(i) * L::ex(i) + L::ey(i) * L::ey(i) + L::ez(i) * L::ez(i);
+      R[c] += g[i];
+      if (L::ex(i) > 0) X[c] += g[i];
+      if (L::ex(i) < 0) X[c] -= g[i];
+      if (L::ey(i) > 0) Y[c] += g[i];
+      if (L::ey(i) < 0) Y[c] -= g[i];
+      if (L::ez(i) > 0) Z[c] += g[i];
+      if (L::ez(i) < 0) Z[c] -= g[i];
+    }
+    constexpr int axis = 1, diag = Q == 9 ? 5 : 7;  // a direction of each class
+    r = wmul<Q>(0, R[0]) + (wmul<Q>(axis, R[1]) + wmul<Q>(diag, R[2]));
+    jx = wmul<Q>(axis, X[1]) + wmul<Q>(diag, X[2]);
+    jy = wmul<Q>(axis, Y[1]) + wmul<Q>(diag, Y[2]);
+    jz = wmul<Q>(axis, Z[1]) + wmul<Q>(diag, Z[2]);
+  }
+}
+
 // Velocity of Eq. 5, u = (j + F/2) / rho, in the compute type, from the
 // momentum component j, the half force h and q = drho / rho.  In FP32 the half
 // force (of order 1e-7 against a momentum of order 1e-3 in a slowly developing
@@ -116,7 +168,8 @@ __device__ __forceinline__ C inv_density(C rho) {
 }
 
 // ---------------------------------------------------------------------------
-// Storage conversion: deviation g_i = f_i - w_i rho0 in the compute type.
+// Storage conversion: deviation g_i = f_i - w_i rho0 in the compute type (in
+// the FP16 form g_i / w_i, as stored).
 // ---------------------------------------------------------------------------
 // Direction i's array of a state with N cells, as a base the compiler holds
 // in scalar registers and cannot re-derive from the others. Where all Q
@@ -155,7 +208,8 @@ template <int PREC, int Q>
 struct Store {
   using S = typename Form<PREC>::S;
   using C = typename Form<PREC>::C;
-  // direction-i array `b` (= A + i N), element e
+  // direction-i array `b` (= A + i N), element e: the deviation g_i in the
+  // compute type, or g_i / w_i as stored in the scaled (FP16) form
   template <bool NT = false>
   __device__ static C ld(S* b, unsigned e, int i, double rho0) {
     const S v = elem_ld<NT>(b, e);
@@ -164,11 +218,13 @@ struct Store {
     } else if constexpr (PREC == PSCLBM_FP32) {
       return v;
     } else {
-      return wmul<Q>(i, static_cast<float>(v));
+      (void)i;
+      return static_cast<float>(v);
     }
   }
-  // stores deviation g of direction i; returns the deviation memory now holds,
-  // exactly, in FP64 (the per-cell part of the mass sum)
+  // stores deviation g of direction i (g / w_i in the scaled form); returns
+  // the deviation memory now holds in FP64 (exactly, and in the FP16 form to
+  // the rounding of h w_i: the per-cell part of the mass sum)
   template <bool NT = false>
   __device__ static double st(S* b, unsigned e, int i, C g, double rho0) {
     if constexpr (PREC == PSCLBM_FP64) {
@@ -179,7 +235,7 @@ struct Store {
       elem_st<NT>(b, e, g);
       return static_cast<double>(g);
     } else {
-      const _Float16 h = static_cast<_Float16>(g * static_cast<float>(1.0 / Lattice<Q>::w(i)));
+      const _Float16 h = static_cast<_Float16>(g);
       elem_st<NT>(b, e, h);
       return static_cast<double>(static_cast<float>(h)) * Lattice<Q>::w(i);
     }
@@ -295,6 +351,7 @@ __global__ void __launch_bounds__(BLOCK)
   constexpr int D = L::D;
   // slot fractions held in FP32 by the FP32 arithmetic forms
   using E = typename std::conditional<PREC == PSCLBM_FP64, double, float>::type;
+  constexpr bool SC = scaled_form<PREC>();
   extern __shared__ double smem_d[];
   __shared__ SlotLdsT<E> slot_lds;
   if ((int)blockIdx.x < a.dem_blocks) {
@@ -522,14 +579,8 @@ __global__ void __launch_bounds__(BLOCK)
       // level, from the neighbour's lane of this wave
       double wu0 = 0.0, wu1 = 0.0, wu2 = 0.0;
       if (a.outlet_wave) {
-        C r_ = 0, j0 = 0, j1 = 0, j2 = 0;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          r_ += g[i];
-          eacc(L::ex(i), j0, g[i]);
-          eacc(L::ey(i), j1, g[i]);
-          eacc(L::ez(i), j2, g[i]);
-        }
+        C r_, j0, j1, j2;
+        cell_moments<Q, SC>(g, r_, j0, j1, j2);
         const int lane = (int)(threadIdx.x & 63);
         int src = lane;
         if ((a.outlet_wave & 1u) && x == 0) src = lane + 1;
@@ -582,23 +633,14 @@ __global__ void __launch_bounds__(BLOCK)
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
           const C eu = edot(L::ex(i), L::ey(i), L::ez(i), u0, u1, u2);
-          g[i] = wmul<Q>(i, (C)rho0 * ((C)3 * eu + (C)4.5 * eu * eu - (C)1.5 * uq));
+          g[i] = wq<Q, SC>(i, (C)rho0 * ((C)3 * eu + (C)4.5 * eu * eu - (C)1.5 * uq));
         }
       }
     }
 
     // ---- moments with the half-force shift (Eq. 5) ----
-    C drho = 0, jx = 0, jy = 0, jz = 0;
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      drho += g[i];
-      if (L::ex(i) > 0) jx += g[i];
-      if (L::ex(i) < 0) jx -= g[i];
-      if (L::ey(i) > 0) jy += g[i];
-      if (L::ey(i) < 0) jy -= g[i];
-      if (L::ez(i) > 0) jz += g[i];
-      if (L::ez(i) < 0) jz -= g[i];
-    }
+    C drho, jx, jy, jz;
+    cell_moments<Q, SC>(g, drho, jx, jy, jz);
     rho = rho0c + drho;
     const C inv_rho = inv_density(rho);
     const C q_rho = drho * inv_rho;
@@ -704,8 +746,8 @@ __global__ void __launch_bounds__(BLOCK)
         {
           C x0 = p0;
           if constexpr (GUO) x0 -= gk * (C)3 * uF;
-          const C fneq = g[0] - wmul<Q>(0, drho - rho * (C)1.5 * uu);
-          g[0] = g[0] - relax * fneq + wmul<Q>(0, x0);
+          const C fneq = g[0] - wq<Q, SC>(0, drho - rho * (C)1.5 * uu);
+          g[0] = g[0] - relax * fneq + wq<Q, SC>(0, x0);
         }
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
@@ -714,8 +756,8 @@ __global__ void __launch_bounds__(BLOCK)
           const int ex = L::ex(i), ey = L::ey(i), ez = L::ez(i);
           const C eu = edot(ex, ey, ez, ux, uy, uz);
           const C sym = drho + rho * ((C)4.5 * eu * eu - (C)1.5 * uu);
-          const C fn_i = g[i] - wmul<Q>(i, sym + rho * (C)3 * eu);
-          const C fn_o = g[o] - wmul<Q>(i, sym - rho * (C)3 * eu);
+          const C fn_i = g[i] - wq<Q, SC>(i, sym + rho * (C)3 * eu);
+          const C fn_o = g[o] - wq<Q, SC>(i, sym - rho * (C)3 * eu);
           // the even and odd parts under e -> -e of the particles' term and
           // of the Guo term (Eq. 4)
           C ps = p0;
@@ -731,8 +773,8 @@ __global__ void __launch_bounds__(BLOCK)
             ps += gk * ((C)9 * eu * eF - (C)3 * uF);
             pa += gk * ((C)3 * eF);
           }
-          g[i] = g[i] - rB * fn_i + Bn * fn_o + wmul<Q>(i, ps + pa);
-          g[o] = g[o] - rB * fn_o + Bn * fn_i + wmul<Q>(i, ps - pa);
+          g[i] = g[i] - rB * fn_i + Bn * fn_o + wq<Q, SC>(i, ps + pa);
+          g[o] = g[o] - rB * fn_o + Bn * fn_i + wq<Q, SC>(i, ps - pa);
         }
       };
       if (forced)
@@ -746,20 +788,20 @@ __global__ void __launch_bounds__(BLOCK)
       // applied as in the folded collision above ----
       const C rB = relax + Bn;
       {
-        const C wi = (C)L::w(0);
-        const C fneq = g[0] - wmul<Q>(0, drho - rho * (C)1.5 * uu);
+        const C wi = SC ? (C)1 : (C)L::w(0);
+        const C fneq = g[0] - wq<Q, SC>(0, drho - rho * (C)1.5 * uu);
         g[0] = g[0] - relax * fneq - omB * kguo * wi * (C)3 * uF;
       }
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
         const int o = L::opp(i);
         if (o < i) continue;
-        const C wi = (C)L::w(i);
+        const C wi = SC ? (C)1 : (C)L::w(i);
         const C eu = edot(L::ex(i), L::ey(i), L::ez(i), ux, uy, uz);
         const C eF = edot(L::ex(i), L::ey(i), L::ez(i), F0, F1, F2);
         const C sym = drho + rho * ((C)4.5 * eu * eu - (C)1.5 * uu);
-        const C fn_i = g[i] - wmul<Q>(i, sym + rho * (C)3 * eu);
-        const C fn_o = g[o] - wmul<Q>(i, sym - rho * (C)3 * eu);
+        const C fn_i = g[i] - wq<Q, SC>(i, sym + rho * (C)3 * eu);
+        const C fn_o = g[o] - wq<Q, SC>(i, sym - rho * (C)3 * eu);
         // Guo term (Eq. 4): even and odd parts under e -> -e
         const C Fsym = kguo * wi * ((C)9 * eu * eF - (C)3 * uF);
         const C Fant = kguo * wi * ((C)3 * eF);
@@ -778,7 +820,7 @@ __global__ void __launch_bounds__(BLOCK)
       const SlotKin t = slot_kin(k);
       const C du2 = t.dv[0] * t.sv[0] + t.dv[1] * t.sv[1] + t.dv[2] * t.sv[2];  // |u_s|^2 - |u|^2
       const C rB = rho * t.Bs;
-      g[0] -= wmul<Q>(0, rB * (C)1.5 * du2);
+      g[0] -= wq<Q, SC>(0, rB * (C)1.5 * du2);
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
         const int o = L::opp(i);
@@ -788,8 +830,8 @@ __global__ void __launch_bounds__(BLOCK)
         // 4.5 [(e.u_s)^2 - (e.u)^2] - 1.5 (|u_s|^2 - |u|^2), and 3 e.(u_s - u)
         const C ds_s = (C)4.5 * de * se - (C)1.5 * du2;
         const C ds_a = (C)3 * de;
-        g[i] += wmul<Q>(i, rB * (ds_s + ds_a));
-        g[o] += wmul<Q>(i, rB * (ds_s - ds_a));
+        g[i] += wq<Q, SC>(i, rB * (ds_s + ds_a));
+        g[o] += wq<Q, SC>(i, rB * (ds_s - ds_a));
       }
       if (a.facc) exchange(t, mv);
     };
@@ -869,7 +911,7 @@ __global__ void __launch_bounds__(BLOCK)
               uw2 += a.g.face_u[f][2];
             }
           const double eu = edot(L::ex(i), L::ey(i), L::ez(i), uw0, uw1, uw2);
-          v -= (C)(6.0 * L::w(i) * eu) * rho;
+          v -= (C)(6.0 * (SC ? 1.0 : L::w(i)) * eu) * rho;
         }
       }
       if (PAR == 0)  // own cell, opposite slot
